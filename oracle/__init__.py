@@ -1,0 +1,220 @@
+"""Oracle: plain CPU implementations that the GPU path is checked against.
+
+TEST INFRASTRUCTURE ONLY.  Only ``tests/``, ``__graft_entry__.smoke()`` and
+the ``cpu_baseline`` leg of ``bench.py`` may import this package.  It shares
+no code with the GPU library (``paper_2311_02206_amd``) and never imports it.
+
+Contents:
+  * ``evaluate``: a single-threaded std::set semi-naive evaluator of positive
+    Datalog (Section 2, semi-naive evaluation; Section 5.1, the fixpoint
+    workflow), with a naive mode as a second algorithm;
+  * ``reach_bfs_histogram`` / ``reach_from``: per-source breadth-first search
+    for transitive closure, an independent checker of Reach (Section 1);
+  * ``sg_tree_closed_form``: the same-generation relation of a rooted tree in
+    closed form, an independent checker of SG (Section 2).
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SO = os.path.join(_HERE, "_build", "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the C++ oracle with g++ into ``oracle/_build/liboracle.so``."""
+    os.makedirs(os.path.dirname(_SO), exist_ok=True)
+    if force or not os.path.exists(_SO):
+        tmp = _SO + ".tmp"
+        subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread",
+                        os.path.join(_HERE, "semi_naive.cpp"), "-o", tmp], check=True)
+        os.replace(tmp, _SO)
+    return _SO
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        src = os.path.join(_HERE, "semi_naive.cpp")
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+            build()
+        L = ctypes.CDLL(_SO)
+        vp, cp, u64, u32 = ctypes.c_void_p, ctypes.c_char_p, ctypes.c_uint64, ctypes.c_uint32
+        L.or_create.restype = vp
+        L.or_destroy.argtypes = [vp]
+        L.or_error.restype = cp
+        L.or_error.argtypes = [vp]
+        L.or_declare.argtypes = [vp, cp, ctypes.c_int, ctypes.c_int]
+        L.or_load.argtypes = [vp, cp, vp, u64]
+        L.or_program.argtypes = [vp, cp]
+        L.or_run.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.or_iterations.argtypes = [vp]
+        L.or_seconds.argtypes = [vp]
+        L.or_seconds.restype = ctypes.c_double
+        L.or_count.argtypes = [vp, cp]
+        L.or_count.restype = ctypes.c_int64
+        L.or_fetch.argtypes = [vp, cp, vp, u64]
+        L.or_delta_counts.argtypes = [vp, cp, vp, ctypes.c_int]
+        L.or_new_counts.argtypes = [vp, cp, vp, ctypes.c_int]
+        L.or_history.argtypes = [vp, cp, ctypes.c_int, ctypes.c_int, vp, u64]
+        L.or_history.restype = ctypes.c_int64
+        L.or_reach_bfs.argtypes = [u32, vp, u64, vp, ctypes.c_int, ctypes.c_int]
+        L.or_reach_bfs.restype = ctypes.c_int64
+        L.or_reach_from.argtypes = [u32, vp, u64, u32, vp, u64]
+        L.or_reach_from.restype = ctypes.c_int64
+        _lib = L
+    return _lib
+
+
+@dataclass
+class Result:
+    relations: dict = field(default_factory=dict)   # name -> (n, arity) uint32, sorted
+    deltas: dict = field(default_factory=dict)      # name -> per-iteration |delta|
+    news: dict = field(default_factory=dict)        # name -> per-iteration |distinct new|
+    delta_history: dict = field(default_factory=dict)  # name -> [array per iteration]
+    new_history: dict = field(default_factory=dict)
+    iterations: int = 0
+    seconds: float = 0.0
+
+
+def evaluate(program: str, edb: dict, idb: dict, mode: str = "semi_naive",
+             plant: int = 0, max_iterations: int = 0, history: bool = False) -> Result:
+    """Evaluate ``program`` to its fixpoint.
+
+    ``edb`` maps a relation name to a row-major uint32 array ``(n, arity)``;
+    ``idb`` maps a relation name to its arity.  Returns every IDB relation
+    sorted lexicographically in declared column order, deduplicated, and the
+    per-iteration delta sizes (iteration 0 evaluates the EDB-only rules; the
+    last iteration is the empty one).  ``plant`` is a test hook that plants a
+    known mistake (see ``or_run`` in semi_naive.cpp); 0 means none.
+    ``history`` keeps every iteration's delta and new sets (small inputs).
+    """
+    L = lib()
+    h = L.or_create()
+    try:
+        def check(rc):
+            if rc < 0:
+                raise RuntimeError("oracle: " + L.or_error(h).decode())
+        for name, rows in edb.items():
+            rows = np.ascontiguousarray(rows, dtype=np.uint32)
+            arity = rows.shape[1] if rows.ndim == 2 else 1
+            check(L.or_declare(h, name.encode(), arity, 1))
+            check(L.or_load(h, name.encode(), rows.ctypes.data, rows.shape[0]))
+        for name, arity in idb.items():
+            check(L.or_declare(h, name.encode(), arity, 0))
+        check(L.or_program(h, program.encode()))
+        check(L.or_run(h, 0 if mode == "semi_naive" else 1, plant, max_iterations,
+                       1 if history else 0))
+        res = Result(iterations=L.or_iterations(h), seconds=L.or_seconds(h))
+        for name, arity in idb.items():
+            n = L.or_count(h, name.encode())
+            out = np.empty((n, arity), dtype=np.uint32)
+            check(L.or_fetch(h, name.encode(), out.ctypes.data, n))
+            res.relations[name] = out
+            cnt = np.zeros(res.iterations + 1, dtype=np.uint64)
+            k = L.or_delta_counts(h, name.encode(), cnt.ctypes.data, len(cnt))
+            res.deltas[name] = [int(x) for x in cnt[:k]]
+            k = L.or_new_counts(h, name.encode(), cnt.ctypes.data, len(cnt))
+            res.news[name] = [int(x) for x in cnt[:k]]
+            if history:
+                for which, store in ((0, res.delta_history), (1, res.new_history)):
+                    per = []
+                    for it in range(res.iterations):
+                        buf = np.empty((int(cnt.max()) + 1, arity), dtype=np.uint32)
+                        m = L.or_history(h, name.encode(), which, it, buf.ctypes.data,
+                                         buf.shape[0])
+                        check(m)
+                        per.append(buf[:m].copy())
+                    store[name] = per
+        return res
+    finally:
+        L.or_destroy(h)
+
+
+def reach_bfs_histogram(n_nodes: int, edges: np.ndarray, threads: int | None = None,
+                        max_dist: int = 1 << 16):
+    """Per-source BFS over ``edges``.  Returns ``(total_pairs, hist)`` where
+    ``hist[d]`` counts the pairs whose shortest path has ``d`` edges."""
+    edges = np.ascontiguousarray(edges, dtype=np.uint32)
+    hist = np.zeros(max_dist, dtype=np.uint64)
+    threads = threads or max(1, os.cpu_count() or 1)
+    total = lib().or_reach_bfs(n_nodes, edges.ctypes.data, edges.shape[0], hist.ctypes.data,
+                               max_dist, threads)
+    if total < 0:
+        raise RuntimeError("reach_bfs: bad input or distance histogram too short")
+    last = int(np.nonzero(hist)[0].max()) if total else 0
+    return int(total), [int(x) for x in hist[:last + 1]]
+
+
+def reach_from(n_nodes: int, edges: np.ndarray, source: int) -> np.ndarray:
+    """Sorted targets reachable from ``source`` by one or more edges."""
+    edges = np.ascontiguousarray(edges, dtype=np.uint32)
+    out = np.empty(n_nodes, dtype=np.uint32)
+    n = lib().or_reach_from(n_nodes, edges.ctypes.data, edges.shape[0], source,
+                            out.ctypes.data, n_nodes)
+    if n < 0:
+        raise RuntimeError("reach_from: bad input")
+    return out[:n].copy()
+
+
+def reach_deltas_from_histogram(hist) -> list:
+    """Per-iteration Reach delta sizes implied by a shortest-distance
+    histogram: iteration i derives the pairs at distance exactly i+1, and the
+    final iteration is the empty one."""
+    return [int(x) for x in hist[1:]] + [0]
+
+
+def sg_tree_closed_form(edges: np.ndarray):
+    """Same generation on a rooted tree, in closed form.
+
+    With Edge = (parent, child) pairs of a rooted tree, SG(x, y) holds iff
+    x != y and x, y are at the same depth >= 1.  Rule 1 derives the sibling
+    pairs (lowest common ancestor one level up); a pair whose lowest common
+    ancestor is k+1 levels up is first derived in iteration k.  Returns
+    ``(total, deltas)`` with the trailing empty iteration included.
+    """
+    edges = np.asarray(edges, dtype=np.int64)
+    n = int(edges.max()) + 1 if len(edges) else 1
+    parent = np.full(n, -1, dtype=np.int64)
+    parent[edges[:, 1]] = edges[:, 0]
+    depth = np.zeros(n, dtype=np.int64)
+    # ids of a breadth-first tree are not assumed: iterate to a fixpoint
+    changed = True
+    while changed:
+        nd = np.where(parent >= 0, depth[np.maximum(parent, 0)] + 1, 0)
+        changed = bool((nd != depth).any())
+        depth = nd
+    maxd = int(depth.max())
+    # anc[j][v] = ancestor of v j levels up (or -1)
+    anc = [np.arange(n, dtype=np.int64)]
+    for _ in range(maxd):
+        prev = anc[-1]
+        anc.append(np.where(prev >= 0, parent[np.maximum(prev, 0)], -1))
+        anc[-1][prev < 0] = -1
+    deltas = [0] * (maxd + 1)
+    total = 0
+    for d in range(1, maxd + 1):
+        nodes = np.nonzero(depth == d)[0]
+        nd_ = len(nodes)
+        total += nd_ * (nd_ - 1)
+
+        def ordered_pairs_sharing(level):
+            a = anc[level][nodes]
+            _, c = np.unique(a, return_counts=True)
+            return int((c * (c - 1)).sum())
+        # pairs whose ancestors k levels up differ but k+1 levels up coincide
+        for k in range(0, d):
+            same_up = ordered_pairs_sharing(k + 1)
+            same_here = ordered_pairs_sharing(k) if k > 0 else 0
+            deltas[k] += same_up - same_here
+    while deltas and deltas[-1] == 0:
+        deltas.pop()
+    deltas.append(0)
+    return total, deltas
