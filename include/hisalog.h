@@ -1,0 +1,213 @@
+/*
+ * hisalog: semi-naive Datalog fixpoint evaluation on one AMD MI355X (gfx950)
+ * over hash-indexed sorted arrays (HISA).
+ *
+ * The method is that of "Optimizing Datalog for the GPU" (Sun, Shovon,
+ * Gilray, Kumar, Micinski): relations are sorted arrays of packed tuples
+ * with an open-addressing hash index from join key to run start (Section 3);
+ * each fixpoint iteration joins the delta of each recursive relation against
+ * the indexed full relations (Section 5.1, Algorithm 3), deduplicates the new
+ * tuples by sorting (Section 3.2), subtracts full to form the next delta
+ * (Section 5.1, "Populating delta") and merges delta into full (Section 5.1,
+ * "Merging Full with Delta"), with multi-atom bodies evaluated as a chain of
+ * materialised binary joins (Section 5.2) and merge buffers kept and grown
+ * eagerly (Section 5.3).  Evaluation stops when every delta is empty.
+ *
+ * Conventions for every call:
+ *   - Return value: HL_OK (0) or a negative HL_E_* code; no call aborts or
+ *     throws.  hl_last_error(engine) describes the most recent failure.
+ *   - Relation tuples are uint32 columns; host and device row buffers are
+ *     row-major n x arity.  This build supports arity 2 (binary relations);
+ *     other arities are rejected with HL_E_UNSUPPORTED.
+ *   - One engine is used by one host thread at a time.  Device work is
+ *     enqueued on the engine's stream; calls that return host-visible
+ *     results synchronise that stream before returning.
+ *   - Pointers named d_* are device pointers (HIP device memory of the
+ *     engine's device); all others are host pointers.  The caller keeps
+ *     ownership of every buffer it passes in.
+ */
+#ifndef HISALOG_H
+#define HISALOG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define HL_OK 0
+#define HL_E_INVALID (-1)     /* bad argument, unknown relation, parse error */
+#define HL_E_NOMEM (-2)       /* device memory (arena or budget) exhausted */
+#define HL_E_DEVICE (-3)      /* a HIP runtime call failed; text in hl_last_error */
+#define HL_E_STATE (-4)       /* call not allowed in the engine's current state */
+#define HL_E_CAPACITY (-5)    /* caller's output buffer too small; size returned */
+#define HL_E_UNSUPPORTED (-6) /* a valid program or option this build does not run */
+
+/* ---------------------------------------------------------------- flags */
+#define HL_FLAG_NO_EBM 0x1u /* disable eager buffer management (exact-size
+                               buffers, reallocated on every growth: the
+                               paper's "Normal" column of Table 1) */
+
+/* Phases of one fixpoint, timed with HIP events (milliseconds). */
+#define HL_PHASE_INDEX_EDB 0 /* EDB dedup + HISA builds before iteration 0 */
+#define HL_PHASE_JOIN 1      /* probes and expands of every rule */
+#define HL_PHASE_SORT 2      /* radix sort of the new tuples */
+#define HL_PHASE_DIFF 3      /* dedup + subtraction of full (delta) */
+#define HL_PHASE_MERGE 4     /* full := full U delta */
+#define HL_PHASE_INDEX 5     /* index refresh of probed full relations */
+#define HL_PHASE_COUNT 6
+
+typedef struct hl_engine hl_engine;
+
+typedef struct hl_options {
+  int32_t device;            /* HIP device ordinal */
+  uint32_t flags;            /* HL_FLAG_* */
+  void* arena;               /* optional caller-owned device memory that all
+                                engine buffers are carved from (never freed
+                                by the engine); NULL: the engine allocates
+                                with hipMalloc up to hbm_budget_bytes */
+  uint64_t arena_bytes;      /* size of arena */
+  uint64_t hbm_budget_bytes; /* cap on engine allocations when arena == NULL
+                                (0: no cap beyond the device) */
+  void* stream;              /* hipStream_t to enqueue on; NULL: own stream */
+  float ebm_k;               /* growth factor k of Section 5.3: a buffer that
+                                must grow to hold |full| + |delta| is
+                                reallocated to |full| + k |delta| (default 8) */
+  float hash_load_factor;    /* HISA hash table load factor in (0, 1]
+                                (Section 6.3 uses 0.8, the default) */
+  uint32_t reserved[8];      /* must be zero */
+} hl_options;
+
+typedef struct hl_stats {
+  uint32_t iterations;           /* iterations run, including iteration 0 (the
+                                    EDB-only rules) and the final empty one */
+  uint32_t key_bytes;            /* 4 or 8: packed key width chosen at run */
+  uint32_t id_bits;              /* w: bits per column in a packed key */
+  uint32_t reserved0;
+  uint64_t idb_tuples;           /* sum over IDB relations of |full| at fixpoint */
+  uint64_t candidates;           /* join outputs over all iterations */
+  uint64_t peak_bytes;           /* peak device bytes held by the engine */
+  uint64_t allocations;          /* device allocations made during the run */
+  uint64_t ebm_reuses;           /* buffer requests served without allocating */
+  double seconds;                /* wall time of hl_run (host clock) */
+  double phase_ms[HL_PHASE_COUNT];
+} hl_stats;
+
+/* Fills *opt with defaults: device 0, no arena, own stream, ebm_k 8,
+ * load factor 0.8. */
+int hl_options_init(hl_options* opt);
+
+/* Creates an engine on opt->device.  *out receives the handle (NULL on
+ * failure).  With opt->stream set, the engine never creates or destroys a
+ * stream; the caller keeps that stream alive until hl_destroy. */
+int hl_create(const hl_options* opt, hl_engine** out);
+
+/* Releases every device buffer the engine allocated (never the caller's
+ * arena or stream).  NULL is ignored. */
+void hl_destroy(hl_engine* e);
+
+/* Declares relation `name` (identifier, at most 63 bytes) of `arity` columns,
+ * extensional (is_edb != 0: loaded with hl_load*) or intensional (derived by
+ * rules).  Before hl_program.  Duplicate names: HL_E_INVALID. */
+int hl_declare(hl_engine* e, const char* name, uint32_t arity, int32_t is_edb);
+
+/* Appends n_rows host rows (row-major n x arity uint32) to EDB relation
+ * `name`.  The rows are copied before the call returns.  Duplicates are
+ * removed at hl_run (relations are sets).  Any uint32 value is a legal id. */
+int hl_load(hl_engine* e, const char* name, const uint32_t* rows, uint64_t n_rows);
+
+/* Same from device memory d_rows (stream-ordered on the engine's stream:
+ * d_rows may be reused once the engine's stream has passed this call). */
+int hl_load_device(hl_engine* e, const char* name, const uint32_t* d_rows, uint64_t n_rows);
+
+/* Requests a HISA on relation `name` keyed by its column cols[0]
+ * (Section 3: sorted array + hash index).  Only ncols == 1 is supported.
+ * Optional: hl_program declares every index its rules probe. */
+int hl_index(hl_engine* e, const char* name, const uint32_t* cols, uint32_t ncols);
+
+/* Adds the rules of `text`:  Head(x, y) :- A(x, z), B(z, y), x != y.
+ * Positive rules over declared relations; variables are identifiers, `_`
+ * is a wildcard in body atoms; `x != y` filters two body variables; `//`
+ * and `#` start comments.  Every head variable must occur in the body.
+ * A rule body is evaluated as a chain of binary joins (Section 5.2) in
+ * which each further atom shares exactly one variable with the pair
+ * carried so far and at most two variables stay live; other shapes give
+ * HL_E_UNSUPPORTED. */
+int hl_program(hl_engine* e, const char* text);
+
+/* Runs semi-naive evaluation to the fixpoint (Section 5.1), Jacobi order:
+ * iteration 0 evaluates the rules whose bodies are EDB-only; iteration
+ * i >= 1 evaluates every rule with an IDB body atom once per such atom,
+ * that atom over the delta of iteration i-1 and the other IDB atoms over
+ * full; deltas are formed and merged after all rules.  Blocking.  May be
+ * called again: IDB relations restart from empty.  stats may be NULL. */
+int hl_run(hl_engine* e, hl_stats* stats);
+
+/* *n = number of tuples of relation `name` (after hl_run). */
+int hl_count(hl_engine* e, const char* name, uint64_t* n);
+
+/* Copies relation `name` as sorted (lexicographic in declared column
+ * order), duplicate-free row-major uint32 rows into host buffer rows of
+ * cap_rows rows.  *n_rows receives the relation size; when cap_rows is
+ * smaller the call copies nothing and returns HL_E_CAPACITY. */
+int hl_fetch(hl_engine* e, const char* name, uint32_t* rows, uint64_t cap_rows,
+             uint64_t* n_rows);
+
+/* Same into device memory d_rows (synchronises before returning). */
+int hl_fetch_device(hl_engine* e, const char* name, uint32_t* d_rows, uint64_t cap_rows,
+                    uint64_t* n_rows);
+
+/* Per-iteration delta sizes of relation `name` from the last hl_run:
+ * counts[i] = |delta| of iteration i, for i < min(cap, iterations);
+ * *n_iters = iterations.  which = 0: delta sizes; 1: number of distinct
+ * tuples derived in the iteration before subtracting full. */
+int hl_iteration_counts(hl_engine* e, const char* name, int32_t which, uint64_t* counts,
+                        uint32_t cap, uint32_t* n_iters);
+
+/* Text of the most recent error of e (never NULL; "" when none). */
+const char* hl_last_error(hl_engine* e);
+
+/* Static text for a return code. */
+const char* hl_strerror(int code);
+
+/* ------------------------------------------------------------ primitives
+ * The kernels of one iteration, exposed on device buffers so each can be
+ * checked on its own.  They run on the engine's stream, use its memory
+ * (arena or budget) for temporaries and synchronise before returning.
+ * key_bytes is 4 (uint32 keys) or 8 (uint64 keys).  Sizes are element
+ * counts. */
+
+/* Sorts n keys of d_keys ascending in place by their low `bits` bits
+ * (all bits when bits == 0); higher bits must be zero (Section 3.2,
+ * Algorithm 1: LSD order over the packed columns).  n < 2^32. */
+int hl_sort_keys(hl_engine* e, void* d_keys, uint64_t n, uint32_t key_bytes, uint32_t bits);
+
+/* d_out = unique(d_sorted) minus d_full (Section 5.1, "Populating delta";
+ * Section 3.2, "Deduplication").  d_sorted: n ascending keys (repeats
+ * allowed); d_full: n_full ascending distinct keys; d_out: room for n keys.
+ * *n_out = |d_out|, *n_unique = distinct keys of d_sorted.  n < 2^32. */
+int hl_unique_diff(hl_engine* e, const void* d_sorted, uint64_t n, const void* d_full,
+                   uint64_t n_full, void* d_out, uint64_t* n_out, uint64_t* n_unique,
+                   uint32_t key_bytes);
+
+/* d_out (room for na + nb keys) = merge of ascending d_a and d_b
+ * (Section 3.2, "Merge operation": merge path). */
+int hl_merge(hl_engine* e, const void* d_a, uint64_t na, const void* d_b, uint64_t nb,
+             void* d_out, uint32_t key_bytes);
+
+/* Builds a HISA over n ascending keys d_keys whose join column is
+ * key >> shift (Section 3.3, Algorithm 2), then answers nq range queries:
+ * for join value d_queries[i], d_start[i] = position of the first key with
+ * that join value and d_len[i] = number of such keys (0 when absent;
+ * d_start is then 0).  *n_runs receives the number of distinct join values.
+ * n < 2^32. */
+int hl_hisa_query(hl_engine* e, const void* d_keys, uint64_t n, uint32_t key_bytes,
+                  uint32_t shift, const uint32_t* d_queries, uint64_t nq, uint64_t* d_start,
+                  uint32_t* d_len, uint64_t* n_runs);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HISALOG_H */

@@ -1,0 +1,1276 @@
+// Host side of hisalog: device memory (arena + eager buffer management),
+// the rule parser and planner, the semi-naive fixpoint driver and the C ABI
+// declared in include/hisalog.h.  Every step of an iteration runs in the
+// gfx950 kernels of this directory; the host only sequences launches and
+// reads back the few counts that size the next launch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <set>
+#include <string>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "../../include/hisalog.h"
+#include "kernels.hpp"
+
+namespace {
+
+using hl::JoinSpec;
+using hl::Slot;
+using hl::u32;
+using hl::u64;
+
+struct Error {
+  int code;
+  std::string msg;
+};
+
+[[noreturn]] void fail(int code, const std::string& msg) { throw Error{code, msg}; }
+
+void hip_check(hipError_t e, const char* what) {
+  if (e != hipSuccess) {
+    (void)hipGetLastError();  // clear the sticky launch error
+    fail(HL_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  }
+}
+#define HIPCK(expr) hip_check((expr), #expr)
+
+// ------------------------------------------------------------------ memory
+
+// Device memory provider.  With a caller arena every buffer is carved out
+// of it (first fit, 256-byte aligned, coalescing free list); otherwise each
+// buffer is a hipMalloc, capped by the budget.
+class Memory {
+ public:
+  void init(void* arena, u64 arena_bytes, u64 budget, hipStream_t s) {
+    base_ = static_cast<char*>(arena);
+    size_ = arena_bytes;
+    budget_ = budget;
+    stream_ = s;
+    if (base_) {
+      u64 start = hl::align_up(reinterpret_cast<uintptr_t>(base_), 256) -
+                  reinterpret_cast<uintptr_t>(base_);
+      if (start < size_) free_[start] = size_ - start;
+    }
+  }
+
+  void* alloc(u64 bytes) {
+    bytes = hl::align_up(bytes ? bytes : 1, 256);
+    void* p = nullptr;
+    if (base_) {
+      for (auto it = free_.begin(); it != free_.end(); ++it) {
+        if (it->second >= bytes) {
+          u64 off = it->first, sz = it->second;
+          free_.erase(it);
+          if (sz > bytes) free_[off + bytes] = sz - bytes;
+          p = base_ + off;
+          break;
+        }
+      }
+      if (!p) fail(HL_E_NOMEM, "arena exhausted: need " + std::to_string(bytes) + " bytes, " +
+                                   std::to_string(in_use_) + " in use of " +
+                                   std::to_string(size_));
+    } else {
+      if (budget_ && in_use_ + bytes > budget_)
+        fail(HL_E_NOMEM, "device budget exceeded: need " + std::to_string(bytes) + " bytes");
+      hipError_t e = hipMalloc(&p, bytes);
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        fail(HL_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+      }
+    }
+    live_[p] = bytes;
+    in_use_ += bytes;
+    peak_ = std::max(peak_, in_use_);
+    ++allocs_;
+    return p;
+  }
+
+  void release(void* p) {
+    if (!p) return;
+    auto it = live_.find(p);
+    if (it == live_.end()) return;
+    u64 bytes = it->second;
+    live_.erase(it);
+    in_use_ -= bytes;
+    if (base_) {
+      // later stream work may reuse the range: every user is on one stream
+      u64 off = static_cast<char*>(p) - base_;
+      auto nx = free_.lower_bound(off);
+      if (nx != free_.end() && off + bytes == nx->first) {
+        bytes += nx->second;
+        free_.erase(nx);
+      }
+      auto pv = free_.lower_bound(off);
+      if (pv != free_.begin()) {
+        --pv;
+        if (pv->first + pv->second == off) {
+          pv->second += bytes;
+          return;
+        }
+      }
+      free_[off] = bytes;
+    } else {
+      (void)hipStreamSynchronize(stream_);
+      (void)hipFree(p);
+    }
+  }
+
+  void release_all() {
+    std::vector<void*> ps;
+    for (auto& kv : live_) ps.push_back(kv.first);
+    for (void* p : ps) release(p);
+  }
+
+  u64 peak() const { return peak_; }
+  u64 allocs() const { return allocs_; }
+  void reset_counters() {
+    peak_ = in_use_;
+    allocs_ = 0;
+  }
+
+ private:
+  char* base_ = nullptr;
+  u64 size_ = 0, budget_ = 0, in_use_ = 0, peak_ = 0, allocs_ = 0;
+  hipStream_t stream_ = nullptr;
+  std::map<u64, u64> free_;
+  std::unordered_map<void*, u64> live_;
+};
+
+struct Buf {
+  void* p = nullptr;
+  u64 bytes = 0;
+};
+
+// ------------------------------------------------------------------ program
+
+struct Atom {
+  int rel = -1;
+  int arg[2] = {-1, -1};  // variable ids; wildcards get fresh ids
+};
+
+struct Rule {
+  Atom head;
+  std::vector<Atom> body;
+  std::vector<std::pair<int, int>> neq;  // variable pairs that must differ
+  int nvars = 0;
+  std::string text;
+};
+
+// One binary join of a chain (Section 5.2): the carried pair (outer) is
+// joined with the HISA of `inner_rel` keyed by column `inner_col`.
+struct Step {
+  int inner_rel = -1;
+  int inner_col = 0;
+  JoinSpec js{};
+};
+
+struct Plan {
+  int rule = -1;
+  int head = -1;
+  int outer_rel = -1;
+  bool outer_delta = false;
+  JoinSpec proj{};          // for a body of one atom
+  std::vector<Step> steps;  // empty: projection only
+};
+
+struct Index {
+  bool used = false;
+  Buf keys, spare;  // column 1 only: the relation with columns swapped
+  u64 n = 0;
+  Buf table;
+  u64 cap = 0, runs = 0;
+};
+
+struct Relation {
+  std::string name;
+  int arity = 2;
+  bool edb = false;
+  Buf raw;
+  u64 n_raw = 0;
+  Buf full, full_spare, delta, cand;
+  u64 n_full = 0, n_delta = 0, n_cand = 0;
+  Index idx[2];
+  std::vector<u64> delta_counts, new_counts;
+};
+
+// --------------------------------------------------------------- the parser
+
+class Lexer {
+ public:
+  explicit Lexer(const std::string& s) : s_(s) {}
+  void skip() {
+    for (;;) {
+      while (i_ < s_.size() && isspace(static_cast<unsigned char>(s_[i_]))) ++i_;
+      if (i_ < s_.size() && (s_[i_] == '#' || (s_[i_] == '/' && i_ + 1 < s_.size() &&
+                                               s_[i_ + 1] == '/'))) {
+        while (i_ < s_.size() && s_[i_] != '\n') ++i_;
+        continue;
+      }
+      return;
+    }
+  }
+  bool done() {
+    skip();
+    return i_ >= s_.size();
+  }
+  bool accept(const char* lit) {
+    skip();
+    size_t n = strlen(lit);
+    if (s_.compare(i_, n, lit) == 0) {
+      i_ += n;
+      return true;
+    }
+    return false;
+  }
+  void expect(const char* lit) {
+    if (!accept(lit)) fail(HL_E_INVALID, std::string("parse error: expected '") + lit +
+                                             "' at offset " + std::to_string(i_));
+  }
+  std::string ident() {
+    skip();
+    size_t b = i_;
+    if (i_ < s_.size() && (isalpha(static_cast<unsigned char>(s_[i_])) || s_[i_] == '_')) {
+      ++i_;
+      while (i_ < s_.size() && (isalnum(static_cast<unsigned char>(s_[i_])) || s_[i_] == '_'))
+        ++i_;
+    }
+    if (b == i_) fail(HL_E_INVALID, "parse error: expected a name at offset " + std::to_string(i_));
+    return s_.substr(b, i_ - b);
+  }
+  size_t pos() const { return i_; }
+  void seek(size_t p) { i_ = p; }
+
+ private:
+  const std::string& s_;
+  size_t i_ = 0;
+};
+
+}  // namespace
+
+// ------------------------------------------------------------------ engine
+
+struct hl_engine {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  u32 flags = 0;
+  float ebm_k = 8.0f;
+  float load_factor = 0.8f;
+  Memory mem;
+  std::string err;
+
+  std::vector<Relation> rels;
+  std::vector<Rule> rules;
+  std::vector<Plan> plans0, plansR;  // iteration 0 / recursive plans
+  bool ran = false;
+
+  // run state
+  int w = 1;
+  int key_bytes = 4;
+  Buf alt, tmp[2], ws, join_start, join_len, join_off, join_parts, rows;
+  u64* d_small = nullptr;  // device scalars
+  u64* h_small = nullptr;  // pinned mirror
+  static constexpr int kSmall = 512;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, hipEvent_t>> marks;
+  hl_stats st{};
+  u64 reuses = 0;
+
+  // ---------------------------------------------------------------- utils
+
+  int find(const std::string& n) const {
+    for (size_t k = 0; k < rels.size(); ++k)
+      if (rels[k].name == n) return int(k);
+    return -1;
+  }
+  int find_or_fail(const char* n) const {
+    if (!n) fail(HL_E_INVALID, "null relation name");
+    int k = find(n);
+    if (k < 0) fail(HL_E_INVALID, std::string("unknown relation ") + n);
+    return k;
+  }
+
+  void sync() { HIPCK(hipStreamSynchronize(stream)); }
+
+  // Eager buffer management (Section 5.3): a buffer that is large enough is
+  // reused; one that must grow is reallocated to `want` (>= need) bytes.
+  // With HL_FLAG_NO_EBM every request gets an exact-size buffer.
+  void reserve(Buf& b, u64 need, u64 want) {
+    if (need == 0) return;
+    bool no_ebm = flags & HL_FLAG_NO_EBM;
+    if (!no_ebm && b.bytes >= need) {
+      ++reuses;
+      return;
+    }
+    if (no_ebm && b.bytes == need) {
+      ++reuses;
+      return;
+    }
+    mem.release(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+    u64 sz = no_ebm ? need : std::max(need, want);
+    b.p = mem.alloc(sz);
+    b.bytes = sz;
+  }
+  void reserve_grow(Buf& b, u64 need) { reserve(b, need, need + need / 2); }
+  // Like reserve_grow, but keeps the first `used` bytes of the buffer.
+  void reserve_keep(Buf& b, u64 used, u64 need) {
+    if (need <= b.bytes && !(flags & HL_FLAG_NO_EBM)) {
+      ++reuses;
+      return;
+    }
+    if (need <= b.bytes && b.bytes == need) {
+      ++reuses;
+      return;
+    }
+    Buf nb;
+    const u64 sz = (flags & HL_FLAG_NO_EBM) ? need : need + need / 2;
+    nb.p = mem.alloc(sz);
+    nb.bytes = sz;
+    if (used) HIPCK(hipMemcpyAsync(nb.p, b.p, used, hipMemcpyDeviceToDevice, stream));
+    drop(b);
+    b = nb;
+  }
+  void drop(Buf& b) {
+    mem.release(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+
+  void mark(int phase) {
+    if (ev_used == ev_pool.size()) {
+      hipEvent_t ev;
+      HIPCK(hipEventCreate(&ev));
+      ev_pool.push_back(ev);
+    }
+    hipEvent_t ev = ev_pool[ev_used++];
+    HIPCK(hipEventRecord(ev, stream));
+    marks.push_back({phase, ev});
+  }
+  // After a synchronisation: attributes the time between marks to phases.
+  void collect() {
+    for (size_t k = 1; k < marks.size(); ++k) {
+      int ph = marks[k - 1].first;
+      if (ph < 0) continue;
+      float ms = 0.f;
+      HIPCK(hipEventElapsedTime(&ms, marks[k - 1].second, marks[k].second));
+      st.phase_ms[ph] += ms;
+    }
+    if (!marks.empty()) {
+      auto last = marks.back();
+      marks.clear();
+      // keep the last event as the start of the next segment
+      std::swap(ev_pool[0], ev_pool[ev_used - 1]);
+      marks.push_back({last.first, ev_pool[0]});
+      ev_used = 1;
+    }
+  }
+
+  // --------------------------------------------------------------- parse
+
+  Atom parse_atom(Lexer& lx, std::map<std::string, int>& vars, int& nvars, bool head) {
+    Atom a;
+    std::string name = lx.ident();
+    a.rel = find(name);
+    if (a.rel < 0) fail(HL_E_INVALID, "undeclared relation " + name);
+    lx.expect("(");
+    int k = 0;
+    for (;;) {
+      std::string v = lx.ident();
+      if (k >= 2) fail(HL_E_INVALID, "too many arguments for " + name);
+      if (v == "_") {
+        if (head) fail(HL_E_INVALID, "wildcard in a rule head");
+        a.arg[k] = nvars++;
+      } else {
+        auto it = vars.find(v);
+        if (it == vars.end()) it = vars.emplace(v, nvars++).first;
+        a.arg[k] = it->second;
+      }
+      ++k;
+      if (lx.accept(",")) continue;
+      lx.expect(")");
+      break;
+    }
+    if (k != rels[a.rel].arity) fail(HL_E_INVALID, "arity mismatch for " + name);
+    return a;
+  }
+
+  std::vector<Rule> parse(const std::string& text) {
+    Lexer lx(text);
+    std::vector<Rule> out;
+    while (!lx.done()) {
+      Rule r;
+      size_t begin = lx.pos();
+      std::map<std::string, int> vars;
+      r.head = parse_atom(lx, vars, r.nvars, true);
+      if (rels[r.head.rel].edb) fail(HL_E_INVALID, "rule head is an EDB relation");
+      lx.expect(":-");
+      std::vector<std::pair<std::string, std::string>> filters;
+      for (;;) {
+        size_t save = lx.pos();
+        std::string id = lx.ident();
+        if (lx.accept("!=")) {
+          filters.push_back({id, lx.ident()});
+        } else {
+          lx.seek(save);
+          r.body.push_back(parse_atom(lx, vars, r.nvars, false));
+        }
+        if (lx.accept(",")) continue;
+        lx.expect(".");
+        break;
+      }
+      std::set<int> bodyvars;
+      for (auto& a : r.body) bodyvars.insert({a.arg[0], a.arg[1]});
+      for (int v : r.head.arg)
+        if (!bodyvars.count(v)) fail(HL_E_INVALID, "head variable not bound in the body");
+      for (auto& f : filters) {
+        auto a = vars.find(f.first), b = vars.find(f.second);
+        if (a == vars.end() || b == vars.end() || !bodyvars.count(a->second) ||
+            !bodyvars.count(b->second))
+          fail(HL_E_INVALID, "filter on a variable that no body atom binds");
+        r.neq.push_back({a->second, b->second});
+      }
+      if (r.body.empty()) fail(HL_E_INVALID, "rule without a body");
+      r.text = text.substr(begin, lx.pos() - begin);
+      out.push_back(r);
+    }
+    return out;
+  }
+
+  // ---------------------------------------------------------------- plan
+
+  // Chain of binary joins starting from body atom `first` (Section 5.2,
+  // temporarily materialised n-way joins).
+  Plan plan_rule(int rule_id, int first, bool outer_delta) {
+    const Rule& r = rules[rule_id];
+    Plan p;
+    p.rule = rule_id;
+    p.head = r.head.rel;
+    p.outer_rel = r.body[first].rel;
+    p.outer_delta = outer_delta;
+    auto unsupported = [&](const std::string& why) {
+      fail(HL_E_UNSUPPORTED, "rule '" + r.text + "': " + why);
+    };
+    int cur[2] = {r.body[first].arg[0], r.body[first].arg[1]};
+    if (cur[0] == cur[1]) unsupported("an atom repeats a variable");
+    std::vector<int> remaining;
+    for (int j = 0; j < int(r.body.size()); ++j)
+      if (j != first) remaining.push_back(j);
+    std::vector<bool> applied(r.neq.size(), false);
+    auto src_of = [&](int v, const int* avail, int navail) {
+      for (int k = 0; k < navail; ++k)
+        if (avail[k] == v) return k;
+      return -1;
+    };
+    auto take_filter = [&](JoinSpec& js, const int* avail, int navail) {
+      js.fa = js.fb = -1;
+      for (size_t f = 0; f < r.neq.size(); ++f) {
+        if (applied[f]) continue;
+        int a = src_of(r.neq[f].first, avail, navail), b = src_of(r.neq[f].second, avail, navail);
+        if (a < 0 || b < 0) continue;
+        if (js.fa >= 0) unsupported("two filters apply at one join");
+        js.fa = a;
+        js.fb = b;
+        applied[f] = true;
+      }
+    };
+    if (remaining.empty()) {
+      p.proj.outer_col = 0;
+      take_filter(p.proj, cur, 2);
+      p.proj.src0 = src_of(r.head.arg[0], cur, 2);
+      p.proj.src1 = src_of(r.head.arg[1], cur, 2);
+      return p;
+    }
+    while (!remaining.empty()) {
+      int pick = -1, shared = -1;
+      for (size_t q = 0; q < remaining.size() && pick < 0; ++q) {
+        const Atom& b = r.body[remaining[q]];
+        int hits = 0;
+        for (int c = 0; c < 2; ++c)
+          if (b.arg[c] == cur[0] || b.arg[c] == cur[1]) ++hits, shared = c;
+        if (hits == 2) unsupported("an atom shares two variables with the carried pair");
+        if (hits == 1) pick = int(q);
+      }
+      if (pick < 0) unsupported("a body atom shares no variable with the carried pair");
+      const Atom& b = r.body[remaining[pick]];
+      remaining.erase(remaining.begin() + pick);
+      if (b.arg[0] == b.arg[1]) unsupported("an atom repeats a variable");
+      Step s;
+      s.inner_rel = b.rel;
+      s.inner_col = shared;
+      const int sv = b.arg[shared], other = b.arg[1 - shared];
+      s.js.outer_col = (cur[0] == sv) ? 0 : 1;
+      int avail[3] = {cur[0], cur[1], other};
+      take_filter(s.js, avail, 3);
+      if (remaining.empty()) {
+        s.js.src0 = src_of(r.head.arg[0], avail, 3);
+        s.js.src1 = src_of(r.head.arg[1], avail, 3);
+        if (s.js.src0 < 0 || s.js.src1 < 0) unsupported("head variable lost");
+      } else {
+        std::set<int> need;
+        for (int q : remaining) need.insert({r.body[q].arg[0], r.body[q].arg[1]});
+        need.insert({r.head.arg[0], r.head.arg[1]});
+        for (size_t f = 0; f < r.neq.size(); ++f)
+          if (!applied[f]) need.insert({r.neq[f].first, r.neq[f].second});
+        std::vector<int> keep;
+        for (int k = 0; k < 3; ++k)
+          if (need.count(avail[k]) && std::find(keep.begin(), keep.end(), avail[k]) == keep.end())
+            keep.push_back(avail[k]);
+        if (keep.size() > 2) unsupported("three variables stay live between joins");
+        if (keep.empty()) unsupported("no variable carried to the next join");
+        if (keep.size() == 1) keep.push_back(keep[0]);
+        s.js.src0 = src_of(keep[0], avail, 3);
+        s.js.src1 = src_of(keep[1], avail, 3);
+        cur[0] = keep[0];
+        cur[1] = keep[1];
+        if (cur[0] == cur[1]) {
+          // a single live variable: the next atom must still share it
+        }
+      }
+      p.steps.push_back(s);
+    }
+    for (size_t f = 0; f < applied.size(); ++f)
+      if (!applied[f]) unsupported("a filter was never applicable");
+    return p;
+  }
+
+  void build_plans() {
+    plans0.clear();
+    plansR.clear();
+    for (int k = 0; k < int(rules.size()); ++k) {
+      const Rule& r = rules[k];
+      bool edb_only = true;
+      for (auto& a : r.body) edb_only &= rels[a.rel].edb;
+      if (edb_only) {
+        plans0.push_back(plan_rule(k, 0, false));
+      } else {
+        for (int t = 0; t < int(r.body.size()); ++t)
+          if (!rels[r.body[t].rel].edb) plansR.push_back(plan_rule(k, t, true));
+      }
+    }
+    for (auto* ps : {&plans0, &plansR})
+      for (auto& p : *ps)
+        for (auto& s : p.steps) rels[s.inner_rel].idx[s.inner_col].used = true;
+  }
+
+  // ----------------------------------------------------------------- run
+
+  template <typename K>
+  K* kp(Buf& b) {
+    return static_cast<K*>(b.p);
+  }
+
+  template <typename K>
+  void build_index(Relation& R, int col, u64* d_runs) {
+    Index& ix = R.idx[col];
+    const K* keys;
+    if (col == 0) {
+      keys = kp<K>(R.full);
+      ix.n = R.n_full;
+    } else {
+      keys = kp<K>(ix.keys);
+    }
+    HIPCK(hl::hisa_count_runs<K>(keys, ix.n, w, d_runs, stream));
+  }
+
+  template <typename K>
+  void finish_index(Relation& R, int col, u64 runs) {
+    Index& ix = R.idx[col];
+    ix.runs = runs;
+    if (ix.n == 0) {
+      ix.cap = 0;
+      return;
+    }
+    if (ix.n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "indexed relation " + R.name +
+                                                           " has 2^32 or more tuples");
+    u64 cap = u64(std::ceil(double(runs) / load_factor));
+    cap = std::max(cap, runs + 1);
+    cap = std::max<u64>(cap, 16);
+    reserve(ix.table, cap * sizeof(Slot), cap * sizeof(Slot) * 2);
+    ix.cap = cap;
+    HIPCK(hl::fill_zero(ix.table.p, cap * sizeof(Slot), stream));
+    const K* keys = col == 0 ? kp<K>(R.full) : kp<K>(ix.keys);
+    HIPCK(hl::hisa_build<K>(keys, ix.n, w, static_cast<Slot*>(ix.table.p), cap, stream));
+  }
+
+  // Refreshes every used index of the listed relations: column-1 copies
+  // take the new delta (swapped, sorted, merged), then the hash tables are
+  // rebuilt from the run counts (one synchronisation for all of them).
+  template <typename K>
+  void refresh_indexes(const std::vector<int>& which) {
+    std::vector<std::pair<int, int>> todo;
+    for (int r : which)
+      for (int c = 0; c < 2; ++c)
+        if (rels[r].idx[c].used) todo.push_back({r, c});
+    if (todo.empty()) return;
+    if (todo.size() > kSmall) fail(HL_E_UNSUPPORTED, "too many indexes");
+    for (size_t q = 0; q < todo.size(); ++q) {
+      Relation& R = rels[todo[q].first];
+      build_index<K>(R, todo[q].second, d_small + q);
+    }
+    HIPCK(hipMemcpyAsync(h_small, d_small, todo.size() * sizeof(u64), hipMemcpyDeviceToHost,
+                         stream));
+    sync();
+    for (size_t q = 0; q < todo.size(); ++q)
+      finish_index<K>(rels[todo[q].first], todo[q].second, h_small[q]);
+  }
+
+  // Column-1 index copy of R: merge in the swapped new delta (or build it
+  // from full for an EDB relation).
+  template <typename K>
+  void update_swapped(Relation& R, const K* src, u64 n_src, bool from_scratch) {
+    Index& ix = R.idx[1];
+    if (!ix.used) return;
+    if (n_src == 0) {
+      if (from_scratch) ix.n = 0;
+      return;
+    }
+    const int bits = 2 * w;
+    reserve_grow(alt, n_src * sizeof(K));
+    reserve_grow(tmp[0], n_src * sizeof(K));
+    HIPCK(hl::swap_cols<K>(src, n_src, w, kp<K>(tmp[0]), stream));
+    reserve(ws, hl::sort_workspace_bytes(n_src), hl::sort_workspace_bytes(n_src) * 2);
+    K* sorted = nullptr;
+    HIPCK(hl::radix_sort<K>(kp<K>(tmp[0]), kp<K>(alt), n_src, bits, ws.p, stream, &sorted));
+    if (from_scratch || ix.n == 0) {
+      reserve(ix.keys, n_src * sizeof(K), u64(double(n_src) * sizeof(K) * 1.5));
+      HIPCK(hipMemcpyAsync(ix.keys.p, sorted, n_src * sizeof(K), hipMemcpyDeviceToDevice, stream));
+      ix.n = n_src;
+      return;
+    }
+    const u64 total = ix.n + n_src;
+    reserve(ix.spare, total * sizeof(K), u64((double(ix.n) + ebm_k * double(n_src)) * sizeof(K)));
+    reserve(ws, hl::merge_workspace_bytes(ix.n, n_src), hl::merge_workspace_bytes(ix.n, n_src) * 2);
+    HIPCK(hl::merge<K>(kp<K>(ix.keys), ix.n, sorted, n_src, kp<K>(ix.spare), ws.p, stream));
+    std::swap(ix.keys, ix.spare);
+    ix.n = total;
+  }
+
+  template <typename K>
+  void load_edbs() {
+    std::vector<int> edbs;
+    for (int k = 0; k < int(rels.size()); ++k) {
+      Relation& R = rels[k];
+      if (!R.edb) continue;
+      edbs.push_back(k);
+      R.n_full = 0;
+      R.idx[0].n = R.idx[1].n = 0;
+      if (R.n_raw == 0) continue;
+      if (R.n_raw >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "EDB relation with 2^32 or more rows");
+      reserve_grow(R.cand, R.n_raw * sizeof(K));
+      reserve_grow(alt, R.n_raw * sizeof(K));
+      HIPCK(hl::pack_rows<K>(static_cast<const u32*>(R.raw.p), R.n_raw, R.arity, w, kp<K>(R.cand),
+                             stream));
+      reserve(ws, hl::sort_workspace_bytes(R.n_raw), hl::sort_workspace_bytes(R.n_raw) * 2);
+      K* sorted = nullptr;
+      HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_raw, 2 * w, ws.p, stream, &sorted));
+      K* other = sorted == kp<K>(R.cand) ? kp<K>(alt) : kp<K>(R.cand);
+      reserve(R.full, R.n_raw * sizeof(K), R.n_raw * sizeof(K));
+      reserve(ws, hl::unique_diff_workspace_bytes(R.n_raw),
+              hl::unique_diff_workspace_bytes(R.n_raw) * 2);
+      HIPCK(hl::unique_diff<K>(sorted, R.n_raw, static_cast<const K*>(nullptr), 0, other,
+                               kp<K>(R.full), d_small, ws.p, stream));
+      HIPCK(hipMemcpyAsync(h_small, d_small, sizeof(u64), hipMemcpyDeviceToHost, stream));
+      sync();
+      R.n_full = h_small[0];
+      R.idx[0].n = R.n_full;
+      if (R.idx[1].used) update_swapped<K>(R, kp<K>(R.full), R.n_full, true);
+    }
+    refresh_indexes<K>(edbs);
+  }
+
+  // Evaluates one plan, appending head tuples to the head's candidates.
+  template <typename K>
+  void run_plan(const Plan& p) {
+    Relation& O = rels[p.outer_rel];
+    Relation& H = rels[p.head];
+    const K* cur = p.outer_delta ? kp<K>(O.delta) : kp<K>(O.full);
+    u64 n = p.outer_delta ? O.n_delta : O.n_full;
+    if (n == 0) return;
+    u64* d_cursor = d_small;
+    if (p.steps.empty()) {
+      JoinSpec js = p.proj;
+      js.w = w;
+      reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + n) * sizeof(K));
+      const bool filtered = js.fa >= 0;
+      if (filtered) {
+        h_small[0] = H.n_cand;
+        HIPCK(hipMemcpyAsync(d_cursor, h_small, sizeof(u64), hipMemcpyHostToDevice, stream));
+      }
+      HIPCK(hl::project<K>(cur, n, js, kp<K>(H.cand) + (filtered ? 0 : H.n_cand), d_cursor,
+                           stream));
+      if (filtered) {
+        HIPCK(hipMemcpyAsync(h_small, d_cursor, sizeof(u64), hipMemcpyDeviceToHost, stream));
+        sync();
+        st.candidates += h_small[0] - H.n_cand;
+        H.n_cand = h_small[0];
+      } else {
+        H.n_cand += n;
+        st.candidates += n;
+      }
+      return;
+    }
+    int ping = 0;
+    for (size_t q = 0; q < p.steps.size(); ++q) {
+      const Step& s = p.steps[q];
+      Relation& I = rels[s.inner_rel];
+      Index& ix = I.idx[s.inner_col];
+      if (ix.n == 0 || ix.cap == 0) return;
+      const K* inner = s.inner_col == 0 ? kp<K>(I.full) : kp<K>(ix.keys);
+      JoinSpec js = s.js;
+      js.w = w;
+      if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "join outer side of 2^32 or more tuples");
+      reserve_grow(join_start, n * sizeof(u32));
+      reserve_grow(join_len, n * sizeof(u32));
+      reserve_grow(join_off, n * sizeof(u64));
+      HIPCK(hl::join_probe<K>(cur, n, js, static_cast<const Slot*>(ix.table.p), ix.cap,
+                              static_cast<u32*>(join_start.p), static_cast<u32*>(join_len.p),
+                              stream));
+      reserve(ws, hl::scan_workspace_bytes(n), hl::scan_workspace_bytes(n) * 2);
+      HIPCK(hl::scan_u32_u64(static_cast<u32*>(join_len.p), n, static_cast<u64*>(join_off.p),
+                             d_small + 1, ws.p, stream));
+      HIPCK(hipMemcpyAsync(h_small + 1, d_small + 1, sizeof(u64), hipMemcpyDeviceToHost, stream));
+      sync();
+      const u64 total = h_small[1];
+      if (total == 0) return;
+      const bool last = q + 1 == p.steps.size();
+      const bool filtered = js.fa >= 0;
+      K* out;
+      u64 base = 0;
+      if (last) {
+        reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + total) * sizeof(K));
+        out = kp<K>(H.cand);
+        base = H.n_cand;
+      } else {
+        reserve_grow(tmp[ping], total * sizeof(K));
+        out = kp<K>(tmp[ping]);
+      }
+      if (filtered) {
+        h_small[0] = base;
+        HIPCK(hipMemcpyAsync(d_cursor, h_small, sizeof(u64), hipMemcpyHostToDevice, stream));
+      }
+      reserve_grow(join_parts, hl::join_parts(n, total) * sizeof(u64));
+      HIPCK(hl::join_expand<K>(cur, n, static_cast<u64*>(join_off.p),
+                               static_cast<u32*>(join_start.p), inner, total, js,
+                               static_cast<u64*>(join_parts.p), filtered ? out : out + base,
+                               d_cursor, stream));
+      u64 produced = total;
+      if (filtered) {
+        HIPCK(hipMemcpyAsync(h_small, d_cursor, sizeof(u64), hipMemcpyDeviceToHost, stream));
+        sync();
+        produced = h_small[0] - base;
+      }
+      if (last) {
+        H.n_cand += produced;
+        st.candidates += produced;
+      } else {
+        cur = kp<K>(tmp[ping]);
+        n = produced;
+        ping ^= 1;
+        if (n == 0) return;
+      }
+    }
+  }
+
+  // Sort + unique + subtraction of full for every IDB relation, then the
+  // merges and index refreshes.  Returns the total delta size.
+  template <typename K>
+  u64 close_iteration() {
+    const int bits = 2 * w;
+    std::vector<int> idbs;
+    for (int k = 0; k < int(rels.size()); ++k)
+      if (!rels[k].edb) idbs.push_back(k);
+    if (2 * idbs.size() > kSmall) fail(HL_E_UNSUPPORTED, "too many relations");
+    // the deltas become the new outers: free their old contents
+    mark(HL_PHASE_SORT);
+    for (size_t q = 0; q < idbs.size(); ++q) {
+      Relation& R = rels[idbs[q]];
+      R.n_delta = 0;
+      if (R.n_cand == 0) {
+        HIPCK(hl::fill_zero(d_small + 2 * q, 2 * sizeof(u64), stream));
+        continue;
+      }
+      if (R.n_cand >= (u64(1) << 32))
+        fail(HL_E_UNSUPPORTED, "2^32 or more new tuples in one iteration");
+      reserve_grow(alt, R.n_cand * sizeof(K));
+      reserve(ws, hl::sort_workspace_bytes(R.n_cand), hl::sort_workspace_bytes(R.n_cand) * 2);
+      K* sorted = nullptr;
+      mark(HL_PHASE_SORT);
+      HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_cand, bits, ws.p, stream, &sorted));
+      Buf& sbuf = (sorted == kp<K>(R.cand)) ? R.cand : alt;
+      Buf& obuf = (sorted == kp<K>(R.cand)) ? alt : R.cand;
+      reserve(ws, hl::unique_diff_workspace_bytes(R.n_cand),
+              hl::unique_diff_workspace_bytes(R.n_cand) * 2);
+      mark(HL_PHASE_DIFF);
+      // delta is written over the sorted candidates, then takes their buffer
+      HIPCK(hl::unique_diff<K>(kp<K>(sbuf), R.n_cand, kp<K>(R.full), R.n_full, kp<K>(obuf),
+                               kp<K>(sbuf), d_small + 2 * q, ws.p, stream));
+      std::swap(R.delta, sbuf);
+    }
+    HIPCK(hipMemcpyAsync(h_small, d_small, 2 * idbs.size() * sizeof(u64), hipMemcpyDeviceToHost,
+                         stream));
+    mark(-1);
+    sync();
+    collect();
+    u64 total = 0;
+    std::vector<int> grown;
+    mark(HL_PHASE_MERGE);
+    for (size_t q = 0; q < idbs.size(); ++q) {
+      Relation& R = rels[idbs[q]];
+      const u64 D = h_small[2 * q], U = h_small[2 * q + 1];
+      R.n_delta = D;
+      R.delta_counts.push_back(D);
+      R.new_counts.push_back(U);
+      R.n_cand = 0;
+      total += D;
+      if (D == 0) continue;
+      const u64 F = R.n_full;
+      if (F == 0) {
+        reserve(R.full, D * sizeof(K), u64(ebm_k * double(D) * sizeof(K)));
+        HIPCK(hipMemcpyAsync(R.full.p, R.delta.p, D * sizeof(K), hipMemcpyDeviceToDevice, stream));
+      } else {
+        reserve(R.full_spare, (F + D) * sizeof(K), u64((double(F) + ebm_k * double(D)) * sizeof(K)));
+        reserve(ws, hl::merge_workspace_bytes(F, D), hl::merge_workspace_bytes(F, D) * 2);
+        HIPCK(hl::merge<K>(kp<K>(R.full), F, kp<K>(R.delta), D, kp<K>(R.full_spare), ws.p, stream));
+        std::swap(R.full, R.full_spare);
+      }
+      R.n_full = F + D;
+      R.idx[0].n = R.n_full;
+      grown.push_back(idbs[q]);
+    }
+    mark(HL_PHASE_INDEX);
+    for (int r : grown) update_swapped<K>(rels[r], kp<K>(rels[r].delta), rels[r].n_delta, false);
+    refresh_indexes<K>(grown);
+    mark(-1);
+    return total;
+  }
+
+  template <typename K>
+  void run_typed() {
+    mark(HL_PHASE_INDEX_EDB);
+    load_edbs<K>();
+    mark(HL_PHASE_JOIN);
+    for (const Plan& p : plans0) run_plan<K>(p);
+    u64 d = close_iteration<K>();
+    st.iterations = 1;
+    while (d != 0) {
+      mark(HL_PHASE_JOIN);
+      for (const Plan& p : plansR) run_plan<K>(p);
+      d = close_iteration<K>();
+      ++st.iterations;
+    }
+    sync();
+    collect();
+  }
+
+  void run(hl_stats* out) {
+    if (rules.empty()) fail(HL_E_STATE, "no program");
+    auto t0 = std::chrono::steady_clock::now();
+    st = hl_stats{};
+    reuses = 0;
+    mem.reset_counters();
+    marks.clear();
+    ev_used = 0;
+    for (Relation& R : rels) {
+      R.delta_counts.clear();
+      R.new_counts.clear();
+      R.n_delta = R.n_cand = 0;
+      if (!R.edb) {
+        R.n_full = 0;
+        R.idx[0].n = R.idx[1].n = 0;
+        R.idx[0].cap = R.idx[1].cap = 0;
+      }
+    }
+    // key width: ids of every IDB tuple come from the EDBs (range restriction)
+    HIPCK(hl::fill_zero(d_small, sizeof(u64), stream));
+    for (Relation& R : rels)
+      if (R.edb && R.n_raw)
+        HIPCK(hl::max_u32(static_cast<const u32*>(R.raw.p), R.n_raw * R.arity,
+                          reinterpret_cast<u32*>(d_small), stream));
+    HIPCK(hipMemcpyAsync(h_small, d_small, sizeof(u64), hipMemcpyDeviceToHost, stream));
+    sync();
+    const u32 maxid = u32(h_small[0]);
+    w = 1;
+    while (w < 32 && (u64(maxid) >> w) != 0) ++w;
+    key_bytes = (2 * w <= 32) ? 4 : 8;
+    if (key_bytes == 4) run_typed<u32>();
+    else run_typed<u64>();
+    st.key_bytes = key_bytes;
+    st.id_bits = w;
+    for (Relation& R : rels)
+      if (!R.edb) st.idb_tuples += R.n_full;
+    st.peak_bytes = mem.peak();
+    st.allocations = mem.allocs();
+    st.ebm_reuses = reuses;
+    st.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    ran = true;
+    if (out) *out = st;
+  }
+
+  template <typename K>
+  void fetch_typed(Relation& R, u32* d_rows) {
+    HIPCK(hl::unpack_rows<K>(kp<K>(R.full), R.n_full, R.arity, w, d_rows, stream));
+  }
+
+  void fetch(const char* name, u32* rows, u64 cap, u64* n_rows, bool device) {
+    Relation& R = rels[find_or_fail(name)];
+    if (!ran) fail(HL_E_STATE, "fetch before hl_run");
+    if (n_rows) *n_rows = R.n_full;
+    if (cap < R.n_full) fail(HL_E_CAPACITY, "buffer holds " + std::to_string(cap) + " rows, need " +
+                                               std::to_string(R.n_full));
+    if (R.n_full == 0) return;
+    if (!rows) fail(HL_E_INVALID, "null output buffer");
+    const u64 bytes = R.n_full * R.arity * sizeof(u32);
+    u32* dst;
+    if (device) {
+      dst = rows;
+    } else {
+      reserve_grow(this->rows, bytes);
+      dst = static_cast<u32*>(this->rows.p);
+    }
+    if (key_bytes == 4) fetch_typed<u32>(R, dst);
+    else fetch_typed<u64>(R, dst);
+    if (!device) HIPCK(hipMemcpyAsync(rows, dst, bytes, hipMemcpyDeviceToHost, stream));
+    sync();
+  }
+};
+
+// ---------------------------------------------------------------- C ABI
+
+namespace {
+
+template <typename F>
+int guard(hl_engine* e, F&& f) {
+  if (!e) return HL_E_INVALID;
+  try {
+    HIPCK(hipSetDevice(e->device));
+    f();
+    e->err.clear();
+    return HL_OK;
+  } catch (const Error& x) {
+    e->err = x.msg;
+    return x.code;
+  } catch (const std::bad_alloc&) {
+    e->err = "host out of memory";
+    return HL_E_NOMEM;
+  } catch (...) {
+    e->err = "unexpected internal error";
+    return HL_E_INVALID;
+  }
+}
+
+bool valid_key_bytes(u32 kb) { return kb == 4 || kb == 8; }
+
+}  // namespace
+
+extern "C" {
+
+int hl_options_init(hl_options* opt) {
+  if (!opt) return HL_E_INVALID;
+  memset(opt, 0, sizeof(*opt));
+  opt->ebm_k = 8.0f;
+  opt->hash_load_factor = 0.8f;
+  return HL_OK;
+}
+
+int hl_create(const hl_options* opt, hl_engine** out) {
+  if (!out) return HL_E_INVALID;
+  *out = nullptr;
+  hl_options o;
+  hl_options_init(&o);
+  if (opt) o = *opt;
+  if (!(o.ebm_k >= 1.0f) || !(o.hash_load_factor > 0.0f && o.hash_load_factor <= 1.0f))
+    return HL_E_INVALID;
+  for (u32 r : o.reserved)
+    if (r) return HL_E_INVALID;
+  if (o.arena && o.arena_bytes < 4096) return HL_E_INVALID;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
+    (void)hipGetLastError();
+    return HL_E_DEVICE;
+  }
+  hl_engine* e = new (std::nothrow) hl_engine();
+  if (!e) return HL_E_NOMEM;
+  e->device = o.device;
+  e->flags = o.flags;
+  e->ebm_k = o.ebm_k;
+  e->load_factor = o.hash_load_factor;
+  int rc = guard(e, [&] {
+    if (o.stream) {
+      e->stream = static_cast<hipStream_t>(o.stream);
+    } else {
+      HIPCK(hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking));
+      e->own_stream = true;
+    }
+    e->mem.init(o.arena, o.arena_bytes, o.hbm_budget_bytes, e->stream);
+    e->d_small = static_cast<u64*>(e->mem.alloc(hl_engine::kSmall * sizeof(u64)));
+    HIPCK(hipHostMalloc(reinterpret_cast<void**>(&e->h_small), hl_engine::kSmall * sizeof(u64),
+                        hipHostMallocDefault));
+  });
+  if (rc != HL_OK) {
+    hl_destroy(e);
+    return rc;
+  }
+  *out = e;
+  return HL_OK;
+}
+
+void hl_destroy(hl_engine* e) {
+  if (!e) return;
+  (void)hipSetDevice(e->device);
+  if (e->stream) (void)hipStreamSynchronize(e->stream);
+  e->mem.release_all();
+  for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
+  if (e->h_small) (void)hipHostFree(e->h_small);
+  if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
+  delete e;
+}
+
+int hl_declare(hl_engine* e, const char* name, uint32_t arity, int32_t is_edb) {
+  return guard(e, [&] {
+    if (!name || !*name || strlen(name) > 63) fail(HL_E_INVALID, "bad relation name");
+    for (const char* c = name; *c; ++c)
+      if (!(isalnum(static_cast<unsigned char>(*c)) || *c == '_'))
+        fail(HL_E_INVALID, "bad relation name");
+    if (!e->rules.empty()) fail(HL_E_STATE, "declare before hl_program");
+    if (e->find(name) >= 0) fail(HL_E_INVALID, std::string("relation declared twice: ") + name);
+    if (arity != 2) fail(HL_E_UNSUPPORTED, "only binary relations are supported");
+    Relation R;
+    R.name = name;
+    R.arity = int(arity);
+    R.edb = is_edb != 0;
+    e->rels.push_back(R);
+  });
+}
+
+static int load_impl(hl_engine* e, const char* name, const uint32_t* rows, uint64_t n, bool dev) {
+  return guard(e, [&] {
+    Relation& R = e->rels[e->find_or_fail(name)];
+    if (!R.edb) fail(HL_E_INVALID, "load into an IDB relation");
+    if (n == 0) return;
+    if (!rows) fail(HL_E_INVALID, "null rows");
+    const u64 row_bytes = u64(R.arity) * sizeof(u32);
+    const u64 total = R.n_raw + n;
+    if (total >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "EDB relation with 2^32 or more rows");
+    Buf nb;
+    nb.p = e->mem.alloc(total * row_bytes);
+    nb.bytes = total * row_bytes;
+    if (R.n_raw)
+      HIPCK(hipMemcpyAsync(nb.p, R.raw.p, R.n_raw * row_bytes, hipMemcpyDeviceToDevice, e->stream));
+    HIPCK(hipMemcpyAsync(static_cast<char*>(nb.p) + R.n_raw * row_bytes, rows, n * row_bytes,
+                         dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, e->stream));
+    if (!dev) e->sync();  // the caller may reuse its host buffer on return
+    e->drop(R.raw);
+    R.raw = nb;
+    R.n_raw = total;
+  });
+}
+
+int hl_load(hl_engine* e, const char* name, const uint32_t* rows, uint64_t n_rows) {
+  return load_impl(e, name, rows, n_rows, false);
+}
+
+int hl_load_device(hl_engine* e, const char* name, const uint32_t* d_rows, uint64_t n_rows) {
+  return load_impl(e, name, d_rows, n_rows, true);
+}
+
+int hl_index(hl_engine* e, const char* name, const uint32_t* cols, uint32_t ncols) {
+  return guard(e, [&] {
+    Relation& R = e->rels[e->find_or_fail(name)];
+    if (!cols || ncols != 1) fail(HL_E_UNSUPPORTED, "indexes on one column only");
+    if (cols[0] >= u32(R.arity)) fail(HL_E_INVALID, "column out of range");
+    R.idx[cols[0]].used = true;
+  });
+}
+
+int hl_program(hl_engine* e, const char* text) {
+  return guard(e, [&] {
+    if (!text) fail(HL_E_INVALID, "null program");
+    std::vector<Rule> parsed = e->parse(text);
+    std::vector<Rule> saved = e->rules;
+    e->rules.insert(e->rules.end(), parsed.begin(), parsed.end());
+    try {
+      e->build_plans();
+    } catch (...) {
+      e->rules = saved;
+      throw;
+    }
+  });
+}
+
+int hl_run(hl_engine* e, hl_stats* stats) {
+  return guard(e, [&] { e->run(stats); });
+}
+
+int hl_count(hl_engine* e, const char* name, uint64_t* n) {
+  return guard(e, [&] {
+    if (!n) fail(HL_E_INVALID, "null output");
+    Relation& R = e->rels[e->find_or_fail(name)];
+    if (!e->ran) fail(HL_E_STATE, "count before hl_run");
+    *n = R.n_full;
+  });
+}
+
+int hl_fetch(hl_engine* e, const char* name, uint32_t* rows, uint64_t cap_rows,
+             uint64_t* n_rows) {
+  return guard(e, [&] { e->fetch(name, rows, cap_rows, n_rows, false); });
+}
+
+int hl_fetch_device(hl_engine* e, const char* name, uint32_t* d_rows, uint64_t cap_rows,
+                    uint64_t* n_rows) {
+  return guard(e, [&] { e->fetch(name, d_rows, cap_rows, n_rows, true); });
+}
+
+int hl_iteration_counts(hl_engine* e, const char* name, int32_t which, uint64_t* counts,
+                        uint32_t cap, uint32_t* n_iters) {
+  return guard(e, [&] {
+    Relation& R = e->rels[e->find_or_fail(name)];
+    if (which != 0 && which != 1) fail(HL_E_INVALID, "which must be 0 or 1");
+    const std::vector<u64>& v = which == 0 ? R.delta_counts : R.new_counts;
+    if (n_iters) *n_iters = u32(v.size());
+    for (u32 i = 0; i < cap && i < v.size(); ++i) counts[i] = v[i];
+  });
+}
+
+const char* hl_last_error(hl_engine* e) { return e ? e->err.c_str() : "null engine"; }
+
+const char* hl_strerror(int code) {
+  switch (code) {
+    case HL_OK: return "ok";
+    case HL_E_INVALID: return "invalid argument";
+    case HL_E_NOMEM: return "out of device memory";
+    case HL_E_DEVICE: return "HIP runtime error";
+    case HL_E_STATE: return "call not allowed in this state";
+    case HL_E_CAPACITY: return "output buffer too small";
+    case HL_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown error";
+  }
+}
+
+// ------------------------------------------------------------ primitives
+
+int hl_sort_keys(hl_engine* e, void* d_keys, uint64_t n, uint32_t key_bytes, uint32_t bits) {
+  return guard(e, [&] {
+    if (!valid_key_bytes(key_bytes)) fail(HL_E_INVALID, "key_bytes must be 4 or 8");
+    if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "2^32 or more keys");
+    if (n <= 1) return;
+    if (!d_keys) fail(HL_E_INVALID, "null keys");
+    int b = bits ? int(bits) : int(8 * key_bytes);
+    if (b > int(8 * key_bytes)) fail(HL_E_INVALID, "bits exceed the key width");
+    e->reserve_grow(e->alt, n * key_bytes);
+    e->reserve(e->ws, hl::sort_workspace_bytes(n), hl::sort_workspace_bytes(n));
+    void* sorted = nullptr;
+    if (key_bytes == 4) {
+      u32* s = nullptr;
+      HIPCK(hl::radix_sort<u32>(static_cast<u32*>(d_keys), static_cast<u32*>(e->alt.p), n, b,
+                                e->ws.p, e->stream, &s));
+      sorted = s;
+    } else {
+      u64* s = nullptr;
+      HIPCK(hl::radix_sort<u64>(static_cast<u64*>(d_keys), static_cast<u64*>(e->alt.p), n, b,
+                                e->ws.p, e->stream, &s));
+      sorted = s;
+    }
+    if (sorted != d_keys)
+      HIPCK(hipMemcpyAsync(d_keys, sorted, n * key_bytes, hipMemcpyDeviceToDevice, e->stream));
+    e->sync();
+  });
+}
+
+int hl_unique_diff(hl_engine* e, const void* d_sorted, uint64_t n, const void* d_full,
+                   uint64_t n_full, void* d_out, uint64_t* n_out, uint64_t* n_unique,
+                   uint32_t key_bytes) {
+  return guard(e, [&] {
+    if (!valid_key_bytes(key_bytes)) fail(HL_E_INVALID, "key_bytes must be 4 or 8");
+    if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "2^32 or more keys");
+    if ((n && (!d_sorted || !d_out)) || (n_full && !d_full)) fail(HL_E_INVALID, "null buffer");
+    e->reserve_grow(e->alt, std::max<u64>(n, 1) * key_bytes);
+    e->reserve(e->ws, hl::unique_diff_workspace_bytes(n), hl::unique_diff_workspace_bytes(n));
+    if (key_bytes == 4)
+      HIPCK(hl::unique_diff<u32>(static_cast<const u32*>(d_sorted), n,
+                                 static_cast<const u32*>(d_full), n_full,
+                                 static_cast<u32*>(e->alt.p), static_cast<u32*>(d_out),
+                                 e->d_small, e->ws.p, e->stream));
+    else
+      HIPCK(hl::unique_diff<u64>(static_cast<const u64*>(d_sorted), n,
+                                 static_cast<const u64*>(d_full), n_full,
+                                 static_cast<u64*>(e->alt.p), static_cast<u64*>(d_out),
+                                 e->d_small, e->ws.p, e->stream));
+    HIPCK(hipMemcpyAsync(e->h_small, e->d_small, 2 * sizeof(u64), hipMemcpyDeviceToHost,
+                         e->stream));
+    e->sync();
+    if (n_out) *n_out = e->h_small[0];
+    if (n_unique) *n_unique = e->h_small[1];
+  });
+}
+
+int hl_merge(hl_engine* e, const void* d_a, uint64_t na, const void* d_b, uint64_t nb,
+             void* d_out, uint32_t key_bytes) {
+  return guard(e, [&] {
+    if (!valid_key_bytes(key_bytes)) fail(HL_E_INVALID, "key_bytes must be 4 or 8");
+    if ((na && !d_a) || (nb && !d_b) || (na + nb && !d_out)) fail(HL_E_INVALID, "null buffer");
+    e->reserve(e->ws, hl::merge_workspace_bytes(na, nb), hl::merge_workspace_bytes(na, nb));
+    if (key_bytes == 4)
+      HIPCK(hl::merge<u32>(static_cast<const u32*>(d_a), na, static_cast<const u32*>(d_b), nb,
+                           static_cast<u32*>(d_out), e->ws.p, e->stream));
+    else
+      HIPCK(hl::merge<u64>(static_cast<const u64*>(d_a), na, static_cast<const u64*>(d_b), nb,
+                           static_cast<u64*>(d_out), e->ws.p, e->stream));
+    e->sync();
+  });
+}
+
+int hl_hisa_query(hl_engine* e, const void* d_keys, uint64_t n, uint32_t key_bytes,
+                  uint32_t shift, const uint32_t* d_queries, uint64_t nq, uint64_t* d_start,
+                  uint32_t* d_len, uint64_t* n_runs) {
+  return guard(e, [&] {
+    if (!valid_key_bytes(key_bytes)) fail(HL_E_INVALID, "key_bytes must be 4 or 8");
+    if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "2^32 or more keys");
+    if (shift >= 8 * key_bytes) fail(HL_E_INVALID, "shift out of range");
+    if ((n && !d_keys) || (nq && (!d_queries || !d_start || !d_len)))
+      fail(HL_E_INVALID, "null buffer");
+    if (key_bytes == 4)
+      HIPCK(hl::hisa_count_runs<u32>(static_cast<const u32*>(d_keys), n, int(shift), e->d_small,
+                                     e->stream));
+    else
+      HIPCK(hl::hisa_count_runs<u64>(static_cast<const u64*>(d_keys), n, int(shift), e->d_small,
+                                     e->stream));
+    HIPCK(hipMemcpyAsync(e->h_small, e->d_small, sizeof(u64), hipMemcpyDeviceToHost, e->stream));
+    e->sync();
+    const u64 runs = e->h_small[0];
+    if (n_runs) *n_runs = runs;
+    u64 cap = std::max<u64>(u64(std::ceil(double(runs) / e->load_factor)), runs + 1);
+    cap = std::max<u64>(cap, 16);
+    Buf table;
+    table.p = e->mem.alloc(cap * sizeof(Slot));
+    table.bytes = cap * sizeof(Slot);
+    try {
+      HIPCK(hl::fill_zero(table.p, cap * sizeof(Slot), e->stream));
+      if (key_bytes == 4)
+        HIPCK(hl::hisa_build<u32>(static_cast<const u32*>(d_keys), n, int(shift),
+                                  static_cast<Slot*>(table.p), cap, e->stream));
+      else
+        HIPCK(hl::hisa_build<u64>(static_cast<const u64*>(d_keys), n, int(shift),
+                                  static_cast<Slot*>(table.p), cap, e->stream));
+      HIPCK(hl::hisa_probe(static_cast<Slot*>(table.p), cap, d_queries, nq, d_start, d_len,
+                           e->stream));
+      e->sync();
+    } catch (...) {
+      e->drop(table);
+      throw;
+    }
+    e->drop(table);
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,242 @@
+// Binary join of an outer pair array against an inner HISA (Section 5.1,
+// "Implementing Joins", Algorithm 3): every outer tuple hashes its join
+// column, finds the start of the matching run of the inner sorted array,
+// and scans the run, emitting one projected (and filtered) pair per inner
+// tuple.  Multi-atom bodies run one such join per atom with the
+// intermediate result materialised (Section 5.2).
+//
+// GPU shape.  Algorithm 3 gives one thread per outer tuple, so a hub key
+// with a long run keeps one lane busy while its wave idles (the imbalance
+// Section 5.2 describes for nested joins).  Here the join is three passes:
+//   probe   one lane per outer tuple: (run start, run length);
+//   scan    exclusive prefix of the lengths = output offsets;
+//   expand  output positions are split evenly over workgroups by a merge
+//           path of the offsets against the output index (load-balanced
+//           search), so every lane emits about the same number of pairs
+//           whatever the run lengths, with coalesced reads of each run and
+//           coalesced writes.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace hl {
+
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kItems = 8;
+constexpr u64 kTile = u64(kNT) * kItems;
+
+__device__ __forceinline__ bool hisa_find(const Slot* table, u64 cap, u32 key, u32& start,
+                                          u32& len) {
+  u64 slot = slot_of(key, cap);
+  for (u64 probe = 0; probe < cap; ++probe) {
+    const Slot sl = table[slot];
+    if (sl.w0 == 0) return false;
+    if (u32(sl.w0) == key) {
+      len = u32(sl.w0 >> 32);
+      start = u32(sl.w1);
+      return true;
+    }
+    slot = (slot + 1 == cap) ? 0 : slot + 1;
+  }
+  return false;
+}
+
+template <typename K>
+__device__ __forceinline__ K pick(int src, K c0, K c1, K o) {
+  return src == 0 ? c0 : (src == 1 ? c1 : o);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kNT) void probe_kernel(const K* outer, u64 n, int outer_col, int w,
+                                                    const Slot* table, u64 cap, u32* start,
+                                                    u32* len) {
+  const u64 i = u64(blockIdx.x) * kNT + threadIdx.x;
+  if (i >= n) return;
+  const K k = outer[i];
+  const K mask = (K(1) << w) - 1;
+  const u32 jc = outer_col == 0 ? u32(k >> w) : u32(k & mask);
+  u32 st = 0, ln = 0;
+  if (!hisa_find(table, cap, jc, st, ln)) ln = 0;
+  start[i] = st;
+  len[i] = ln;
+}
+
+// Merged order of outer tuple i (key off[i]) and output j (key j): the
+// outer tuple comes first when off[i] <= j.  Returns how many outer tuples
+// are among the first `diag` merged items.
+__device__ __forceinline__ u64 lbs_path(const u64* off, u64 na, u64 nb, u64 diag) {
+  u64 lo = diag > nb ? diag - nb : 0;
+  u64 hi = diag < na ? diag : na;
+  while (lo < hi) {
+    u64 mid = (lo + hi) >> 1;
+    if (off[mid] <= diag - 1 - mid) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void lbs_partition_kernel(const u64* off, u64 na, u64 nb, u64* parts, u64 nparts) {
+  const u64 t = u64(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nparts) return;
+  u64 diag = t * kTile;
+  if (diag > na + nb) diag = na + nb;
+  parts[t] = lbs_path(off, na, nb, diag);
+}
+
+template <typename K>
+__device__ __forceinline__ void emit(K* out, u64 j, K v, bool keep, bool filtered, u64* cursor) {
+  if (!filtered) {
+    if (keep) out[j] = v;
+    return;
+  }
+  // wave-level compaction: one atomic per wave and round
+  const u64 bal = ballot(keep);
+  if (bal == 0) return;
+  u64 base = 0;
+  if (lane_id() == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(cursor),
+                                       (unsigned long long)popc(bal));
+  base = __shfl(base, 0, kWave);
+  if (keep) out[base + popc(bal & lanemask_lt())] = v;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer, const u64* off,
+                                                     const u32* start, const K* inner,
+                                                     u64 total, JoinSpec js, const u64* parts,
+                                                     K* out, u64* cursor) {
+  __shared__ u64 s_off[kTile];
+  __shared__ u32 s_owner[kTile];
+  const u32 tile = blockIdx.x;
+  const u64 d0 = u64(tile) * kTile;
+  const u64 dend = n_outer + total;
+  const u64 d1 = (d0 + kTile) < dend ? (d0 + kTile) : dend;
+  const u64 a0 = parts[tile], a1 = parts[tile + 1];
+  const u64 b0 = d0 - a0, b1 = d1 - a1;
+  const u32 la = u32(a1 - a0), lb = u32(b1 - b0);
+  for (u32 k = threadIdx.x; k < la; k += kNT) s_off[k] = off[a0 + k];
+  __syncthreads();
+  // serial merge of this thread's slice of the tile's merged sequence
+  {
+    const u32 tot = la + lb;
+    u32 diag = threadIdx.x * kItems;
+    if (diag > tot) diag = tot;
+    u32 lo = diag > lb ? diag - lb : 0;
+    u32 hi = diag < la ? diag : la;
+    while (lo < hi) {
+      u32 mid = (lo + hi) >> 1;
+      if (s_off[mid] <= b0 + (diag - 1 - mid)) lo = mid + 1;
+      else hi = mid;
+    }
+    u32 ai = lo, bi = diag - lo;
+    for (int k = 0; k < kItems && diag + k < tot; ++k) {
+      if (ai < la && (bi >= lb || s_off[ai] <= b0 + bi)) {
+        ++ai;
+      } else {
+        s_owner[bi] = u32(a0 + ai - 1);  // global index of the owning outer tuple
+        ++bi;
+      }
+    }
+  }
+  __syncthreads();
+  const bool filtered = js.fa >= 0;
+  const K mask = (K(1) << js.w) - 1;
+  for (u32 kk = 0; kk < lb; kk += kNT) {
+    const u32 k = kk + threadIdx.x;
+    bool keep = false;
+    K v = 0;
+    const u64 j = b0 + k;
+    if (k < lb) {
+      const u32 i = s_owner[k];
+      const u64 oi = (u64(i) >= a0) ? s_off[u64(i) - a0] : off[i];
+      const u64 pos = u64(start[i]) + (j - oi);
+      const K ok = outer[i];
+      const K c0 = ok >> js.w, c1 = ok & mask;
+      const K o = inner[pos] & mask;
+      const K x = pick(js.src0, c0, c1, o), y = pick(js.src1, c0, c1, o);
+      v = (x << js.w) | y;
+      keep = !filtered || pick(js.fa, c0, c1, o) != pick(js.fb, c0, c1, o);
+    }
+    emit(out, j, v, keep, filtered, cursor);
+  }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kNT) void project_kernel(const K* in, u64 n, JoinSpec js, K* out,
+                                                      u64* cursor) {
+  const bool filtered = js.fa >= 0;
+  const K mask = (K(1) << js.w) - 1;
+  const u64 stride = u64(gridDim.x) * kNT;
+  // the loop bound is uniform per wave so the compaction ballot sees every lane
+  for (u64 base = u64(blockIdx.x) * kNT; base < n; base += stride) {
+    const u64 i = base + threadIdx.x;
+    bool keep = false;
+    K v = 0;
+    if (i < n) {
+      const K k = in[i];
+      const K c0 = k >> js.w, c1 = k & mask;
+      const K x = pick(js.src0, c0, c1, K(0)), y = pick(js.src1, c0, c1, K(0));
+      v = (x << js.w) | y;
+      keep = !filtered || pick(js.fa, c0, c1, K(0)) != pick(js.fb, c0, c1, K(0));
+    }
+    emit(out, i, v, keep, filtered, cursor);
+  }
+}
+
+u64 tiles_of(u64 n) { return (n + kTile - 1) / kTile; }
+
+}  // namespace
+
+template <typename K>
+hipError_t join_probe(const K* outer, u64 n, const JoinSpec& js, const Slot* table, u64 cap,
+                      u32* start, u32* len, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  if (cap == 0 || cap > (u64(1) << 32) || js.outer_col < 0 || js.outer_col > 1)
+    return hipErrorInvalidValue;
+  const u64 blocks = (n + kNT - 1) / kNT;
+  if (blocks >= (u64(1) << 31)) return hipErrorInvalidValue;
+  probe_kernel<K><<<dim3(u32(blocks)), kNT, 0, s>>>(outer, n, js.outer_col, js.w, table, cap,
+                                                    start, len);
+  return hipGetLastError();
+}
+
+u64 join_parts(u64 n_outer, u64 total) { return tiles_of(n_outer + total) + 1; }
+
+template <typename K>
+hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* start,
+                       const K* inner, u64 total, const JoinSpec& js, u64* parts, K* out,
+                       u64* cursor, hipStream_t s) {
+  if (total == 0) return hipSuccess;
+  if (n_outer >= (u64(1) << 32)) return hipErrorInvalidValue;
+  const u64 nt = tiles_of(n_outer + total);
+  if (nt >= (u64(1) << 31)) return hipErrorInvalidValue;
+  const u64 nparts = nt + 1;
+  lbs_partition_kernel<<<dim3(u32((nparts + 255) / 256)), 256, 0, s>>>(off, n_outer, total,
+                                                                       parts, nparts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  expand_kernel<K><<<dim3(u32(nt)), kNT, 0, s>>>(outer, n_outer, off, start, inner, total, js,
+                                                 parts, out, cursor);
+  return hipGetLastError();
+}
+
+template <typename K>
+hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  u64 blocks = (n + kNT - 1) / kNT;
+  if (blocks > 65536) blocks = 65536;
+  project_kernel<K><<<dim3(u32(blocks)), kNT, 0, s>>>(in, n, js, out, cursor);
+  return hipGetLastError();
+}
+
+#define HL_INSTANTIATE(K)                                                                     \
+  template hipError_t join_probe<K>(const K*, u64, const JoinSpec&, const Slot*, u64, u32*,  \
+                                    u32*, hipStream_t);                                       \
+  template hipError_t join_expand<K>(const K*, u64, const u64*, const u32*, const K*, u64,  \
+                                     const JoinSpec&, u64*, K*, u64*, hipStream_t);           \
+  template hipError_t project<K>(const K*, u64, const JoinSpec&, K*, u64*, hipStream_t);
+HL_INSTANTIATE(u32)
+HL_INSTANTIATE(u64)
+#undef HL_INSTANTIATE
+
+}  // namespace hl

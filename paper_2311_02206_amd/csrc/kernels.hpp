@@ -1,0 +1,106 @@
+// Host-side launchers of the gfx950 kernels.  Every launcher validates its
+// sizes before it launches, enqueues on `s`, and returns the first HIP
+// error.  Workspaces are caller-provided device memory of at least the
+// size the matching *_workspace_bytes() function returns; nothing here
+// allocates.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hl {
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+// One slot of the HISA hash index.  w0 = (run length << 32) | join key;
+// w0 == 0 marks an empty slot (every stored run has length >= 1, so no
+// stored slot is 0).  w1 = position of the run's first tuple in the
+// sorted array.
+struct alignas(16) Slot {
+  u64 w0;
+  u64 w1;
+};
+
+inline u64 align_up(u64 x, u64 a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------- scan
+u64 scan_workspace_bytes(u64 n);
+// Exclusive prefix sum of u32 values into u64 offsets; *d_total (device)
+// receives the sum.  In place (out aliasing in) is not allowed.
+hipError_t scan_u32_u64(const u32* in, u64 n, u64* out, u64* d_total, void* ws, hipStream_t s);
+
+// ---------------------------------------------------------- radix sort
+u64 sort_workspace_bytes(u64 n);
+// LSD radix sort of the low `bits` bits of n keys.  Ping-pongs between
+// `keys` and `alt`; *sorted receives whichever holds the result (the other
+// one is free afterwards).  n must be below 2^32.
+template <typename K>
+hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted);
+
+// --------------------------------------------- unique + set difference
+u64 unique_diff_workspace_bytes(u64 n);
+// out = unique(sorted) \ full.  Both inputs sorted ascending; full has no
+// duplicates.  `tmp` holds n keys.  d_counts[0] = |out|, d_counts[1] =
+// number of distinct keys in `sorted`.  n must be below 2^32.
+template <typename K>
+hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
+                       u64* d_counts, void* ws, hipStream_t s);
+
+// --------------------------------------------------------------- merge
+u64 merge_workspace_bytes(u64 na, u64 nb);
+// out = merge of two ascending arrays (ties take a first).
+template <typename K>
+hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipStream_t s);
+
+// ---------------------------------------------------------------- HISA
+// Counts the runs of equal join key (key >> shift) of a sorted array.
+template <typename K>
+hipError_t hisa_count_runs(const K* keys, u64 n, int shift, u64* d_runs, hipStream_t s);
+// Inserts every run into an open-addressing table of `cap` slots, which
+// must exceed the number of runs and start zeroed (see fill_zero).
+template <typename K>
+hipError_t hisa_build(const K* keys, u64 n, int shift, Slot* table, u64 cap, hipStream_t s);
+// Looks up nq join keys; len 0 means absent.
+hipError_t hisa_probe(const Slot* table, u64 cap, const u32* q, u64 nq, u64* start, u32* len,
+                      hipStream_t s);
+
+// ---------------------------------------------------------------- misc
+hipError_t fill_zero(void* p, u64 bytes, hipStream_t s);
+// *d_max = max(*d_max, v[i]); *d_max must be initialised.
+hipError_t max_u32(const u32* v, u64 n, u32* d_max, hipStream_t s);
+// Row-major uint32 pairs -> keys (c0 << w) | c1; arity 1 packs (c0 << w).
+template <typename K>
+hipError_t pack_rows(const u32* rows, u64 n, int arity, int w, K* out, hipStream_t s);
+// (c0 << w) | c1  ->  (c1 << w) | c0
+template <typename K>
+hipError_t swap_cols(const K* in, u64 n, int w, K* out, hipStream_t s);
+template <typename K>
+hipError_t unpack_rows(const K* keys, u64 n, int arity, int w, u32* rows, hipStream_t s);
+
+// ---------------------------------------------------------------- join
+// Values of the current pair (c0, c1) and of the inner tuple's non-join
+// column are numbered 0, 1, 2.  The output pair is (v[src0], v[src1]); a
+// filter (fa >= 0) keeps it only when v[fa] != v[fb].
+struct JoinSpec {
+  int outer_col;  // which column of the outer pair is the join key
+  int src0, src1;
+  int fa, fb;
+  int w;  // id bits of a column
+};
+
+template <typename K>
+hipError_t join_probe(const K* outer, u64 n, const JoinSpec& js, const Slot* table, u64 cap,
+                      u32* start, u32* len, hipStream_t s);
+u64 join_parts(u64 n_outer, u64 total);  // entries of the partition array
+// Expands every (outer, inner run) pair.  Without a filter, output j goes
+// to out[j]; with one, survivors are appended at *cursor (device, u64).
+template <typename K>
+hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* start,
+                       const K* inner, u64 total, const JoinSpec& js, u64* parts, K* out,
+                       u64* cursor, hipStream_t s);
+// A rule body of one atom: projects (and filters) every outer pair.
+template <typename K>
+hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, hipStream_t s);
+
+}  // namespace hl

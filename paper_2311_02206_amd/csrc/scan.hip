@@ -1,0 +1,101 @@
+// Device-wide exclusive prefix sum: reduce tiles, scan the tile sums
+// (recursively), then scan each tile with its offset.  Used for join output
+// offsets and for the digit offsets of the radix sort.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace hl {
+
+namespace {
+
+constexpr int kNT = 256;
+constexpr int kItems = 8;
+constexpr u64 kTile = kNT * kItems;
+
+template <typename Tin>
+__global__ __launch_bounds__(kNT) void scan_reduce_kernel(const Tin* in, u64 n, u64* sums) {
+  __shared__ u64 lds[kNT / kWave];
+  const u64 base = u64(blockIdx.x) * kTile;
+  u64 s = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    u64 i = base + u64(j) * kNT + threadIdx.x;
+    if (i < n) s += u64(in[i]);
+  }
+  s = block_sum<kNT>(s, lds);
+  if (threadIdx.x == 0) sums[blockIdx.x] = s;
+}
+
+// offsets == nullptr: a single tile starting at 0.
+template <typename Tin>
+__global__ __launch_bounds__(kNT) void scan_down_kernel(const Tin* in, u64 n, const u64* offsets,
+                                                        u64* out, u64* d_total) {
+  __shared__ u64 lds[kNT / kWave];
+  const u64 base = u64(blockIdx.x) * kTile;
+  u64 carry = offsets ? offsets[blockIdx.x] : 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) {
+    u64 i = base + u64(j) * kNT + threadIdx.x;
+    u64 v = i < n ? u64(in[i]) : 0;
+    u64 tot;
+    u64 ex = block_exclusive_scan<kNT>(v, lds, tot);
+    if (i < n) out[i] = carry + ex;
+    carry += tot;
+  }
+  if (d_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *d_total = carry;
+}
+
+__global__ void set_u64_kernel(u64* p, u64 v) { *p = v; }
+
+u64 tiles_of(u64 n) { return (n + kTile - 1) / kTile; }
+
+template <typename Tin>
+hipError_t scan_impl(const Tin* in, u64 n, u64* out, u64* d_total, char* ws, hipStream_t s) {
+  if (n == 0) {
+    if (d_total) set_u64_kernel<<<1, 1, 0, s>>>(d_total, 0);
+    return hipGetLastError();
+  }
+  u64 nt = tiles_of(n);
+  if (nt == 1) {
+    scan_down_kernel<Tin><<<1, kNT, 0, s>>>(in, n, nullptr, out, d_total);
+    return hipGetLastError();
+  }
+  if (nt > 0x7fffffffULL) return hipErrorInvalidValue;
+  u64* sums = reinterpret_cast<u64*>(ws);
+  char* rest = ws + align_up(nt * sizeof(u64), 256);
+  scan_reduce_kernel<Tin><<<dim3(u32(nt)), kNT, 0, s>>>(in, n, sums);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  // scan the tile sums in place (each element is read before it is written
+  // by the same thread, and the reduce pass has finished before)
+  u64* sums_scanned = reinterpret_cast<u64*>(rest);
+  rest += align_up(nt * sizeof(u64), 256);
+  e = scan_impl<u64>(sums, nt, sums_scanned, nullptr, rest, s);
+  if (e != hipSuccess) return e;
+  scan_down_kernel<Tin><<<dim3(u32(nt)), kNT, 0, s>>>(in, n, sums_scanned, out, d_total);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+u64 scan_workspace_bytes(u64 n) {
+  u64 total = 0;
+  u64 m = n;
+  while (tiles_of(m) > 1) {
+    u64 nt = tiles_of(m);
+    total += 2 * align_up(nt * sizeof(u64), 256);
+    m = nt;
+  }
+  return total + 256;
+}
+
+hipError_t scan_u32_u64(const u32* in, u64 n, u64* out, u64* d_total, void* ws, hipStream_t s) {
+  return scan_impl<u32>(in, n, out, d_total, static_cast<char*>(ws), s);
+}
+
+// u64 -> u64 scan, used internally by other launchers.
+hipError_t scan_u64_u64(const u64* in, u64 n, u64* out, u64* d_total, void* ws, hipStream_t s) {
+  return scan_impl<u64>(in, n, out, d_total, static_cast<char*>(ws), s);
+}
+
+}  // namespace hl

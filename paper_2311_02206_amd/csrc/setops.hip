@@ -1,0 +1,259 @@
+// Set operations on sorted key arrays.
+//
+// unique_diff: populating delta (Section 5.1, "Populating delta"): the
+// sorted new tuples are deduplicated by comparing each with its neighbour
+// (Section 3.2, "Deduplication") and every tuple already in full is
+// removed, so delta and full stay disjoint.  Membership in full is a binary
+// search restricted to the slice of full spanned by the tile, staged in
+// LDS when it is small.
+//
+// merge: full := full U delta by merge path (Section 3.2, "Merge
+// operation", after Green, McColl and Bader 2012): a diagonal search splits
+// the output into equal tiles, each tile merges its two input slices in
+// LDS and writes its output with coalesced stores.
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace hl {
+
+hipError_t scan_u64_u64(const u64* in, u64 n, u64* out, u64* d_total, void* ws, hipStream_t s);
+
+namespace {
+
+// ------------------------------------------------------------ unique_diff
+
+constexpr int kUdNT = 256;
+constexpr int kUdItems = 16;
+constexpr u64 kUdTile = u64(kUdNT) * kUdItems;
+constexpr u64 kUdStage = 4096;  // keys of full staged in LDS per tile
+
+template <typename K>
+__device__ __forceinline__ u64 lower_bound(const K* a, u64 lo, u64 hi, K x) {
+  while (lo < hi) {
+    u64 mid = (lo + hi) >> 1;
+    if (a[mid] < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename K>
+__device__ __forceinline__ u64 upper_bound(const K* a, u64 lo, u64 hi, K x) {
+  while (lo < hi) {
+    u64 mid = (lo + hi) >> 1;
+    if (!(x < a[mid])) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, const K* full,
+                                                          u64 nf, K* tmp, u32* tile_counts,
+                                                          u64* d_unique) {
+  __shared__ u64 range[2];
+  __shared__ u32 wsum[kUdNT / kWave];
+  __shared__ u64 wsum64[kUdNT / kWave];
+  __shared__ K staged[kUdStage];
+  const u32 tile = blockIdx.x;
+  const u64 base = u64(tile) * kUdTile;
+  const u64 cnt = (n - base) < kUdTile ? (n - base) : kUdTile;
+  if (threadIdx.x == 0) {
+    range[0] = lower_bound(full, 0, nf, cand[base]);
+    range[1] = upper_bound(full, range[0], nf, cand[base + cnt - 1]);
+  }
+  __syncthreads();
+  const u64 lo = range[0], hi = range[1];
+  const u64 m = hi - lo;
+  const bool in_lds = m <= kUdStage;
+  if (in_lds) {
+    for (u64 k = threadIdx.x; k < m; k += kUdNT) staged[k] = full[lo + k];
+  }
+  __syncthreads();
+  u32 carry = 0;
+  u64 uniq = 0;
+  for (int j = 0; j < kUdItems; ++j) {
+    const u64 r = u64(j) * kUdNT + threadIdx.x;
+    const u64 i = base + r;
+    const bool valid = r < cnt;
+    bool keep = false;
+    K c = 0;
+    if (valid) {
+      c = cand[i];
+      bool first = (i == 0) || (cand[i - 1] != c);
+      if (first) {
+        ++uniq;
+        bool member;
+        if (in_lds) {
+          u64 p = lower_bound(staged, 0, m, c);
+          member = p < m && staged[p] == c;
+        } else {
+          u64 p = lower_bound(full, lo, hi, c);
+          member = p < hi && full[p] == c;
+        }
+        keep = !member;
+      }
+    }
+    u32 tot;
+    u32 pos = block_exclusive_scan<kUdNT>(keep ? 1u : 0u, wsum, tot);
+    if (keep) tmp[base + carry + pos] = c;
+    carry += tot;
+  }
+  uniq = block_sum<kUdNT>(uniq, wsum64);
+  if (threadIdx.x == 0) {
+    tile_counts[tile] = carry;
+    atomicAdd(reinterpret_cast<unsigned long long*>(d_unique), (unsigned long long)uniq);
+  }
+}
+
+template <typename K>
+__global__ __launch_bounds__(kUdNT) void ud_gather_kernel(const K* tmp, const u32* tile_counts,
+                                                          const u64* tile_off, K* out) {
+  const u32 tile = blockIdx.x;
+  const u32 c = tile_counts[tile];
+  const u64 src = u64(tile) * kUdTile;
+  const u64 dst = tile_off[tile];
+  for (u32 k = threadIdx.x; k < c; k += kUdNT) out[dst + k] = tmp[src + k];
+}
+
+__global__ void zero_u64x2_kernel(u64* p) {
+  p[0] = 0;
+  p[1] = 0;
+}
+
+// ----------------------------------------------------------------- merge
+
+constexpr int kMgNT = 256;
+constexpr int kMgItems = 8;
+constexpr u64 kMgTile = u64(kMgNT) * kMgItems;
+
+// Number of elements of `a` among the first `diag` outputs of the merge
+// (ties: a first).
+template <typename K>
+__device__ __forceinline__ u64 merge_path(const K* a, u64 na, const K* b, u64 nb, u64 diag) {
+  u64 lo = diag > nb ? diag - nb : 0;
+  u64 hi = diag < na ? diag : na;
+  while (lo < hi) {
+    u64 mid = (lo + hi) >> 1;
+    if (!(b[diag - 1 - mid] < a[mid])) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename K>
+__global__ void merge_partition_kernel(const K* a, u64 na, const K* b, u64 nb, u64* parts,
+                                       u64 nparts) {
+  u64 t = u64(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= nparts) return;
+  u64 diag = t * kMgTile;
+  if (diag > na + nb) diag = na + nb;
+  parts[t] = merge_path(a, na, b, nb, diag);
+}
+
+template <typename K>
+__global__ __launch_bounds__(kMgNT) void merge_kernel(const K* a, u64 na, const K* b, u64 nb,
+                                                      const u64* parts, K* out) {
+  __shared__ K s[kMgTile];
+  const u32 tile = xcd_tile(blockIdx.x, gridDim.x);
+  const u64 d0 = u64(tile) * kMgTile;
+  const u64 d1 = (d0 + kMgTile) < (na + nb) ? (d0 + kMgTile) : (na + nb);
+  const u64 a0 = parts[tile], a1 = parts[tile + 1];
+  const u64 b0 = d0 - a0, b1 = d1 - a1;
+  const u32 la = u32(a1 - a0), lb = u32(b1 - b0);
+  for (u32 k = threadIdx.x; k < la; k += kMgNT) s[k] = a[a0 + k];
+  for (u32 k = threadIdx.x; k < lb; k += kMgNT) s[la + k] = b[b0 + k];
+  __syncthreads();
+  const u32 total = la + lb;
+  u32 diag = threadIdx.x * kMgItems;
+  if (diag > total) diag = total;
+  u32 ai = u32(merge_path(s, la, s + la, lb, diag));
+  u32 bi = diag - ai;
+  K r[kMgItems];
+#pragma unroll
+  for (int k = 0; k < kMgItems; ++k) {
+    K v = 0;
+    if (diag + k < total) {  // then ai < la or bi < lb
+      bool take_a = (bi >= lb) || (ai < la && !(s[la + bi] < s[ai]));
+      if (take_a) {
+        v = s[ai];
+        ++ai;
+      } else {
+        v = s[la + bi];
+        ++bi;
+      }
+    }
+    r[k] = v;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kMgItems; ++k) {
+    u32 o = threadIdx.x * kMgItems + k;
+    if (o < total) s[o] = r[k];
+  }
+  __syncthreads();
+  for (u32 k = threadIdx.x; k < total; k += kMgNT) out[d0 + k] = s[k];
+}
+
+u64 ud_tiles(u64 n) { return (n + kUdTile - 1) / kUdTile; }
+u64 mg_tiles(u64 n) { return (n + kMgTile - 1) / kMgTile; }
+
+}  // namespace
+
+u64 unique_diff_workspace_bytes(u64 n) {
+  u64 nt = ud_tiles(n);
+  return align_up(nt * sizeof(u32), 256) + align_up(nt * sizeof(u64), 256) +
+         scan_workspace_bytes(nt);
+}
+
+template <typename K>
+hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
+                       u64* d_counts, void* ws, hipStream_t s) {
+  zero_u64x2_kernel<<<1, 1, 0, s>>>(d_counts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || n == 0) return e;
+  if (n >= (u64(1) << 32)) return hipErrorInvalidValue;
+  const u64 nt = ud_tiles(n);
+  char* p = static_cast<char*>(ws);
+  u32* tile_counts = reinterpret_cast<u32*>(p);
+  p += align_up(nt * sizeof(u32), 256);
+  u64* tile_off = reinterpret_cast<u64*>(p);
+  p += align_up(nt * sizeof(u64), 256);
+  ud_select_kernel<K><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
+                                                      d_counts + 1);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  e = scan_u32_u64(tile_counts, nt, tile_off, d_counts, p, s);
+  if (e != hipSuccess) return e;
+  ud_gather_kernel<K><<<dim3(u32(nt)), kUdNT, 0, s>>>(tmp, tile_counts, tile_off, out);
+  return hipGetLastError();
+}
+
+u64 merge_workspace_bytes(u64 na, u64 nb) {
+  return align_up((mg_tiles(na + nb) + 1) * sizeof(u64), 256);
+}
+
+template <typename K>
+hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipStream_t s) {
+  const u64 n = na + nb;
+  if (n == 0) return hipSuccess;
+  const u64 nt = mg_tiles(n);
+  if (nt >= (u64(1) << 31)) return hipErrorInvalidValue;
+  u64* parts = static_cast<u64*>(ws);
+  const u64 nparts = nt + 1;
+  merge_partition_kernel<K><<<dim3(u32((nparts + 255) / 256)), 256, 0, s>>>(a, na, b, nb, parts,
+                                                                           nparts);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  merge_kernel<K><<<dim3(u32(nt)), kMgNT, 0, s>>>(a, na, b, nb, parts, out);
+  return hipGetLastError();
+}
+
+template hipError_t unique_diff<u32>(const u32*, u64, const u32*, u64, u32*, u32*, u64*, void*,
+                                     hipStream_t);
+template hipError_t unique_diff<u64>(const u64*, u64, const u64*, u64, u64*, u64*, u64*, void*,
+                                     hipStream_t);
+template hipError_t merge<u32>(const u32*, u64, const u32*, u64, u32*, void*, hipStream_t);
+template hipError_t merge<u64>(const u64*, u64, const u64*, u64, u64*, void*, hipStream_t);
+
+}  // namespace hl

@@ -1,0 +1,317 @@
+"""Python binding of libhisalog (include/hisalog.h): argument marshalling only.
+
+Every step of the fixpoint runs in the library's gfx950 kernels.  PyTorch
+provides device memory (tensors passed to the ``*_device`` calls and the
+primitives) and the stream the engine enqueues on.  There is no fallback:
+if the library has not been built, importing the binding raises.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhisalog.so")
+
+HL_OK = 0
+HL_E_INVALID = -1
+HL_E_NOMEM = -2
+HL_E_DEVICE = -3
+HL_E_STATE = -4
+HL_E_CAPACITY = -5
+HL_E_UNSUPPORTED = -6
+HL_FLAG_NO_EBM = 0x1
+PHASES = ("index_edb", "join", "sort", "diff", "merge", "index")
+
+# Symbols of include/hisalog.h, in declaration order.
+EXPORTS = (
+    "hl_options_init", "hl_create", "hl_destroy", "hl_declare", "hl_load", "hl_load_device",
+    "hl_index", "hl_program", "hl_run", "hl_count", "hl_fetch", "hl_fetch_device",
+    "hl_iteration_counts", "hl_last_error", "hl_strerror", "hl_sort_keys", "hl_unique_diff",
+    "hl_merge", "hl_hisa_query",
+)
+
+
+class HlError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32), ("flags", ctypes.c_uint32), ("arena", ctypes.c_void_p),
+        ("arena_bytes", ctypes.c_uint64), ("hbm_budget_bytes", ctypes.c_uint64),
+        ("stream", ctypes.c_void_p), ("ebm_k", ctypes.c_float),
+        ("hash_load_factor", ctypes.c_float), ("reserved", ctypes.c_uint32 * 8),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", ctypes.c_uint32), ("key_bytes", ctypes.c_uint32),
+        ("id_bits", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+        ("idb_tuples", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
+        ("peak_bytes", ctypes.c_uint64), ("allocations", ctypes.c_uint64),
+        ("ebm_reuses", ctypes.c_uint64), ("seconds", ctypes.c_double),
+        ("phase_ms", ctypes.c_double * len(PHASES)),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("phase_ms", "reserved0")}
+        d["phase_ms"] = dict(zip(PHASES, list(self.phase_ms)))
+        return d
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libhisalog.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python -m paper_2311_02206_amd.build` (hipcc, gfx950)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, cp, u64, u32, i32 = (ctypes.c_void_p, ctypes.c_char_p, ctypes.c_uint64,
+                             ctypes.c_uint32, ctypes.c_int32)
+    pu64, pu32 = ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32)
+    sig = {
+        "hl_options_init": [ctypes.POINTER(Options)],
+        "hl_create": [ctypes.POINTER(Options), ctypes.POINTER(vp)],
+        "hl_destroy": [vp],
+        "hl_declare": [vp, cp, u32, i32],
+        "hl_load": [vp, cp, vp, u64],
+        "hl_load_device": [vp, cp, vp, u64],
+        "hl_index": [vp, cp, pu32, u32],
+        "hl_program": [vp, cp],
+        "hl_run": [vp, ctypes.POINTER(Stats)],
+        "hl_count": [vp, cp, pu64],
+        "hl_fetch": [vp, cp, vp, u64, pu64],
+        "hl_fetch_device": [vp, cp, vp, u64, pu64],
+        "hl_iteration_counts": [vp, cp, i32, pu64, u32, pu32],
+        "hl_last_error": [vp],
+        "hl_strerror": [ctypes.c_int],
+        "hl_sort_keys": [vp, vp, u64, u32, u32],
+        "hl_unique_diff": [vp, vp, u64, vp, u64, vp, pu64, pu64, u32],
+        "hl_merge": [vp, vp, u64, vp, u64, vp, u32],
+        "hl_hisa_query": [vp, vp, u64, u32, u32, vp, u64, vp, vp, pu64],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    L.hl_destroy.restype = None
+    L.hl_last_error.restype = cp
+    L.hl_strerror.restype = cp
+    _lib = L
+    return L
+
+
+def _ptr(t) -> int:
+    return int(t.data_ptr())
+
+
+def _key_bytes(t) -> int:
+    import torch
+    if t.dtype in (torch.int32, torch.uint32):
+        return 4
+    if t.dtype in (torch.int64, torch.uint64):
+        return 8
+    raise TypeError("keys must be a 32- or 64-bit integer tensor")
+
+
+@dataclass
+class RunStats:
+    iterations: int
+    key_bytes: int
+    id_bits: int
+    idb_tuples: int
+    candidates: int
+    peak_bytes: int
+    allocations: int
+    ebm_reuses: int
+    seconds: float
+    phase_ms: dict = field(default_factory=dict)
+
+
+class Engine:
+    """One hisalog engine on one GPU (see include/hisalog.h)."""
+
+    def __init__(self, device: int = 0, stream=None, arena=None, ebm: bool = True,
+                 ebm_k: float = 8.0, load_factor: float = 0.8, budget_bytes: int = 0):
+        L = lib()
+        opt = Options()
+        L.hl_options_init(ctypes.byref(opt))
+        opt.device = device
+        opt.flags = 0 if ebm else HL_FLAG_NO_EBM
+        opt.ebm_k = ebm_k
+        opt.hash_load_factor = load_factor
+        opt.hbm_budget_bytes = budget_bytes
+        self._arena = arena  # keep the caller's tensor alive
+        if arena is not None:
+            opt.arena = _ptr(arena)
+            opt.arena_bytes = arena.numel() * arena.element_size()
+        if stream is not None:
+            opt.stream = int(stream.cuda_stream if hasattr(stream, "cuda_stream") else stream)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        rc = L.hl_create(ctypes.byref(opt), ctypes.byref(h))
+        if rc != HL_OK:
+            raise HlError(rc, "hl_create: " + L.hl_strerror(rc).decode())
+        self._h = h
+        self._L = L
+        self.arity = {}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.hl_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc: int, what: str):
+        if rc != HL_OK:
+            raise HlError(rc, f"{what}: {self._L.hl_last_error(self._h).decode()}")
+
+    # ------------------------------------------------------------- engine
+    def declare(self, name: str, arity: int, edb: bool):
+        self._check(self._L.hl_declare(self._h, name.encode(), arity, 1 if edb else 0),
+                    "hl_declare")
+        self.arity[name] = arity
+
+    def load(self, name: str, rows):
+        """Loads EDB rows from a numpy array or a CUDA tensor (n x arity)."""
+        try:
+            import torch
+            is_tensor = isinstance(rows, torch.Tensor)
+        except ImportError:
+            is_tensor = False
+        if is_tensor and rows.is_cuda:
+            rows = rows.contiguous()
+            if rows.element_size() != 4:
+                raise TypeError("rows must be 32-bit")
+            self._check(self._L.hl_load_device(self._h, name.encode(), _ptr(rows),
+                                               rows.shape[0]), "hl_load_device")
+            return
+        arr = np.ascontiguousarray(np.asarray(rows), dtype=np.uint32)
+        if arr.ndim == 1:
+            arr = arr.reshape(-1, self.arity.get(name, 2))
+        self._check(self._L.hl_load(self._h, name.encode(), arr.ctypes.data, arr.shape[0]),
+                    "hl_load")
+
+    def index(self, name: str, col: int):
+        c = (ctypes.c_uint32 * 1)(col)
+        self._check(self._L.hl_index(self._h, name.encode(), c, 1), "hl_index")
+
+    def program(self, text: str):
+        self._check(self._L.hl_program(self._h, text.encode()), "hl_program")
+
+    def run(self) -> RunStats:
+        st = Stats()
+        self._check(self._L.hl_run(self._h, ctypes.byref(st)), "hl_run")
+        d = st.as_dict()
+        return RunStats(**d)
+
+    def count(self, name: str) -> int:
+        n = ctypes.c_uint64()
+        self._check(self._L.hl_count(self._h, name.encode(), ctypes.byref(n)), "hl_count")
+        return n.value
+
+    def fetch(self, name: str) -> np.ndarray:
+        n = self.count(name)
+        ar = self.arity.get(name, 2)
+        out = np.empty((n, ar), dtype=np.uint32)
+        got = ctypes.c_uint64()
+        self._check(self._L.hl_fetch(self._h, name.encode(), out.ctypes.data if n else None, n,
+                                     ctypes.byref(got)), "hl_fetch")
+        return out
+
+    def fetch_device(self, name: str):
+        import torch
+        n = self.count(name)
+        ar = self.arity.get(name, 2)
+        out = torch.empty((n, ar), dtype=torch.int32, device="cuda")
+        got = ctypes.c_uint64()
+        self._check(self._L.hl_fetch_device(self._h, name.encode(), _ptr(out) if n else None, n,
+                                            ctypes.byref(got)), "hl_fetch_device")
+        return out
+
+    def iteration_counts(self, name: str, which: int = 0) -> list:
+        cap = 1 << 16
+        buf = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_uint32()
+        self._check(self._L.hl_iteration_counts(self._h, name.encode(), which, buf, cap,
+                                                ctypes.byref(n)), "hl_iteration_counts")
+        return [int(buf[i]) for i in range(min(n.value, cap))]
+
+    # --------------------------------------------------------- primitives
+    def sort_keys(self, keys, bits: int = 0):
+        """Sorts a CUDA int32/int64 tensor in place (unsigned order)."""
+        self._check(self._L.hl_sort_keys(self._h, _ptr(keys), keys.numel(), _key_bytes(keys),
+                                         bits), "hl_sort_keys")
+        return keys
+
+    def unique_diff(self, sorted_keys, full):
+        import torch
+        kb = _key_bytes(sorted_keys)
+        out = torch.empty_like(sorted_keys)
+        n_out, n_uni = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self._L.hl_unique_diff(self._h, _ptr(sorted_keys), sorted_keys.numel(),
+                                           _ptr(full) if full.numel() else None, full.numel(),
+                                           _ptr(out), ctypes.byref(n_out), ctypes.byref(n_uni),
+                                           kb), "hl_unique_diff")
+        return out[:n_out.value], n_uni.value
+
+    def merge(self, a, b):
+        import torch
+        out = torch.empty(a.numel() + b.numel(), dtype=a.dtype, device=a.device)
+        self._check(self._L.hl_merge(self._h, _ptr(a) if a.numel() else None, a.numel(),
+                                     _ptr(b) if b.numel() else None, b.numel(), _ptr(out),
+                                     _key_bytes(a)), "hl_merge")
+        return out
+
+    def hisa_query(self, keys, shift: int, queries):
+        import torch
+        start = torch.empty(queries.numel(), dtype=torch.int64, device=keys.device)
+        length = torch.empty(queries.numel(), dtype=torch.int32, device=keys.device)
+        runs = ctypes.c_uint64()
+        self._check(self._L.hl_hisa_query(self._h, _ptr(keys), keys.numel(), _key_bytes(keys),
+                                          shift, _ptr(queries), queries.numel(), _ptr(start),
+                                          _ptr(length), ctypes.byref(runs)), "hl_hisa_query")
+        return start, length, runs.value
+
+
+def evaluate(program: str, edb: dict, idb: dict, **engine_kw):
+    """Declares, loads, runs and fetches in one call.
+
+    Returns ``(relations, deltas, stats)``: sorted uint32 arrays per IDB
+    relation, per-iteration delta sizes, and the run's statistics."""
+    with Engine(**engine_kw) as e:
+        for name, rows in edb.items():
+            e.declare(name, 2, True)
+        for name, ar in idb.items():
+            e.declare(name, ar, False)
+        for name, rows in edb.items():
+            e.load(name, rows)
+        e.program(program)
+        st = e.run()
+        rels = {n: e.fetch(n) for n in idb}
+        deltas = {n: e.iteration_counts(n, 0) for n in idb}
+        return rels, deltas, st

@@ -1,0 +1,233 @@
+"""GPU fixpoints against the oracle, bit-exact: final IDB sets (sorted rows)
+and the per-iteration delta and new-tuple counts.  Small inputs that still
+span several tiles and ragged tails; edge cases of the method."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PROG = {n: open(os.path.join(ROOT, "workloads", "programs", n + ".dl")).read()
+        for n in ("reach", "sg", "cspa_shaped")}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_eval(program, edb, idb, **kw):
+    import torch
+    import paper_2311_02206_amd as pkg
+    torch.cuda.set_device(0)
+    return pkg.evaluate(program, edb, idb, device=0, stream=torch.cuda.current_stream(), **kw)
+
+
+def check_same(program, edb, idb, **kw):
+    want = oracle.evaluate(program, edb, idb, max_iterations=100_000)
+    rels, deltas, st = gpu_eval(program, edb, idb, **kw)
+    for name in idb:
+        assert np.array_equal(rels[name], want.relations[name]), name
+        assert deltas[name] == want.deltas[name], name
+    return rels, deltas, st, want
+
+
+def test_reach_er1000():
+    say("reach er1000")
+    wl = workloads.reach_er_1000()
+    rels, deltas, st, want = check_same(PROG["reach"], wl["edb"], {"Reach": 2})
+    assert st.key_bytes == 4 and st.id_bits == 10
+    assert st.iterations == want.iterations
+
+
+def test_new_counts_match_oracle():
+    import torch
+    import paper_2311_02206_amd as pkg
+    say("new counts sg tree")
+    wl = workloads.scaled_tree(3000, seed=5)
+    want = oracle.evaluate(PROG["sg"], wl["edb"], {"SG": 2})
+    with pkg.Engine(device=0, stream=torch.cuda.current_stream()) as e:
+        e.declare("Edge", 2, True)
+        e.declare("SG", 2, False)
+        e.load("Edge", wl["edb"]["Edge"])
+        e.program(PROG["sg"])
+        e.run()
+        assert e.iteration_counts("SG", 1) == want.news["SG"]
+        assert e.iteration_counts("SG", 0) == want.deltas["SG"]
+
+
+def test_sg_paper_example():
+    say("sg paper example")
+    E = np.array([[9, 0], [9, 2], [0, 3], [1, 3], [1, 4], [1, 5], [2, 5], [3, 6], [4, 7], [4, 8],
+                  [5, 8], [6, 10], [8, 11], [12, 10], [12, 11]], dtype=np.uint32)
+    rels, deltas, st, want = check_same(PROG["sg"], {"Edge": E}, {"SG": 2})
+    assert deltas["SG"] == [12, 4, 0]
+
+
+@pytest.mark.parametrize("n", [2, 50, 5000, 40_000])
+def test_sg_tree(n):
+    say(f"sg tree {n}")
+    wl = workloads.scaled_tree(n, seed=n)
+    rels, deltas, st, want = check_same(PROG["sg"], wl["edb"], {"SG": 2})
+    total, cf = oracle.sg_tree_closed_form(wl["edb"]["Edge"])
+    assert len(rels["SG"]) == total and deltas["SG"] == cf
+
+
+@pytest.mark.parametrize("scale,m", [(8, 700), (10, 3000), (12, 12_000)])
+def test_reach_rmat_small(scale, m):
+    say(f"reach rmat {scale} {m}")
+    wl = workloads.scaled_rmat(scale, m, seed=scale)
+    check_same(PROG["reach"], wl["edb"], {"Reach": 2})
+
+
+def test_reach_closed_forms():
+    for n in (2, 3, 100, 700):
+        say(f"reach closed forms n={n}")
+        path = np.array([[i, i + 1] for i in range(n - 1)], dtype=np.uint32)
+        rels, deltas, st = gpu_eval(PROG["reach"], {"Edge": path}, {"Reach": 2})
+        assert len(rels["Reach"]) == n * (n - 1) // 2
+        assert deltas["Reach"] == list(range(n - 1, 0, -1)) + [0]
+        cyc = np.array([[i, (i + 1) % n] for i in range(n)], dtype=np.uint32)
+        rels, _, _ = gpu_eval(PROG["reach"], {"Edge": cyc}, {"Reach": 2})
+        assert len(rels["Reach"]) == n * n
+    say("reach empty / self loop")
+    rels, deltas, st = gpu_eval(PROG["reach"], {"Edge": np.zeros((0, 2), np.uint32)},
+                                {"Reach": 2})
+    assert len(rels["Reach"]) == 0 and deltas["Reach"] == [0]
+    rels, deltas, st = gpu_eval(PROG["reach"], {"Edge": np.array([[7, 7]], np.uint32)},
+                                {"Reach": 2})
+    assert rels["Reach"].tolist() == [[7, 7]]
+
+
+def test_wide_ids_use_64bit_keys():
+    say("wide ids")
+    wl = workloads.reach_er_1000()
+    E = wl["edb"]["Edge"].astype(np.uint64)
+    # spread ids over the whole uint32 range, including 0 and 2^32-1
+    perm = (E * np.uint64(4294967291) + np.uint64(12345)) % np.uint64(1 << 32)
+    perm[0, 0] = 0
+    perm[1, 1] = 0xFFFFFFFF
+    E2 = perm.astype(np.uint32)
+    rels, deltas, st, want = check_same(PROG["reach"], {"Edge": E2}, {"Reach": 2})
+    assert st.key_bytes == 8 and st.id_bits == 32
+
+
+def test_duplicates_and_row_order():
+    say("duplicates")
+    wl = workloads.scaled_rmat(9, 1500, seed=4)
+    E = wl["edb"]["Edge"]
+    rng = np.random.default_rng(0)
+    E2 = np.concatenate([E[rng.permutation(len(E))], E[:300], E[:10]])
+    r1, d1, _ = gpu_eval(PROG["reach"], {"Edge": E}, {"Reach": 2})
+    r2, d2, _ = gpu_eval(PROG["reach"], {"Edge": E2}, {"Reach": 2})
+    assert np.array_equal(r1["Reach"], r2["Reach"]) and d1 == d2
+
+
+def test_ebm_off_and_arena_give_same_result():
+    import torch
+    say("ebm off / arena")
+    wl = workloads.scaled_rmat(10, 3000, seed=8)
+    r0, d0, s0 = gpu_eval(PROG["reach"], wl["edb"], {"Reach": 2})
+    r1, d1, s1 = gpu_eval(PROG["reach"], wl["edb"], {"Reach": 2}, ebm=False)
+    arena = torch.empty(256 << 20, dtype=torch.uint8, device="cuda")
+    r2, d2, s2 = gpu_eval(PROG["reach"], wl["edb"], {"Reach": 2}, arena=arena)
+    for r, d in ((r1, d1), (r2, d2)):
+        assert np.array_equal(r["Reach"], r0["Reach"]) and d == d0
+    assert s1.allocations > s0.allocations
+
+
+def test_two_delta_variants():
+    say("two delta variants")
+    prog = """P(a, b) :- E(a, b).
+P(a, b) :- P(a, c), F(c, b).
+Q(a, b) :- P(a, c), P(c, b)."""
+    edb = {"E": np.array([[1, 2], [2, 3]], np.uint32),
+           "F": np.array([[3, 4], [4, 5], [5, 6]], np.uint32)}
+    rels, deltas, st, want = check_same(prog, edb, {"P": 2, "Q": 2})
+    assert [1, 4] in rels["Q"].tolist()
+
+
+def test_nonlinear_closure():
+    say("nonlinear closure")
+    prog = "T(x, y) :- E(x, y).\nT(x, y) :- T(x, z), T(z, y)."
+    wl = workloads.scaled_rmat(10, 2500, seed=3)
+    check_same(prog, {"E": wl["edb"]["Edge"]}, {"T": 2})
+
+
+def test_random_programs():
+    """Random binary-relation programs (the brute-force pin generator); the
+    planner rejects shapes outside its chain-join form, the rest must match."""
+    import random
+    import paper_2311_02206_amd as pkg
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    from test_oracle_pins import random_program, render
+    rng = random.Random(77)
+    ran = 0
+    for k in range(120):
+        rules = random_program(rng)
+        n = rng.randint(3, 40)
+        edb = {}
+        for name in ("E", "F"):
+            m = rng.randint(0, 3 * n)
+            edb[name] = np.array(sorted({(rng.randrange(n), rng.randrange(n)) for _ in range(m)}),
+                                 dtype=np.uint32).reshape(-1, 2)
+        prog = render(rules)
+        try:
+            check_same(prog, edb, {"P": 2, "Q": 2})
+            ran += 1
+        except pkg.HlError as e:
+            assert e.code == pkg.hisalog.HL_E_UNSUPPORTED, (prog, e)
+    say(f"random programs run: {ran}")
+    assert ran >= 40
+
+
+def test_cspa_shaped_small():
+    say("cspa small")
+    A = workloads.zipf_pairs(1 << 9, 300, 1.2, 0xC3, 0, orient="by_rank")
+    D = workloads.zipf_pairs(1 << 9, 120, 1.2, 0xC3, 1, orient="by_rank")
+    check_same(PROG["cspa_shaped"], {"Assign": A, "Dereference": D},
+               {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2})
+
+
+def test_error_paths():
+    import torch
+    import paper_2311_02206_amd as pkg
+    say("error paths")
+    with pkg.Engine(device=0, stream=torch.cuda.current_stream()) as e:
+        e.declare("E", 2, True)
+        e.declare("R", 2, False)
+        with pytest.raises(pkg.HlError) as ei:
+            e.declare("E", 2, True)
+        assert ei.value.code == pkg.hisalog.HL_E_INVALID
+        with pytest.raises(pkg.HlError) as ei:
+            e.declare("T3", 3, False)
+        assert ei.value.code == pkg.hisalog.HL_E_UNSUPPORTED
+        with pytest.raises(pkg.HlError) as ei:
+            e.program("R(x, y) :- E(x, y), E(y, x).")  # shares two variables
+        assert ei.value.code == pkg.hisalog.HL_E_UNSUPPORTED
+        with pytest.raises(pkg.HlError) as ei:
+            e.program("R(x, y) :- E(x, .")
+        assert ei.value.code == pkg.hisalog.HL_E_INVALID
+        with pytest.raises(pkg.HlError) as ei:
+            e.run()  # no program yet
+        assert ei.value.code == pkg.hisalog.HL_E_STATE
+        e.program("R(x, y) :- E(x, y).\nR(x, y) :- E(x, z), R(z, y).")
+        e.load("E", np.array([[1, 2], [2, 3]], np.uint32))
+        e.run()
+        import ctypes
+        n = ctypes.c_uint64()
+        rc = e._L.hl_fetch(e._h, b"R", None, 0, ctypes.byref(n))
+        assert rc == pkg.hisalog.HL_E_CAPACITY and n.value == 3
+        assert e.fetch("R").tolist() == [[1, 2], [1, 3], [2, 3]]
+    say("budget exhaustion")
+    wl = workloads.scaled_rmat(10, 3000, seed=8)
+    with pytest.raises(pkg.HlError) as ei:
+        gpu_eval(PROG["reach"], wl["edb"], {"Reach": 2}, budget_bytes=1 << 16)
+    assert ei.value.code == pkg.hisalog.HL_E_NOMEM

@@ -1,0 +1,141 @@
+"""GPU parity of each kernel of an iteration against plain numpy definitions:
+sort (Section 3.2 / Algorithm 1), unique + set difference (Section 5.1,
+populating delta), merge (Section 3.2, merge path) and the HISA range
+query (Section 3.3 / Algorithm 2).  Bit-exact."""
+
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+U = {4: np.uint32, 8: np.uint64}
+S = {4: np.int32, 8: np.int64}
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import torch
+    import paper_2311_02206_amd as pkg
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    e = pkg.Engine(device=0, stream=torch.cuda.current_stream())
+    yield e
+    e.close()
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def to_dev(a, kb):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=U[kb]).view(S[kb])).cuda()
+
+
+def to_host(t, kb):
+    return t.cpu().numpy().view(U[kb])
+
+
+def rand_keys(rng, n, kb, bits):
+    hi = (1 << bits) - 1
+    if kb == 8:
+        a = rng.integers(0, 1 << 63, size=n, dtype=np.uint64) * np.uint64(2) + \
+            rng.integers(0, 2, size=n, dtype=np.uint64)
+        return a & np.uint64(hi)
+    return (rng.integers(0, 1 << 32, size=n, dtype=np.uint64) & np.uint64(hi)).astype(np.uint32)
+
+
+SIZES = [0, 1, 2, 63, 64, 65, 1000, 4095, 4096, 4097, 100_003, 1_000_000]
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("n", SIZES)
+def test_sort_random(eng, kb, n):
+    rng = np.random.default_rng(n + kb)
+    for bits in sorted({8 * kb, 20, 13}):
+        say(f"sort kb={kb} n={n} bits={bits}")
+        a = rand_keys(rng, n, kb, bits)
+        t = to_dev(a, kb)
+        eng.sort_keys(t, bits)
+        assert np.array_equal(to_host(t, kb), np.sort(a))
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+def test_sort_special(eng, kb):
+    n = 50_001
+    top = np.iinfo(U[kb]).max
+    cases = {
+        "equal": np.full(n, 7, dtype=U[kb]),
+        "sorted": np.arange(n, dtype=U[kb]),
+        "reversed": np.arange(n, dtype=U[kb])[::-1].copy(),
+        "extremes": np.array([top, 0, top, 1, 0, top - 1] * 1000, dtype=U[kb]),
+        "two_values": np.where(np.arange(n) % 3 == 0, top, 0).astype(U[kb]),
+    }
+    for name, a in cases.items():
+        say(f"sort special {name} kb={kb}")
+        t = to_dev(a, kb)
+        eng.sort_keys(t, 0)
+        assert np.array_equal(to_host(t, kb), np.sort(a)), name
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("n,nf,span", [(0, 10, 100), (1, 0, 10), (5000, 0, 1000),
+                                        (20_000, 30_000, 60_000), (100_000, 5_000, 1 << 30),
+                                        (50_000, 2_000_000, 4_000_000), (300_000, 1000, 2000)])
+def test_unique_diff(eng, kb, n, nf, span):
+    import torch
+    say(f"unique_diff kb={kb} n={n} nf={nf} span={span}")
+    rng = np.random.default_rng(n * 7 + nf)
+    c = np.sort(rng.integers(0, span, size=n).astype(U[kb]))
+    f = np.unique(rng.integers(0, span, size=nf).astype(U[kb]))
+    out, nu = eng.unique_diff(to_dev(c, kb), to_dev(f, kb) if len(f) else
+                              torch.empty(0, dtype=getattr(torch, "int32" if kb == 4 else "int64"),
+                                          device="cuda"))
+    want = np.setdiff1d(np.unique(c), f)
+    assert nu == len(np.unique(c))
+    assert np.array_equal(to_host(out, kb), want)
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("na,nb", [(0, 0), (0, 5), (7, 0), (1, 1), (2048, 1), (3000, 5000),
+                                   (1_000_000, 1234), (17, 400_000), (500_000, 500_000)])
+def test_merge(eng, kb, na, nb):
+    say(f"merge kb={kb} na={na} nb={nb}")
+    rng = np.random.default_rng(na + 3 * nb)
+    allk = np.unique(rand_keys(rng, 2 * (na + nb) + 10, kb, 8 * kb))
+    rng.shuffle(allk)
+    a = np.sort(allk[:na])
+    b = np.sort(allk[na:na + nb])
+    out = eng.merge(to_dev(a, kb), to_dev(b, kb))
+    assert np.array_equal(to_host(out, kb), np.sort(np.concatenate([a, b])))
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("n", [0, 1, 1000, 100_000])
+def test_hisa_query(eng, kb, n):
+    import torch
+    say(f"hisa kb={kb} n={n}")
+    rng = np.random.default_rng(n + 11)
+    shift = 16 if kb == 4 else 32
+    jc_max = (1 << (32 - shift)) - 1 if kb == 4 else (1 << 32) - 1
+    # skewed join keys: a few long runs and many short ones
+    jc = np.concatenate([rng.integers(0, min(jc_max, 50_000) + 1, size=n),
+                         np.full(n // 3, 5), np.full(n // 7, min(jc_max, 0xFFFFFFFF))])
+    other = rng.integers(0, 1 << shift, size=len(jc))
+    keys = np.unique((jc.astype(np.uint64) << np.uint64(shift)) | other.astype(np.uint64))
+    keys = keys.astype(U[kb])
+    jk = (keys.astype(np.uint64) >> np.uint64(shift)).astype(np.uint32)
+    q = np.concatenate([np.unique(jk), rng.integers(0, min(jc_max, 60_000) + 1, size=2000),
+                        np.array([0, 1, min(jc_max, 0xFFFFFFFF)])]).astype(np.uint32)
+    tq = torch.from_numpy(q.view(np.int32)).cuda()
+    st, ln, runs = eng.hisa_query(to_dev(keys, kb), shift, tq)
+    lo = np.searchsorted(jk, q, side="left")
+    hi = np.searchsorted(jk, q, side="right")
+    want_len = (hi - lo).astype(np.int64)
+    want_start = np.where(want_len > 0, lo, 0)
+    assert runs == len(np.unique(jk))
+    assert np.array_equal(ln.cpu().numpy().astype(np.int64), want_len)
+    assert np.array_equal(st.cpu().numpy(), want_start)
