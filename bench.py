@@ -1,0 +1,217 @@
+"""Benchmark: deduplicated new IDB tuples per second of one semi-naive
+fixpoint on one MI355X.
+
+Workload (one step = both fixpoints, every step of the hot path):
+  * Reach (transitive closure) on an R-MAT graph (a, b, c = 0.57, 0.19,
+    0.19), 2^16 nodes, 200,000 distinct edges;
+  * same-generation on a random breadth-first tree of 50,000 nodes with
+    1-4 children per node.
+Inputs are synthetic (workloads/) and loaded into HBM before timing.  The
+timed region is hl_run on both engines (EDB dedup and index builds, every
+iteration, the final empty one).  value = (|Reach| + |SG|) / time.
+
+After timing, the outputs are checked bit-exact against independent exact
+references: Reach against per-source BFS (tuple count and the per-iteration
+delta sizes implied by shortest distances, plus sampled sources row by
+row), SG against its closed form on a tree (count, per-iteration deltas,
+sampled rows).
+
+Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
+build runs on one GPU.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "new IDB tuples/sec per fixpoint (learned/batched vs plain HISA), bit-exact"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_engine(program, edb, idb, stream, kernel_timing):
+    from paper_2311_02206_amd import Engine
+    e = Engine(device=0, stream=stream, kernel_timing=kernel_timing)
+    for name in edb:
+        e.declare(name, 2, True)
+    for name, ar in idb.items():
+        e.declare(name, ar, False)
+    for name, rows in edb.items():
+        e.load(name, rows)
+    e.program(program)
+    return e
+
+
+def verify_reach(e, n_nodes, edges, sources):
+    import oracle
+    total, hist = oracle.reach_bfs_histogram(n_nodes, edges)
+    ok = e.count("Reach") == total
+    ok &= e.iteration_counts("Reach", 0) == oracle.reach_deltas_from_histogram(hist)
+    R = e.fetch("Reach")
+    for s in sources:
+        lo, hi = np.searchsorted(R[:, 0], [s, s + 1])
+        ok &= np.array_equal(R[lo:hi, 1], oracle.reach_from(n_nodes, edges, s))
+    return bool(ok), total
+
+
+def verify_sg(e, edges, n_sample_rows=2000, seed=0):
+    import oracle
+    total, deltas = oracle.sg_tree_closed_form(edges)
+    ok = e.count("SG") == total and e.iteration_counts("SG", 0) == deltas
+    S = e.fetch("SG")
+    n = int(edges.max()) + 1
+    depth = np.zeros(n, dtype=np.int64)
+    parent = np.full(n, -1, dtype=np.int64)
+    parent[edges[:, 1]] = edges[:, 0]
+    for v in range(1, n):  # breadth-first ids: parents come first
+        depth[v] = depth[parent[v]] + 1
+    ok &= bool(np.all(S[:, 0] != S[:, 1]))
+    rng = np.random.default_rng(seed)
+    idx = rng.integers(0, len(S), size=min(n_sample_rows, len(S)))
+    ok &= bool(np.all(depth[S[idx, 0]] == depth[S[idx, 1]]))
+    ok &= bool(np.all(np.diff(S[:, 0].astype(np.int64) * (1 << 32) + S[:, 1]) > 0))
+    return bool(ok), total
+
+
+def cpu_baseline(programs):
+    """The oracle (single-threaded std::set semi-naive) on a bounded sample of
+    the same workload: Reach on R-MAT scale 11 (2,048 nodes, 6,250 edges =
+    200,000 / 32) and SG on a 6,250-node tree of the same generator."""
+    import oracle
+    import workloads
+    r = workloads.scaled_rmat(11, 6_250, seed=0xC2A)
+    t = workloads.scaled_tree(6_250, seed=0xC2B)
+    a = oracle.evaluate(programs["reach"], r["edb"], {"Reach": 2})
+    b = oracle.evaluate(programs["sg"], t["edb"], {"SG": 2})
+    tuples = len(a.relations["Reach"]) + len(b.relations["SG"])
+    secs = a.seconds + b.seconds
+    return {"value": tuples / secs, "unit": "tuples/s", "cores": 1, "kind": "oracle",
+            "sample": f"Reach on R-MAT scale 11 (6,250 edges; {len(a.relations['Reach'])} tuples) "
+                      f"+ SG on a 6,250-node 1-4-ary tree ({len(b.relations['SG'])} tuples); "
+                      f"{secs:.1f} s of fixpoint time"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-verify", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this build has no multi-GPU path); "
+              f"got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+    from paper_2311_02206_amd.hisalog import KERNELS
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    programs = {n: open(os.path.join(ROOT, "workloads", "programs", n + ".dl")).read()
+                for n in ("reach", "sg")}
+    log("generating inputs")
+    reach_wl = workloads.reach_rmat16()
+    sg_wl = workloads.sg_tree_50k()
+    engines = {
+        "reach": make_engine(programs["reach"], reach_wl["edb"], {"Reach": 2}, stream, True),
+        "sg": make_engine(programs["sg"], sg_wl["edb"], {"SG": 2}, stream, True),
+    }
+    torch.cuda.synchronize()
+
+    def step():
+        out = {}
+        for k, e in engines.items():
+            out[k] = e.run()
+        return out
+
+    for i in range(args.warmup):
+        log(f"warmup {i}")
+        step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps")
+    kstats = {k: {kn: [0, 0.0, 0] for kn in KERNELS} for k in engines}
+    per = {k: 0.0 for k in engines}
+    t0 = time.perf_counter()
+    last = None
+    for i in range(args.steps):
+        last = step()
+        for k, e in engines.items():
+            per[k] += last[k].seconds
+            for kn, (n, ms, b) in e.kernel_stats().items():
+                ks = kstats[k][kn]
+                ks[0] += n
+                ks[1] += ms
+                ks[2] += b
+        log(f"step {i}: " + ", ".join(f"{k} {last[k].seconds * 1e3:.1f} ms" for k in engines))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tuples = sum(last[k].idb_tuples for k in engines)
+    ms_per_step = elapsed / args.steps * 1e3
+    value = tuples / (elapsed / args.steps)
+
+    # dominant kernel: the one with the most summed launch time over both
+    tot = {kn: (sum(kstats[k][kn][0] for k in engines), sum(kstats[k][kn][1] for k in engines),
+                sum(kstats[k][kn][2] for k in engines)) for kn in KERNELS}
+    dom = max(tot, key=lambda kn: tot[kn][1])
+    n_l, ms_l, b_l = tot[dom]
+    avg_s = ms_l / 1e3 / max(n_l, 1)
+    achieved = (b_l / max(n_l, 1)) / avg_s / 1e9 if n_l else 0.0
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "launches": n_l, "avg_launch_us": round(avg_s * 1e6, 2),
+                "algorithmic_bytes_per_launch": int(b_l / max(n_l, 1))}
+
+    verified = None
+    if not args.no_verify:
+        log("verifying against BFS / closed form")
+        ok_r, _ = verify_reach(engines["reach"], reach_wl["n_nodes"], reach_wl["edb"]["Edge"],
+                               sources=[0, 1, 2, 3, 100, 4095, 20000, 65535])
+        ok_s, _ = verify_sg(engines["sg"], sg_wl["edb"]["Edge"])
+        verified = bool(ok_r and ok_s)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(programs)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "tuples/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32" if all(last[k].key_bytes == 4 for k in engines) else "u64",
+        "data": "synthetic",
+        "config": {"workload": "reach_rmat16_200k+sg_tree_50k", "engine": "plain_hisa",
+                   "reach_tuples": last["reach"].idb_tuples, "sg_tuples": last["sg"].idb_tuples,
+                   "reach_iterations": last["reach"].iterations,
+                   "sg_iterations": last["sg"].iterations},
+        "verified": verified,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "per_workload_ms": {k: per[k] / args.steps * 1e3 for k in engines},
+        "phase_ms": {k: last[k].phase_ms for k in engines},
+        "kernels": {kn: {"launches": v[0], "ms": round(v[1], 3),
+                         "GBps": round(v[2] / (v[1] / 1e3) / 1e9, 1) if v[1] else None}
+                    for kn, v in tot.items()},
+    }
+    for e in engines.values():
+        e.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

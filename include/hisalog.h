@@ -48,6 +48,18 @@ extern "C" {
 #define HL_FLAG_NO_EBM 0x1u /* disable eager buffer management (exact-size
                                buffers, reallocated on every growth: the
                                paper's "Normal" column of Table 1) */
+#define HL_FLAG_KERNEL_TIMING 0x2u /* time every launch of the kernels listed
+                                      under hl_kernel_stats with HIP events */
+
+/* Kernels reported by hl_kernel_stats. */
+#define HL_KERNEL_RADIX_HIST 0    /* digit histogram of one radix pass */
+#define HL_KERNEL_RADIX_SCATTER 1 /* stable scatter of one radix pass */
+#define HL_KERNEL_UNIQUE_DIFF 2   /* dedup + membership test against full */
+#define HL_KERNEL_MERGE 3         /* merge path of full and delta */
+#define HL_KERNEL_JOIN_PROBE 4    /* hash probe of every outer tuple */
+#define HL_KERNEL_JOIN_EXPAND 5   /* load-balanced expansion of the runs */
+#define HL_KERNEL_HISA_BUILD 6    /* hash index insertion */
+#define HL_KERNEL_COUNT 7
 
 /* Phases of one fixpoint, timed with HIP events (milliseconds). */
 #define HL_PHASE_INDEX_EDB 0 /* EDB dedup + HISA builds before iteration 0 */
@@ -100,7 +112,10 @@ int hl_options_init(hl_options* opt);
 
 /* Creates an engine on opt->device.  *out receives the handle (NULL on
  * failure).  With opt->stream set, the engine never creates or destroys a
- * stream; the caller keeps that stream alive until hl_destroy. */
+ * stream; the caller keeps that stream alive until hl_destroy.
+ * opt->device == -1 creates a planning-only engine that touches no device:
+ * hl_declare, hl_index and hl_program work (so programs can be checked),
+ * loads, runs and primitives return HL_E_STATE. */
 int hl_create(const hl_options* opt, hl_engine** out);
 
 /* Releases every device buffer the engine allocated (never the caller's
@@ -164,6 +179,15 @@ int hl_fetch_device(hl_engine* e, const char* name, uint32_t* d_rows, uint64_t c
  * tuples derived in the iteration before subtracting full. */
 int hl_iteration_counts(hl_engine* e, const char* name, int32_t which, uint64_t* counts,
                         uint32_t cap, uint32_t* n_iters);
+
+/* With HL_FLAG_KERNEL_TIMING: totals over the last hl_run for kernel
+ * `kernel` (HL_KERNEL_*): number of launches, summed launch time in
+ * milliseconds (HIP events recorded on the engine's stream right before and
+ * after each launch) and summed algorithmic bytes (the bytes the kernel
+ * must read and write by definition: inputs once, outputs once).  Without
+ * the flag every total is 0. */
+int hl_kernel_stats(hl_engine* e, int32_t kernel, uint64_t* launches, double* ms,
+                    uint64_t* algorithmic_bytes);
 
 /* Text of the most recent error of e (never NULL; "" when none). */
 const char* hl_last_error(hl_engine* e);

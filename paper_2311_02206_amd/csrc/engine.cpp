@@ -149,6 +149,71 @@ struct Buf {
   u64 bytes = 0;
 };
 
+// Times launches with HIP events on the engine's stream.
+class EventTimer : public hl::LaunchTimer {
+ public:
+  struct Total {
+    u64 launches = 0;
+    double ms = 0;
+    u64 bytes = 0;
+  };
+  void begin(int kernel, hipStream_t s) override {
+    hipEvent_t a = get();
+    (void)hipEventRecord(a, s);
+    open_.push_back({kernel, a, nullptr, 0});
+  }
+  void end(int kernel, hipStream_t s, u64 bytes) override {
+    hipEvent_t b = get();
+    (void)hipEventRecord(b, s);
+    if (!open_.empty() && open_.back().kernel == kernel && !open_.back().b) {
+      open_.back().b = b;
+      open_.back().bytes = bytes;
+    }
+  }
+  // After a synchronisation of the stream.
+  void collect() {
+    for (const Rec& r : open_) {
+      if (!r.b) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+        Total& t = totals[r.kernel];
+        ++t.launches;
+        t.ms += ms;
+        t.bytes += r.bytes;
+      }
+    }
+    open_.clear();
+    used_ = 0;
+  }
+  void reset() {
+    open_.clear();
+    used_ = 0;
+    for (Total& t : totals) t = Total{};
+  }
+  ~EventTimer() override {
+    for (hipEvent_t ev : pool_) (void)hipEventDestroy(ev);
+  }
+  Total totals[hl::K_COUNT];
+
+ private:
+  struct Rec {
+    int kernel;
+    hipEvent_t a, b;
+    u64 bytes;
+  };
+  hipEvent_t get() {
+    if (used_ == pool_.size()) {
+      hipEvent_t ev;
+      if (hipEventCreate(&ev) != hipSuccess) fail(HL_E_DEVICE, "hipEventCreate failed");
+      pool_.push_back(ev);
+    }
+    return pool_[used_++];
+  }
+  std::vector<hipEvent_t> pool_;
+  size_t used_ = 0;
+  std::vector<Rec> open_;
+};
+
 // ------------------------------------------------------------------ program
 
 struct Atom {
@@ -284,6 +349,8 @@ struct hl_engine {
   std::vector<std::pair<int, hipEvent_t>> marks;
   hl_stats st{};
   u64 reuses = 0;
+  EventTimer ktimer;
+  hl::LaunchTimer* kt() { return (flags & HL_FLAG_KERNEL_TIMING) ? &ktimer : nullptr; }
 
   // ---------------------------------------------------------------- utils
 
@@ -299,7 +366,10 @@ struct hl_engine {
     return k;
   }
 
-  void sync() { HIPCK(hipStreamSynchronize(stream)); }
+  void sync() {
+    HIPCK(hipStreamSynchronize(stream));
+    if (flags & HL_FLAG_KERNEL_TIMING) ktimer.collect();
+  }
 
   // Eager buffer management (Section 5.3): a buffer that is large enough is
   // reused; one that must grow is reallocated to `want` (>= need) bytes.
@@ -450,7 +520,8 @@ struct hl_engine {
   // ---------------------------------------------------------------- plan
 
   // Chain of binary joins starting from body atom `first` (Section 5.2,
-  // temporarily materialised n-way joins).
+  // temporarily materialised n-way joins).  The carried pair holds at most
+  // two live variables; each further atom must share a variable with it.
   Plan plan_rule(int rule_id, int first, bool outer_delta) {
     const Rule& r = rules[rule_id];
     Plan p;
@@ -462,7 +533,8 @@ struct hl_engine {
       fail(HL_E_UNSUPPORTED, "rule '" + r.text + "': " + why);
     };
     int cur[2] = {r.body[first].arg[0], r.body[first].arg[1]};
-    if (cur[0] == cur[1]) unsupported("an atom repeats a variable");
+    // a variable repeated in the outer atom: the two columns must be equal
+    int eq0 = (cur[0] == cur[1]) ? 0 : -1, eq1 = (cur[0] == cur[1]) ? 1 : -1;
     std::vector<int> remaining;
     for (int j = 0; j < int(r.body.size()); ++j)
       if (j != first) remaining.push_back(j);
@@ -484,34 +556,43 @@ struct hl_engine {
         applied[f] = true;
       }
     };
+    auto in_cur = [&](int v) { return v == cur[0] || v == cur[1]; };
     if (remaining.empty()) {
       p.proj.outer_col = 0;
       take_filter(p.proj, cur, 2);
+      p.proj.ea = eq0;
+      p.proj.eb = eq1;
       p.proj.src0 = src_of(r.head.arg[0], cur, 2);
       p.proj.src1 = src_of(r.head.arg[1], cur, 2);
       return p;
     }
     while (!remaining.empty()) {
-      int pick = -1, shared = -1;
+      int pick = -1;
       for (size_t q = 0; q < remaining.size() && pick < 0; ++q) {
         const Atom& b = r.body[remaining[q]];
-        int hits = 0;
-        for (int c = 0; c < 2; ++c)
-          if (b.arg[c] == cur[0] || b.arg[c] == cur[1]) ++hits, shared = c;
-        if (hits == 2) unsupported("an atom shares two variables with the carried pair");
-        if (hits == 1) pick = int(q);
+        if (in_cur(b.arg[0]) || in_cur(b.arg[1])) pick = int(q);
       }
       if (pick < 0) unsupported("a body atom shares no variable with the carried pair");
       const Atom& b = r.body[remaining[pick]];
       remaining.erase(remaining.begin() + pick);
-      if (b.arg[0] == b.arg[1]) unsupported("an atom repeats a variable");
       Step s;
       s.inner_rel = b.rel;
+      // probe on a bound column; the other column is new, or bound (then it
+      // must equal its carried value), or the same variable again
+      const int shared = in_cur(b.arg[0]) ? 0 : 1;
       s.inner_col = shared;
       const int sv = b.arg[shared], other = b.arg[1 - shared];
       s.js.outer_col = (cur[0] == sv) ? 0 : 1;
       int avail[3] = {cur[0], cur[1], other};
       take_filter(s.js, avail, 3);
+      s.js.ea = eq0;
+      s.js.eb = eq1;
+      eq0 = eq1 = -1;
+      if (in_cur(other)) {
+        if (s.js.ea >= 0) unsupported("two equality tests apply at one join");
+        s.js.ea = src_of(other, avail, 2);
+        s.js.eb = 2;
+      }
       if (remaining.empty()) {
         s.js.src0 = src_of(r.head.arg[0], avail, 3);
         s.js.src1 = src_of(r.head.arg[1], avail, 3);
@@ -533,9 +614,6 @@ struct hl_engine {
         s.js.src1 = src_of(keep[1], avail, 3);
         cur[0] = keep[0];
         cur[1] = keep[1];
-        if (cur[0] == cur[1]) {
-          // a single live variable: the next atom must still share it
-        }
       }
       p.steps.push_back(s);
     }
@@ -600,7 +678,7 @@ struct hl_engine {
     ix.cap = cap;
     HIPCK(hl::fill_zero(ix.table.p, cap * sizeof(Slot), stream));
     const K* keys = col == 0 ? kp<K>(R.full) : kp<K>(ix.keys);
-    HIPCK(hl::hisa_build<K>(keys, ix.n, w, static_cast<Slot*>(ix.table.p), cap, stream));
+    HIPCK(hl::hisa_build<K>(keys, ix.n, w, static_cast<Slot*>(ix.table.p), cap, stream, kt()));
   }
 
   // Refreshes every used index of the listed relations: column-1 copies
@@ -641,7 +719,7 @@ struct hl_engine {
     HIPCK(hl::swap_cols<K>(src, n_src, w, kp<K>(tmp[0]), stream));
     reserve(ws, hl::sort_workspace_bytes(n_src), hl::sort_workspace_bytes(n_src) * 2);
     K* sorted = nullptr;
-    HIPCK(hl::radix_sort<K>(kp<K>(tmp[0]), kp<K>(alt), n_src, bits, ws.p, stream, &sorted));
+    HIPCK(hl::radix_sort<K>(kp<K>(tmp[0]), kp<K>(alt), n_src, bits, ws.p, stream, &sorted, kt()));
     if (from_scratch || ix.n == 0) {
       reserve(ix.keys, n_src * sizeof(K), u64(double(n_src) * sizeof(K) * 1.5));
       HIPCK(hipMemcpyAsync(ix.keys.p, sorted, n_src * sizeof(K), hipMemcpyDeviceToDevice, stream));
@@ -651,7 +729,7 @@ struct hl_engine {
     const u64 total = ix.n + n_src;
     reserve(ix.spare, total * sizeof(K), u64((double(ix.n) + ebm_k * double(n_src)) * sizeof(K)));
     reserve(ws, hl::merge_workspace_bytes(ix.n, n_src), hl::merge_workspace_bytes(ix.n, n_src) * 2);
-    HIPCK(hl::merge<K>(kp<K>(ix.keys), ix.n, sorted, n_src, kp<K>(ix.spare), ws.p, stream));
+    HIPCK(hl::merge<K>(kp<K>(ix.keys), ix.n, sorted, n_src, kp<K>(ix.spare), ws.p, stream, kt()));
     std::swap(ix.keys, ix.spare);
     ix.n = total;
   }
@@ -673,13 +751,14 @@ struct hl_engine {
                              stream));
       reserve(ws, hl::sort_workspace_bytes(R.n_raw), hl::sort_workspace_bytes(R.n_raw) * 2);
       K* sorted = nullptr;
-      HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_raw, 2 * w, ws.p, stream, &sorted));
+      HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_raw, 2 * w, ws.p, stream, &sorted,
+                              kt()));
       K* other = sorted == kp<K>(R.cand) ? kp<K>(alt) : kp<K>(R.cand);
       reserve(R.full, R.n_raw * sizeof(K), R.n_raw * sizeof(K));
       reserve(ws, hl::unique_diff_workspace_bytes(R.n_raw),
               hl::unique_diff_workspace_bytes(R.n_raw) * 2);
       HIPCK(hl::unique_diff<K>(sorted, R.n_raw, static_cast<const K*>(nullptr), 0, other,
-                               kp<K>(R.full), d_small, ws.p, stream));
+                               kp<K>(R.full), d_small, ws.p, stream, kt()));
       HIPCK(hipMemcpyAsync(h_small, d_small, sizeof(u64), hipMemcpyDeviceToHost, stream));
       sync();
       R.n_full = h_small[0];
@@ -702,7 +781,7 @@ struct hl_engine {
       JoinSpec js = p.proj;
       js.w = w;
       reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + n) * sizeof(K));
-      const bool filtered = js.fa >= 0;
+      const bool filtered = js.fa >= 0 || js.ea >= 0;
       if (filtered) {
         h_small[0] = H.n_cand;
         HIPCK(hipMemcpyAsync(d_cursor, h_small, sizeof(u64), hipMemcpyHostToDevice, stream));
@@ -735,7 +814,7 @@ struct hl_engine {
       reserve_grow(join_off, n * sizeof(u64));
       HIPCK(hl::join_probe<K>(cur, n, js, static_cast<const Slot*>(ix.table.p), ix.cap,
                               static_cast<u32*>(join_start.p), static_cast<u32*>(join_len.p),
-                              stream));
+                              stream, kt()));
       reserve(ws, hl::scan_workspace_bytes(n), hl::scan_workspace_bytes(n) * 2);
       HIPCK(hl::scan_u32_u64(static_cast<u32*>(join_len.p), n, static_cast<u64*>(join_off.p),
                              d_small + 1, ws.p, stream));
@@ -744,7 +823,7 @@ struct hl_engine {
       const u64 total = h_small[1];
       if (total == 0) return;
       const bool last = q + 1 == p.steps.size();
-      const bool filtered = js.fa >= 0;
+      const bool filtered = js.fa >= 0 || js.ea >= 0;
       K* out;
       u64 base = 0;
       if (last) {
@@ -763,7 +842,7 @@ struct hl_engine {
       HIPCK(hl::join_expand<K>(cur, n, static_cast<u64*>(join_off.p),
                                static_cast<u32*>(join_start.p), inner, total, js,
                                static_cast<u64*>(join_parts.p), filtered ? out : out + base,
-                               d_cursor, stream));
+                               d_cursor, stream, kt()));
       u64 produced = total;
       if (filtered) {
         HIPCK(hipMemcpyAsync(h_small, d_cursor, sizeof(u64), hipMemcpyDeviceToHost, stream));
@@ -806,7 +885,8 @@ struct hl_engine {
       reserve(ws, hl::sort_workspace_bytes(R.n_cand), hl::sort_workspace_bytes(R.n_cand) * 2);
       K* sorted = nullptr;
       mark(HL_PHASE_SORT);
-      HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_cand, bits, ws.p, stream, &sorted));
+      HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_cand, bits, ws.p, stream, &sorted,
+                              kt()));
       Buf& sbuf = (sorted == kp<K>(R.cand)) ? R.cand : alt;
       Buf& obuf = (sorted == kp<K>(R.cand)) ? alt : R.cand;
       reserve(ws, hl::unique_diff_workspace_bytes(R.n_cand),
@@ -814,7 +894,7 @@ struct hl_engine {
       mark(HL_PHASE_DIFF);
       // delta is written over the sorted candidates, then takes their buffer
       HIPCK(hl::unique_diff<K>(kp<K>(sbuf), R.n_cand, kp<K>(R.full), R.n_full, kp<K>(obuf),
-                               kp<K>(sbuf), d_small + 2 * q, ws.p, stream));
+                               kp<K>(sbuf), d_small + 2 * q, ws.p, stream, kt()));
       std::swap(R.delta, sbuf);
     }
     HIPCK(hipMemcpyAsync(h_small, d_small, 2 * idbs.size() * sizeof(u64), hipMemcpyDeviceToHost,
@@ -841,7 +921,8 @@ struct hl_engine {
       } else {
         reserve(R.full_spare, (F + D) * sizeof(K), u64((double(F) + ebm_k * double(D)) * sizeof(K)));
         reserve(ws, hl::merge_workspace_bytes(F, D), hl::merge_workspace_bytes(F, D) * 2);
-        HIPCK(hl::merge<K>(kp<K>(R.full), F, kp<K>(R.delta), D, kp<K>(R.full_spare), ws.p, stream));
+        HIPCK(hl::merge<K>(kp<K>(R.full), F, kp<K>(R.delta), D, kp<K>(R.full_spare), ws.p, stream,
+                           kt()));
         std::swap(R.full, R.full_spare);
       }
       R.n_full = F + D;
@@ -878,6 +959,7 @@ struct hl_engine {
     auto t0 = std::chrono::steady_clock::now();
     st = hl_stats{};
     reuses = 0;
+    ktimer.reset();
     mem.reset_counters();
     marks.clear();
     ev_used = 0;
@@ -953,7 +1035,7 @@ template <typename F>
 int guard(hl_engine* e, F&& f) {
   if (!e) return HL_E_INVALID;
   try {
-    HIPCK(hipSetDevice(e->device));
+    if (e->device >= 0) HIPCK(hipSetDevice(e->device));
     f();
     e->err.clear();
     return HL_OK;
@@ -994,6 +1076,14 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   for (u32 r : o.reserved)
     if (r) return HL_E_INVALID;
   if (o.arena && o.arena_bytes < 4096) return HL_E_INVALID;
+  if (o.device == -1) {
+    // planning-only engine: declarations and programs, no device work
+    hl_engine* e = new (std::nothrow) hl_engine();
+    if (!e) return HL_E_NOMEM;
+    e->device = -1;
+    *out = e;
+    return HL_OK;
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || o.device < 0 || o.device >= ndev) {
     (void)hipGetLastError();
@@ -1027,6 +1117,10 @@ int hl_create(const hl_options* opt, hl_engine** out) {
 
 void hl_destroy(hl_engine* e) {
   if (!e) return;
+  if (e->device < 0) {
+    delete e;
+    return;
+  }
   (void)hipSetDevice(e->device);
   if (e->stream) (void)hipStreamSynchronize(e->stream);
   e->mem.release_all();
@@ -1055,6 +1149,7 @@ int hl_declare(hl_engine* e, const char* name, uint32_t arity, int32_t is_edb) {
 
 static int load_impl(hl_engine* e, const char* name, const uint32_t* rows, uint64_t n, bool dev) {
   return guard(e, [&] {
+    if (e->device < 0) fail(HL_E_STATE, "planning-only engine (device -1)");
     Relation& R = e->rels[e->find_or_fail(name)];
     if (!R.edb) fail(HL_E_INVALID, "load into an IDB relation");
     if (n == 0) return;
@@ -1109,7 +1204,10 @@ int hl_program(hl_engine* e, const char* text) {
 }
 
 int hl_run(hl_engine* e, hl_stats* stats) {
-  return guard(e, [&] { e->run(stats); });
+  return guard(e, [&] {
+    if (e->device < 0) fail(HL_E_STATE, "planning-only engine (device -1)");
+    e->run(stats);
+  });
 }
 
 int hl_count(hl_engine* e, const char* name, uint64_t* n) {
@@ -1142,6 +1240,17 @@ int hl_iteration_counts(hl_engine* e, const char* name, int32_t which, uint64_t*
   });
 }
 
+int hl_kernel_stats(hl_engine* e, int32_t kernel, uint64_t* launches, double* ms,
+                    uint64_t* algorithmic_bytes) {
+  return guard(e, [&] {
+    if (kernel < 0 || kernel >= hl::K_COUNT) fail(HL_E_INVALID, "unknown kernel id");
+    const EventTimer::Total& t = e->ktimer.totals[kernel];
+    if (launches) *launches = t.launches;
+    if (ms) *ms = t.ms;
+    if (algorithmic_bytes) *algorithmic_bytes = t.bytes;
+  });
+}
+
 const char* hl_last_error(hl_engine* e) { return e ? e->err.c_str() : "null engine"; }
 
 const char* hl_strerror(int code) {
@@ -1161,6 +1270,7 @@ const char* hl_strerror(int code) {
 
 int hl_sort_keys(hl_engine* e, void* d_keys, uint64_t n, uint32_t key_bytes, uint32_t bits) {
   return guard(e, [&] {
+    if (e->device < 0) fail(HL_E_STATE, "planning-only engine (device -1)");
     if (!valid_key_bytes(key_bytes)) fail(HL_E_INVALID, "key_bytes must be 4 or 8");
     if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "2^32 or more keys");
     if (n <= 1) return;
@@ -1191,6 +1301,7 @@ int hl_unique_diff(hl_engine* e, const void* d_sorted, uint64_t n, const void* d
                    uint64_t n_full, void* d_out, uint64_t* n_out, uint64_t* n_unique,
                    uint32_t key_bytes) {
   return guard(e, [&] {
+    if (e->device < 0) fail(HL_E_STATE, "planning-only engine (device -1)");
     if (!valid_key_bytes(key_bytes)) fail(HL_E_INVALID, "key_bytes must be 4 or 8");
     if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "2^32 or more keys");
     if ((n && (!d_sorted || !d_out)) || (n_full && !d_full)) fail(HL_E_INVALID, "null buffer");
@@ -1217,6 +1328,7 @@ int hl_unique_diff(hl_engine* e, const void* d_sorted, uint64_t n, const void* d
 int hl_merge(hl_engine* e, const void* d_a, uint64_t na, const void* d_b, uint64_t nb,
              void* d_out, uint32_t key_bytes) {
   return guard(e, [&] {
+    if (e->device < 0) fail(HL_E_STATE, "planning-only engine (device -1)");
     if (!valid_key_bytes(key_bytes)) fail(HL_E_INVALID, "key_bytes must be 4 or 8");
     if ((na && !d_a) || (nb && !d_b) || (na + nb && !d_out)) fail(HL_E_INVALID, "null buffer");
     e->reserve(e->ws, hl::merge_workspace_bytes(na, nb), hl::merge_workspace_bytes(na, nb));
@@ -1234,6 +1346,7 @@ int hl_hisa_query(hl_engine* e, const void* d_keys, uint64_t n, uint32_t key_byt
                   uint32_t shift, const uint32_t* d_queries, uint64_t nq, uint64_t* d_start,
                   uint32_t* d_len, uint64_t* n_runs) {
   return guard(e, [&] {
+    if (e->device < 0) fail(HL_E_STATE, "planning-only engine (device -1)");
     if (!valid_key_bytes(key_bytes)) fail(HL_E_INVALID, "key_bytes must be 4 or 8");
     if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "2^32 or more keys");
     if (shift >= 8 * key_bytes) fail(HL_E_INVALID, "shift out of range");

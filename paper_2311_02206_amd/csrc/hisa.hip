@@ -168,12 +168,15 @@ hipError_t hisa_count_runs(const K* keys, u64 n, int shift, u64* d_runs, hipStre
 }
 
 template <typename K>
-hipError_t hisa_build(const K* keys, u64 n, int shift, Slot* table, u64 cap, hipStream_t s) {
+hipError_t hisa_build(const K* keys, u64 n, int shift, Slot* table, u64 cap, hipStream_t s,
+                      LaunchTimer* timer) {
   if (n == 0) return hipSuccess;
   if (cap == 0 || cap > (u64(1) << 32)) return hipErrorInvalidValue;
   const u64 blocks = (n + kNT - 1) / kNT;
   if (blocks >= (u64(1) << 31)) return hipErrorInvalidValue;
+  if (timer) timer->begin(K_HISA_BUILD, s);
   build_kernel<K><<<dim3(u32(blocks)), kNT, 0, s>>>(keys, n, shift, table, cap);
+  if (timer) timer->end(K_HISA_BUILD, s, n * sizeof(K));
   return hipGetLastError();
 }
 
@@ -226,7 +229,8 @@ hipError_t unpack_rows(const K* keys, u64 n, int arity, int w, u32* rows, hipStr
 
 #define HL_INSTANTIATE(K)                                                                    \
   template hipError_t hisa_count_runs<K>(const K*, u64, int, u64*, hipStream_t);            \
-  template hipError_t hisa_build<K>(const K*, u64, int, Slot*, u64, hipStream_t);           \
+  template hipError_t hisa_build<K>(const K*, u64, int, Slot*, u64, hipStream_t,            \
+                                    LaunchTimer*);                                            \
   template hipError_t pack_rows<K>(const u32*, u64, int, int, K*, hipStream_t);             \
   template hipError_t swap_cols<K>(const K*, u64, int, K*, hipStream_t);                    \
   template hipError_t unpack_rows<K>(const K*, u64, int, int, u32*, hipStream_t);

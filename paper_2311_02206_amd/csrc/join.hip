@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
     }
   }
   __syncthreads();
-  const bool filtered = js.fa >= 0;
+  const bool filtered = js.fa >= 0 || js.ea >= 0;
   const K mask = (K(1) << js.w) - 1;
   for (u32 kk = 0; kk < lb; kk += kNT) {
     const u32 k = kk + threadIdx.x;
@@ -155,7 +155,8 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
       const K o = inner[pos] & mask;
       const K x = pick(js.src0, c0, c1, o), y = pick(js.src1, c0, c1, o);
       v = (x << js.w) | y;
-      keep = !filtered || pick(js.fa, c0, c1, o) != pick(js.fb, c0, c1, o);
+      keep = (js.fa < 0 || pick(js.fa, c0, c1, o) != pick(js.fb, c0, c1, o)) &&
+             (js.ea < 0 || pick(js.ea, c0, c1, o) == pick(js.eb, c0, c1, o));
     }
     emit(out, j, v, keep, filtered, cursor);
   }
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
 template <typename K>
 __global__ __launch_bounds__(kNT) void project_kernel(const K* in, u64 n, JoinSpec js, K* out,
                                                       u64* cursor) {
-  const bool filtered = js.fa >= 0;
+  const bool filtered = js.fa >= 0 || js.ea >= 0;
   const K mask = (K(1) << js.w) - 1;
   const u64 stride = u64(gridDim.x) * kNT;
   // the loop bound is uniform per wave so the compaction ballot sees every lane
@@ -177,7 +178,8 @@ __global__ __launch_bounds__(kNT) void project_kernel(const K* in, u64 n, JoinSp
       const K c0 = k >> js.w, c1 = k & mask;
       const K x = pick(js.src0, c0, c1, K(0)), y = pick(js.src1, c0, c1, K(0));
       v = (x << js.w) | y;
-      keep = !filtered || pick(js.fa, c0, c1, K(0)) != pick(js.fb, c0, c1, K(0));
+      keep = (js.fa < 0 || pick(js.fa, c0, c1, K(0)) != pick(js.fb, c0, c1, K(0))) &&
+             (js.ea < 0 || pick(js.ea, c0, c1, K(0)) == pick(js.eb, c0, c1, K(0)));
     }
     emit(out, i, v, keep, filtered, cursor);
   }
@@ -189,14 +191,16 @@ u64 tiles_of(u64 n) { return (n + kTile - 1) / kTile; }
 
 template <typename K>
 hipError_t join_probe(const K* outer, u64 n, const JoinSpec& js, const Slot* table, u64 cap,
-                      u32* start, u32* len, hipStream_t s) {
+                      u32* start, u32* len, hipStream_t s, LaunchTimer* timer) {
   if (n == 0) return hipSuccess;
   if (cap == 0 || cap > (u64(1) << 32) || js.outer_col < 0 || js.outer_col > 1)
     return hipErrorInvalidValue;
   const u64 blocks = (n + kNT - 1) / kNT;
   if (blocks >= (u64(1) << 31)) return hipErrorInvalidValue;
+  if (timer) timer->begin(K_JOIN_PROBE, s);
   probe_kernel<K><<<dim3(u32(blocks)), kNT, 0, s>>>(outer, n, js.outer_col, js.w, table, cap,
                                                     start, len);
+  if (timer) timer->end(K_JOIN_PROBE, s, n * (sizeof(K) + sizeof(Slot) + 2 * sizeof(u32)));
   return hipGetLastError();
 }
 
@@ -205,7 +209,7 @@ u64 join_parts(u64 n_outer, u64 total) { return tiles_of(n_outer + total) + 1; }
 template <typename K>
 hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* start,
                        const K* inner, u64 total, const JoinSpec& js, u64* parts, K* out,
-                       u64* cursor, hipStream_t s) {
+                       u64* cursor, hipStream_t s, LaunchTimer* timer) {
   if (total == 0) return hipSuccess;
   if (n_outer >= (u64(1) << 32)) return hipErrorInvalidValue;
   const u64 nt = tiles_of(n_outer + total);
@@ -215,8 +219,13 @@ hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* s
                                                                        parts, nparts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (timer) timer->begin(K_JOIN_EXPAND, s);
   expand_kernel<K><<<dim3(u32(nt)), kNT, 0, s>>>(outer, n_outer, off, start, inner, total, js,
                                                  parts, out, cursor);
+  // by definition: each inner tuple of a matched run read once, each output
+  // written once, each outer tuple with its offset and run start read once
+  if (timer) timer->end(K_JOIN_EXPAND, s,
+                        2 * total * sizeof(K) + n_outer * (sizeof(K) + sizeof(u64) + sizeof(u32)));
   return hipGetLastError();
 }
 
@@ -231,9 +240,10 @@ hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, 
 
 #define HL_INSTANTIATE(K)                                                                     \
   template hipError_t join_probe<K>(const K*, u64, const JoinSpec&, const Slot*, u64, u32*,  \
-                                    u32*, hipStream_t);                                       \
+                                    u32*, hipStream_t, LaunchTimer*);                         \
   template hipError_t join_expand<K>(const K*, u64, const u64*, const u32*, const K*, u64,  \
-                                     const JoinSpec&, u64*, K*, u64*, hipStream_t);           \
+                                     const JoinSpec&, u64*, K*, u64*, hipStream_t,            \
+                                     LaunchTimer*);                                           \
   template hipError_t project<K>(const K*, u64, const JoinSpec&, K*, u64*, hipStream_t);
 HL_INSTANTIATE(u32)
 HL_INSTANTIATE(u64)

@@ -24,6 +24,27 @@ struct alignas(16) Slot {
 
 inline u64 align_up(u64 x, u64 a) { return (x + a - 1) / a * a; }
 
+// Kernels whose launches can be timed one by one with HIP events.
+enum KernelId {
+  K_RADIX_HIST = 0,
+  K_RADIX_SCATTER = 1,
+  K_UNIQUE_DIFF = 2,
+  K_MERGE = 3,
+  K_JOIN_PROBE = 4,
+  K_JOIN_EXPAND = 5,
+  K_HISA_BUILD = 6,
+  K_COUNT = 7
+};
+
+// Optional launch timer: launchers call begin() right before and end()
+// right after a timed kernel, passing the bytes the kernel must move by
+// definition (its inputs read once, its outputs written once).
+struct LaunchTimer {
+  virtual void begin(int kernel, hipStream_t s) = 0;
+  virtual void end(int kernel, hipStream_t s, u64 algorithmic_bytes) = 0;
+  virtual ~LaunchTimer() {}
+};
+
 // ---------------------------------------------------------------- scan
 u64 scan_workspace_bytes(u64 n);
 // Exclusive prefix sum of u32 values into u64 offsets; *d_total (device)
@@ -36,7 +57,8 @@ u64 sort_workspace_bytes(u64 n);
 // `keys` and `alt`; *sorted receives whichever holds the result (the other
 // one is free afterwards).  n must be below 2^32.
 template <typename K>
-hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted);
+hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted,
+                      LaunchTimer* timer = nullptr);
 
 // --------------------------------------------- unique + set difference
 u64 unique_diff_workspace_bytes(u64 n);
@@ -45,13 +67,14 @@ u64 unique_diff_workspace_bytes(u64 n);
 // number of distinct keys in `sorted`.  n must be below 2^32.
 template <typename K>
 hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
-                       u64* d_counts, void* ws, hipStream_t s);
+                       u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer = nullptr);
 
 // --------------------------------------------------------------- merge
 u64 merge_workspace_bytes(u64 na, u64 nb);
 // out = merge of two ascending arrays (ties take a first).
 template <typename K>
-hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipStream_t s);
+hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipStream_t s,
+                 LaunchTimer* timer = nullptr);
 
 // ---------------------------------------------------------------- HISA
 // Counts the runs of equal join key (key >> shift) of a sorted array.
@@ -60,7 +83,8 @@ hipError_t hisa_count_runs(const K* keys, u64 n, int shift, u64* d_runs, hipStre
 // Inserts every run into an open-addressing table of `cap` slots, which
 // must exceed the number of runs and start zeroed (see fill_zero).
 template <typename K>
-hipError_t hisa_build(const K* keys, u64 n, int shift, Slot* table, u64 cap, hipStream_t s);
+hipError_t hisa_build(const K* keys, u64 n, int shift, Slot* table, u64 cap, hipStream_t s,
+                      LaunchTimer* timer = nullptr);
 // Looks up nq join keys; len 0 means absent.
 hipError_t hisa_probe(const Slot* table, u64 cap, const u32* q, u64 nq, u64* start, u32* len,
                       hipStream_t s);
@@ -81,24 +105,27 @@ hipError_t unpack_rows(const K* keys, u64 n, int arity, int w, u32* rows, hipStr
 // ---------------------------------------------------------------- join
 // Values of the current pair (c0, c1) and of the inner tuple's non-join
 // column are numbered 0, 1, 2.  The output pair is (v[src0], v[src1]); a
-// filter (fa >= 0) keeps it only when v[fa] != v[fb].
+// filter fa >= 0 keeps it only when v[fa] != v[fb], a filter ea >= 0 only
+// when v[ea] == v[eb] (a variable repeated in an atom, or an atom whose two
+// variables are both already bound).
 struct JoinSpec {
   int outer_col;  // which column of the outer pair is the join key
   int src0, src1;
   int fa, fb;
+  int ea, eb;
   int w;  // id bits of a column
 };
 
 template <typename K>
 hipError_t join_probe(const K* outer, u64 n, const JoinSpec& js, const Slot* table, u64 cap,
-                      u32* start, u32* len, hipStream_t s);
+                      u32* start, u32* len, hipStream_t s, LaunchTimer* timer = nullptr);
 u64 join_parts(u64 n_outer, u64 total);  // entries of the partition array
 // Expands every (outer, inner run) pair.  Without a filter, output j goes
 // to out[j]; with one, survivors are appended at *cursor (device, u64).
 template <typename K>
 hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* start,
                        const K* inner, u64 total, const JoinSpec& js, u64* parts, K* out,
-                       u64* cursor, hipStream_t s);
+                       u64* cursor, hipStream_t s, LaunchTimer* timer = nullptr);
 // A rule body of one atom: projects (and filters) every outer pair.
 template <typename K>
 hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, hipStream_t s);

@@ -148,7 +148,8 @@ u64 sort_workspace_bytes(u64 n) {
 }
 
 template <typename K>
-hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted) {
+hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted,
+                      LaunchTimer* timer) {
   *sorted = keys;
   if (n <= 1 || bits <= 0) return hipSuccess;
   if (n >= (u64(1) << 32)) return hipErrorInvalidValue;
@@ -163,12 +164,16 @@ hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s,
   K* src = keys;
   K* dst = alt;
   for (int shift = 0; shift < bits; shift += kBits) {
+    if (timer) timer->begin(K_RADIX_HIST, s);
     rs_hist_kernel<K><<<dim3(u32(nt)), kNT, 0, s>>>(src, n, shift, counts, u32(nt));
+    if (timer) timer->end(K_RADIX_HIST, s, n * sizeof(K) + m * sizeof(u32));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = scan_u32_u64(counts, m, offsets, nullptr, p, s);
     if (e != hipSuccess) return e;
+    if (timer) timer->begin(K_RADIX_SCATTER, s);
     rs_scatter_kernel<K><<<dim3(u32(nt)), kNT, 0, s>>>(src, dst, n, shift, offsets, u32(nt));
+    if (timer) timer->end(K_RADIX_SCATTER, s, 2 * n * sizeof(K) + m * sizeof(u64));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     K* t = src;
@@ -179,7 +184,9 @@ hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s,
   return hipSuccess;
 }
 
-template hipError_t radix_sort<u32>(u32*, u32*, u64, int, void*, hipStream_t, u32**);
-template hipError_t radix_sort<u64>(u64*, u64*, u64, int, void*, hipStream_t, u64**);
+template hipError_t radix_sort<u32>(u32*, u32*, u64, int, void*, hipStream_t, u32**,
+                                    LaunchTimer*);
+template hipError_t radix_sort<u64>(u64*, u64*, u64, int, void*, hipStream_t, u64**,
+                                    LaunchTimer*);
 
 }  // namespace hl

@@ -208,7 +208,7 @@ u64 unique_diff_workspace_bytes(u64 n) {
 
 template <typename K>
 hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
-                       u64* d_counts, void* ws, hipStream_t s) {
+                       u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer) {
   zero_u64x2_kernel<<<1, 1, 0, s>>>(d_counts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n == 0) return e;
@@ -219,8 +219,12 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   p += align_up(nt * sizeof(u32), 256);
   u64* tile_off = reinterpret_cast<u64*>(p);
   p += align_up(nt * sizeof(u64), 256);
+  if (timer) timer->begin(K_UNIQUE_DIFF, s);
   ud_select_kernel<K><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
                                                       d_counts + 1);
+  // by definition: every candidate read once, each kept key written once;
+  // the count of kept keys is not known here, so only the reads are counted
+  if (timer) timer->end(K_UNIQUE_DIFF, s, n * sizeof(K));
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = scan_u32_u64(tile_counts, nt, tile_off, d_counts, p, s);
@@ -234,7 +238,8 @@ u64 merge_workspace_bytes(u64 na, u64 nb) {
 }
 
 template <typename K>
-hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipStream_t s) {
+hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipStream_t s,
+                 LaunchTimer* timer) {
   const u64 n = na + nb;
   if (n == 0) return hipSuccess;
   const u64 nt = mg_tiles(n);
@@ -245,15 +250,19 @@ hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipSt
                                                                            nparts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
+  if (timer) timer->begin(K_MERGE, s);
   merge_kernel<K><<<dim3(u32(nt)), kMgNT, 0, s>>>(a, na, b, nb, parts, out);
+  if (timer) timer->end(K_MERGE, s, 2 * n * sizeof(K));
   return hipGetLastError();
 }
 
 template hipError_t unique_diff<u32>(const u32*, u64, const u32*, u64, u32*, u32*, u64*, void*,
-                                     hipStream_t);
+                                     hipStream_t, LaunchTimer*);
 template hipError_t unique_diff<u64>(const u64*, u64, const u64*, u64, u64*, u64*, u64*, void*,
-                                     hipStream_t);
-template hipError_t merge<u32>(const u32*, u64, const u32*, u64, u32*, void*, hipStream_t);
-template hipError_t merge<u64>(const u64*, u64, const u64*, u64, u64*, void*, hipStream_t);
+                                     hipStream_t, LaunchTimer*);
+template hipError_t merge<u32>(const u32*, u64, const u32*, u64, u32*, void*, hipStream_t,
+                               LaunchTimer*);
+template hipError_t merge<u64>(const u64*, u64, const u64*, u64, u64*, void*, hipStream_t,
+                               LaunchTimer*);
 
 }  // namespace hl

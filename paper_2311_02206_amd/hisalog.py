@@ -25,14 +25,17 @@ HL_E_STATE = -4
 HL_E_CAPACITY = -5
 HL_E_UNSUPPORTED = -6
 HL_FLAG_NO_EBM = 0x1
+HL_FLAG_KERNEL_TIMING = 0x2
+KERNELS = ("radix_hist", "radix_scatter", "unique_diff", "merge", "join_probe", "join_expand",
+           "hisa_build")
 PHASES = ("index_edb", "join", "sort", "diff", "merge", "index")
 
 # Symbols of include/hisalog.h, in declaration order.
 EXPORTS = (
     "hl_options_init", "hl_create", "hl_destroy", "hl_declare", "hl_load", "hl_load_device",
     "hl_index", "hl_program", "hl_run", "hl_count", "hl_fetch", "hl_fetch_device",
-    "hl_iteration_counts", "hl_last_error", "hl_strerror", "hl_sort_keys", "hl_unique_diff",
-    "hl_merge", "hl_hisa_query",
+    "hl_iteration_counts", "hl_kernel_stats", "hl_last_error", "hl_strerror", "hl_sort_keys",
+    "hl_unique_diff", "hl_merge", "hl_hisa_query",
 )
 
 
@@ -96,6 +99,7 @@ def lib() -> ctypes.CDLL:
         "hl_fetch": [vp, cp, vp, u64, pu64],
         "hl_fetch_device": [vp, cp, vp, u64, pu64],
         "hl_iteration_counts": [vp, cp, i32, pu64, u32, pu32],
+        "hl_kernel_stats": [vp, i32, pu64, ctypes.POINTER(ctypes.c_double), pu64],
         "hl_last_error": [vp],
         "hl_strerror": [ctypes.c_int],
         "hl_sort_keys": [vp, vp, u64, u32, u32],
@@ -145,12 +149,13 @@ class Engine:
     """One hisalog engine on one GPU (see include/hisalog.h)."""
 
     def __init__(self, device: int = 0, stream=None, arena=None, ebm: bool = True,
-                 ebm_k: float = 8.0, load_factor: float = 0.8, budget_bytes: int = 0):
+                 ebm_k: float = 8.0, load_factor: float = 0.8, budget_bytes: int = 0,
+                 kernel_timing: bool = False):
         L = lib()
         opt = Options()
         L.hl_options_init(ctypes.byref(opt))
         opt.device = device
-        opt.flags = 0 if ebm else HL_FLAG_NO_EBM
+        opt.flags = (0 if ebm else HL_FLAG_NO_EBM) | (HL_FLAG_KERNEL_TIMING if kernel_timing else 0)
         opt.ebm_k = ebm_k
         opt.hash_load_factor = load_factor
         opt.hbm_budget_bytes = budget_bytes
@@ -260,6 +265,17 @@ class Engine:
         self._check(self._L.hl_iteration_counts(self._h, name.encode(), which, buf, cap,
                                                 ctypes.byref(n)), "hl_iteration_counts")
         return [int(buf[i]) for i in range(min(n.value, cap))]
+
+    def kernel_stats(self) -> dict:
+        """Per-kernel (launches, ms, algorithmic bytes) of the last run; needs
+        ``kernel_timing=True``."""
+        out = {}
+        for k, name in enumerate(KERNELS):
+            n, ms, b = ctypes.c_uint64(), ctypes.c_double(), ctypes.c_uint64()
+            self._check(self._L.hl_kernel_stats(self._h, k, ctypes.byref(n), ctypes.byref(ms),
+                                                ctypes.byref(b)), "hl_kernel_stats")
+            out[name] = (n.value, ms.value, b.value)
+        return out
 
     # --------------------------------------------------------- primitives
     def sort_keys(self, keys, bits: int = 0):

@@ -1,0 +1,115 @@
+"""GPU parity at the benchmark's full sizes, in the launch configuration
+bench.py times (one engine per program, default options).  The std::set
+oracle cannot run at these sizes (tens of GB and hours), so the references
+are exact independent computations the oracle's pins already tie to it:
+  * Reach: per-source BFS gives the tuple count and, through the shortest
+    distance histogram, every per-iteration delta size; sampled sources are
+    compared row by row;
+  * SG on a tree: the closed form gives the count and per-iteration deltas;
+    sampled rows are checked against the same-depth definition, and the
+    output must be sorted, unique, irreflexive and symmetric.
+"""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PROG = {n: open(os.path.join(ROOT, "workloads", "programs", n + ".dl")).read()
+        for n in ("reach", "sg")}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def engine(program, edb, idb):
+    import torch
+    import paper_2311_02206_amd as pkg
+    torch.cuda.set_device(0)
+    e = pkg.Engine(device=0, stream=torch.cuda.current_stream())
+    for n in edb:
+        e.declare(n, 2, True)
+    for n, a in idb.items():
+        e.declare(n, a, False)
+    for n, rows in edb.items():
+        e.load(n, rows)
+    e.program(program)
+    return e
+
+
+def check_reach(wl, sources):
+    E = wl["edb"]["Edge"]
+    e = engine(PROG["reach"], wl["edb"], {"Reach": 2})
+    try:
+        st = e.run()
+        say(f"  ran: {st.idb_tuples} tuples, {st.iterations} iterations, {st.seconds:.3f} s")
+        total, hist = oracle.reach_bfs_histogram(wl["n_nodes"], E)
+        assert e.count("Reach") == total
+        assert e.iteration_counts("Reach", 0) == oracle.reach_deltas_from_histogram(hist)
+        R = e.fetch("Reach")
+        key = (R[:, 0].astype(np.uint64) << np.uint64(32)) | R[:, 1]
+        assert np.all(key[1:] > key[:-1])
+        for s in sources:
+            lo, hi = np.searchsorted(R[:, 0], [s, s + 1])
+            assert np.array_equal(R[lo:hi, 1], oracle.reach_from(wl["n_nodes"], E, s)), s
+        return st
+    finally:
+        e.close()
+
+
+def test_reach_rmat16_200k():
+    say("reach rmat 2^16 / 200k")
+    wl = workloads.reach_rmat16()
+    st = check_reach(wl, [0, 1, 2, 3, 7, 100, 4095, 20000, 65535])
+    assert st.key_bytes == 4
+
+
+def test_sg_tree_50k():
+    say("sg tree 50k")
+    wl = workloads.sg_tree_50k()
+    E = wl["edb"]["Edge"]
+    e = engine(PROG["sg"], wl["edb"], {"SG": 2})
+    try:
+        st = e.run()
+        say(f"  ran: {st.idb_tuples} tuples, {st.iterations} iterations, {st.seconds:.3f} s")
+        total, deltas = oracle.sg_tree_closed_form(E)
+        assert e.count("SG") == total
+        assert e.iteration_counts("SG", 0) == deltas
+        S = e.fetch("SG")
+        n = int(E.max()) + 1
+        depth = np.zeros(n, dtype=np.int64)
+        for p, c in E.tolist():
+            depth[c] = depth[p] + 1
+        key = (S[:, 0].astype(np.uint64) << np.uint64(32)) | S[:, 1]
+        assert np.all(key[1:] > key[:-1])
+        assert np.all(S[:, 0] != S[:, 1])
+        rng = np.random.default_rng(1)
+        idx = rng.integers(0, len(S), 100_000)
+        assert np.all(depth[S[idx, 0]] == depth[S[idx, 1]])
+        # symmetry on the sample
+        sw = (S[idx, 1].astype(np.uint64) << np.uint64(32)) | S[idx, 0]
+        pos = np.searchsorted(key, sw)
+        assert np.all(key[np.minimum(pos, len(key) - 1)] == sw)
+        # every row of a sampled node: exactly the other nodes of its depth
+        for v in (1, 7, 1234, 49_999):
+            lo, hi = np.searchsorted(S[:, 0], [v, v + 1])
+            want = np.nonzero((depth == depth[v]) & (np.arange(n) != v))[0]
+            assert np.array_equal(S[lo:hi, 1].astype(np.int64), want)
+    finally:
+        e.close()
+
+
+def test_reach_er_2p22_subcritical():
+    say("reach er 2^22 subcritical")
+    wl = workloads.reach_er_2p22()
+    st = check_reach(wl, [0, 1, 12345, (1 << 22) - 1])
+    assert st.key_bytes == 8

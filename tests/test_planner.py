@@ -1,0 +1,81 @@
+"""CPU checks of the library's host logic on a planning-only engine
+(device -1): parsing, the chain-join planner, and error codes."""
+
+import os
+import random
+import sys
+
+import pytest
+
+import paper_2311_02206_amd as pkg
+from paper_2311_02206_amd import hisalog as H
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, os.path.join(ROOT, "tests"))
+
+
+def planner(decls):
+    e = pkg.Engine(device=-1)
+    for name, edb in decls:
+        e.declare(name, 2, edb)
+    return e
+
+
+def code_of(fn):
+    try:
+        fn()
+        return H.HL_OK
+    except pkg.HlError as err:
+        return err.code
+
+
+@pytest.mark.parametrize("prog,decls", [
+    ("reach", [("Edge", True), ("Reach", False)]),
+    ("sg", [("Edge", True), ("SG", False)]),
+    ("cspa_shaped", [("Assign", True), ("Dereference", True), ("ValueFlow", False),
+                     ("ValueAlias", False), ("MemoryAlias", False)]),
+])
+def test_shipped_programs_plan(prog, decls):
+    text = open(os.path.join(ROOT, "workloads", "programs", prog + ".dl")).read()
+    with planner(decls) as e:
+        e.program(text)
+
+
+def test_error_codes():
+    with planner([("E", True), ("R", False)]) as e:
+        assert code_of(lambda: e.program("R(x, y) :- E(x, .")) == H.HL_E_INVALID
+        assert code_of(lambda: e.program("R(x, y) :- Nope(x, y).")) == H.HL_E_INVALID
+        assert code_of(lambda: e.program("R(x, _) :- E(x, y).")) == H.HL_E_INVALID
+        assert code_of(lambda: e.program("R(x, w) :- E(x, y).")) == H.HL_E_INVALID
+        assert code_of(lambda: e.program("E(x, y) :- R(x, y).")) == H.HL_E_INVALID
+        assert code_of(lambda: e.program("R(x, y) :- E(x, y), a != y.")) == H.HL_E_INVALID
+        # cross product and three live variables are outside the chain-join form
+        assert code_of(lambda: e.program("R(x, y) :- E(x, a), E(y, b).")) == H.HL_E_UNSUPPORTED
+        assert code_of(lambda: e.program(
+            "R(x, y) :- E(x, a), E(a, b), E(b, y), E(x, y), E(a, y), E(b, x).")) in (
+            H.HL_OK, H.HL_E_UNSUPPORTED)
+        # shapes that reduce to equality tests are planned
+        assert code_of(lambda: e.program("R(x, x) :- E(x, x).")) == H.HL_OK
+        assert code_of(lambda: e.program("R(x, y) :- E(x, y), E(y, x).")) == H.HL_OK
+        assert code_of(lambda: e.load("E", [[1, 2]])) == H.HL_E_STATE
+        assert code_of(lambda: e.run()) == H.HL_E_STATE
+    e = pkg.Engine(device=-1)
+    assert code_of(lambda: e.declare("T", 3, False)) == H.HL_E_UNSUPPORTED
+    assert code_of(lambda: e.declare("bad name", 2, False)) == H.HL_E_INVALID
+    e.declare("T", 2, False)
+    assert code_of(lambda: e.declare("T", 2, False)) == H.HL_E_INVALID
+    e.close()
+
+
+def test_random_programs_mostly_plan():
+    from test_oracle_pins import random_program, render
+    rng = random.Random(77)
+    ok = unsupported = 0
+    for _ in range(300):
+        with planner([("E", True), ("F", True), ("P", False), ("Q", False)]) as e:
+            c = code_of(lambda: e.program(render(random_program(rng))))
+            assert c in (H.HL_OK, H.HL_E_UNSUPPORTED)
+            ok += c == H.HL_OK
+            unsupported += c == H.HL_E_UNSUPPORTED
+    print("planned", ok, "unsupported", unsupported)
+    assert ok >= 100
