@@ -47,19 +47,40 @@ __device__ __forceinline__ K pick(int src, K c0, K c1, K o) {
   return src == 0 ? c0 : (src == 1 ? c1 : o);
 }
 
+// One lane per outer tuple.  Outer arrays are sorted on (or grouped by)
+// their first column, so neighbouring tuples often share the join key: only
+// the first lane of each run of equal keys within a wave probes, and the
+// run's other lanes take its result by a wave shuffle.
 template <typename K>
 __global__ __launch_bounds__(kNT) void probe_kernel(const K* outer, u64 n, int outer_col, int w,
                                                     const Slot* table, u64 cap, u32* start,
                                                     u32* len) {
   const u64 i = u64(blockIdx.x) * kNT + threadIdx.x;
-  if (i >= n) return;
-  const K k = outer[i];
+  const bool valid = i < n;
   const K mask = (K(1) << w) - 1;
-  const u32 jc = outer_col == 0 ? u32(k >> w) : u32(k & mask);
+  u32 jc = 0, prev = 0;
+  if (valid) {
+    const K k = outer[i];
+    jc = outer_col == 0 ? u32(k >> w) : u32(k & mask);
+    if (i > 0) {
+      const K kp = outer[i - 1];
+      prev = outer_col == 0 ? u32(kp >> w) : u32(kp & mask);
+    }
+  }
+  const int lane = lane_id();
+  const bool leader = valid && (lane == 0 || i == 0 || jc != prev);
+  const u64 lm = ballot(leader);
   u32 st = 0, ln = 0;
-  if (!hisa_find(table, cap, jc, st, ln)) ln = 0;
-  start[i] = st;
-  len[i] = ln;
+  if (leader && !hisa_find(table, cap, jc, st, ln)) ln = 0;
+  // the leader of this lane's run: highest leader lane at or below it
+  const u64 upto = lm & ((lane == 63) ? ~u64(0) : ((u64(2) << lane) - 1));
+  const int src = upto ? 63 - __clzll((long long)upto) : lane;
+  st = __shfl(st, src, kWave);
+  ln = __shfl(ln, src, kWave);
+  if (valid) {
+    start[i] = st;
+    len[i] = ln;
+  }
 }
 
 // Merged order of outer tuple i (key off[i]) and output j (key j): the
@@ -84,21 +105,35 @@ __global__ void lbs_partition_kernel(const u64* off, u64 na, u64 nb, u64* parts,
   parts[t] = lbs_path(off, na, nb, diag);
 }
 
+// Block-level compaction of filtered outputs: survivors are gathered in LDS
+// in order, then the block claims one range of the output with a single
+// atomic and writes it coalesced.  (Order between blocks is arbitrary; the
+// new tuples are sorted afterwards.)
 template <typename K>
-__device__ __forceinline__ void emit(K* out, u64 j, K v, bool keep, bool filtered, u64* cursor) {
-  if (!filtered) {
-    if (keep) out[j] = v;
-    return;
+struct Compactor {
+  K* buf;         // LDS, kTile entries
+  u32* counter;   // LDS
+  u32* wsum;      // LDS, kNT / 64
+  __device__ void add(K v, bool keep) {
+    u32 tot;
+    u32 pos = block_exclusive_scan<kNT>(keep ? 1u : 0u, wsum, tot);
+    const u32 base = *counter;
+    if (keep) buf[base + pos] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) *counter = base + tot;
+    __syncthreads();
   }
-  // wave-level compaction: one atomic per wave and round
-  const u64 bal = ballot(keep);
-  if (bal == 0) return;
-  u64 base = 0;
-  if (lane_id() == 0) base = atomicAdd(reinterpret_cast<unsigned long long*>(cursor),
-                                       (unsigned long long)popc(bal));
-  base = __shfl(base, 0, kWave);
-  if (keep) out[base + popc(bal & lanemask_lt())] = v;
-}
+  __device__ void flush(K* out, u64* cursor, u64* s_base) {
+    const u32 n = *counter;
+    if (threadIdx.x == 0)
+      *s_base = n ? atomicAdd(reinterpret_cast<unsigned long long*>(cursor),
+                              (unsigned long long)n)
+                  : 0;
+    __syncthreads();
+    const u64 base = *s_base;
+    for (u32 k = threadIdx.x; k < n; k += kNT) out[base + k] = buf[k];
+  }
+};
 
 template <typename K>
 __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer, const u64* off,
@@ -141,6 +176,13 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   __syncthreads();
   const bool filtered = js.fa >= 0 || js.ea >= 0;
   const K mask = (K(1) << js.w) - 1;
+  __shared__ K s_keep[kTile];
+  __shared__ u32 s_count;
+  __shared__ u32 s_wsum[kNT / kWave];
+  __shared__ u64 s_base;
+  Compactor<K> cmp{s_keep, &s_count, s_wsum};
+  if (threadIdx.x == 0) s_count = 0;
+  __syncthreads();
   for (u32 kk = 0; kk < lb; kk += kNT) {
     const u32 k = kk + threadIdx.x;
     bool keep = false;
@@ -158,19 +200,27 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
       keep = (js.fa < 0 || pick(js.fa, c0, c1, o) != pick(js.fb, c0, c1, o)) &&
              (js.ea < 0 || pick(js.ea, c0, c1, o) == pick(js.eb, c0, c1, o));
     }
-    emit(out, j, v, keep, filtered, cursor);
+    if (filtered) cmp.add(v, keep);  // block-uniform branch
+    else if (k < lb) out[j] = v;
   }
+  if (filtered) cmp.flush(out, cursor, &s_base);
 }
 
 template <typename K>
 __global__ __launch_bounds__(kNT) void project_kernel(const K* in, u64 n, JoinSpec js, K* out,
                                                       u64* cursor) {
+  __shared__ K s_keep[kTile];
+  __shared__ u32 s_count;
+  __shared__ u32 s_wsum[kNT / kWave];
+  __shared__ u64 s_base;
   const bool filtered = js.fa >= 0 || js.ea >= 0;
   const K mask = (K(1) << js.w) - 1;
-  const u64 stride = u64(gridDim.x) * kNT;
-  // the loop bound is uniform per wave so the compaction ballot sees every lane
-  for (u64 base = u64(blockIdx.x) * kNT; base < n; base += stride) {
-    const u64 i = base + threadIdx.x;
+  const u64 t0 = u64(blockIdx.x) * kTile;
+  Compactor<K> cmp{s_keep, &s_count, s_wsum};
+  if (threadIdx.x == 0) s_count = 0;
+  __syncthreads();
+  for (u32 kk = 0; kk < kTile; kk += kNT) {
+    const u64 i = t0 + kk + threadIdx.x;
     bool keep = false;
     K v = 0;
     if (i < n) {
@@ -181,8 +231,10 @@ __global__ __launch_bounds__(kNT) void project_kernel(const K* in, u64 n, JoinSp
       keep = (js.fa < 0 || pick(js.fa, c0, c1, K(0)) != pick(js.fb, c0, c1, K(0))) &&
              (js.ea < 0 || pick(js.ea, c0, c1, K(0)) == pick(js.eb, c0, c1, K(0)));
     }
-    emit(out, i, v, keep, filtered, cursor);
+    if (filtered) cmp.add(v, keep);
+    else if (i < n) out[i] = v;
   }
+  if (filtered) cmp.flush(out, cursor, &s_base);
 }
 
 u64 tiles_of(u64 n) { return (n + kTile - 1) / kTile; }
@@ -232,8 +284,8 @@ hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* s
 template <typename K>
 hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  u64 blocks = (n + kNT - 1) / kNT;
-  if (blocks > 65536) blocks = 65536;
+  const u64 blocks = tiles_of(n);
+  if (blocks >= (u64(1) << 31)) return hipErrorInvalidValue;
   project_kernel<K><<<dim3(u32(blocks)), kNT, 0, s>>>(in, n, js, out, cursor);
   return hipGetLastError();
 }

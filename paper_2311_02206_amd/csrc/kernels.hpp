@@ -55,10 +55,12 @@ hipError_t scan_u32_u64(const u32* in, u64 n, u64* out, u64* d_total, void* ws, 
 u64 sort_workspace_bytes(u64 n);
 // LSD radix sort of the low `bits` bits of n keys.  Ping-pongs between
 // `keys` and `alt`; *sorted receives whichever holds the result (the other
-// one is free afterwards).  n must be below 2^32.
+// one is free afterwards).  n must be below 2^32.  If a look-back wait ran
+// out (the result is then wrong), a nonzero value is OR-ed into *d_err
+// (device memory) when d_err is given.
 template <typename K>
 hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted,
-                      LaunchTimer* timer = nullptr);
+                      LaunchTimer* timer = nullptr, u32* d_err = nullptr);
 
 // --------------------------------------------- unique + set difference
 u64 unique_diff_workspace_bytes(u64 n);

@@ -47,61 +47,85 @@ __device__ __forceinline__ u64 upper_bound(const K* a, u64 lo, u64 hi, K x) {
   return lo;
 }
 
+// One tile of sorted candidates: each thread takes kUdItems consecutive
+// keys, marks the first of each run of equal keys, and tests membership in
+// full by walking the (LDS-staged) slice of full forward from the
+// lower bound of its first key; one block scan places the survivors, which
+// are written compacted (in order) at the tile's start in tmp.
 template <typename K>
 __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, const K* full,
                                                           u64 nf, K* tmp, u32* tile_counts,
                                                           u64* d_unique) {
   __shared__ u64 range[2];
+  __shared__ K before;
   __shared__ u32 wsum[kUdNT / kWave];
   __shared__ u64 wsum64[kUdNT / kWave];
+  __shared__ K s_c[kUdTile];
   __shared__ K staged[kUdStage];
   const u32 tile = blockIdx.x;
   const u64 base = u64(tile) * kUdTile;
-  const u64 cnt = (n - base) < kUdTile ? (n - base) : kUdTile;
+  const u32 cnt = u32((n - base) < kUdTile ? (n - base) : kUdTile);
   if (threadIdx.x == 0) {
     range[0] = lower_bound(full, 0, nf, cand[base]);
     range[1] = upper_bound(full, range[0], nf, cand[base + cnt - 1]);
+    before = base > 0 ? cand[base - 1] : K(0);
   }
+  for (u32 k = threadIdx.x; k < cnt; k += kUdNT) s_c[k] = cand[base + k];
   __syncthreads();
   const u64 lo = range[0], hi = range[1];
   const u64 m = hi - lo;
   const bool in_lds = m <= kUdStage;
   if (in_lds) {
-    for (u64 k = threadIdx.x; k < m; k += kUdNT) staged[k] = full[lo + k];
+    for (u32 k = threadIdx.x; k < m; k += kUdNT) staged[k] = full[lo + k];
   }
   __syncthreads();
-  u32 carry = 0;
+  const u32 b = threadIdx.x * kUdItems;
+  u32 keep_bits = 0, nkeep = 0;
   u64 uniq = 0;
-  for (int j = 0; j < kUdItems; ++j) {
-    const u64 r = u64(j) * kUdNT + threadIdx.x;
-    const u64 i = base + r;
-    const bool valid = r < cnt;
-    bool keep = false;
-    K c = 0;
-    if (valid) {
-      c = cand[i];
-      bool first = (i == 0) || (cand[i - 1] != c);
-      if (first) {
-        ++uniq;
-        bool member;
-        if (in_lds) {
-          u64 p = lower_bound(staged, 0, m, c);
-          member = p < m && staged[p] == c;
-        } else {
-          u64 p = lower_bound(full, lo, hi, c);
-          member = p < hi && full[p] == c;
+  if (b < cnt) {
+    u64 p = in_lds ? lower_bound(staged, u64(0), m, s_c[b]) : 0;
+    K prevk = b > 0 ? s_c[b - 1] : before;
+#pragma unroll
+    for (int q = 0; q < kUdItems; ++q) {
+      const u32 idx = b + q;
+      if (idx < cnt) {
+        const K c = s_c[idx];
+        const bool first = (base + idx == 0) || prevk != c;
+        prevk = c;
+        if (first) {
+          ++uniq;
+          bool member;
+          if (in_lds) {
+            while (p < m && staged[p] < c) ++p;
+            member = p < m && staged[p] == c;
+          } else {
+            u64 g = lower_bound(full, lo, hi, c);
+            member = g < hi && full[g] == c;
+          }
+          if (!member) {
+            keep_bits |= 1u << q;
+            ++nkeep;
+          }
         }
-        keep = !member;
       }
     }
-    u32 tot;
-    u32 pos = block_exclusive_scan<kUdNT>(keep ? 1u : 0u, wsum, tot);
-    if (keep) tmp[base + carry + pos] = c;
-    carry += tot;
   }
+  u32 total;
+  u32 pos = block_exclusive_scan<kUdNT>(nkeep, wsum, total);
+  // survivors go back into s_c at their compacted positions (all reads of
+  // s_c happened before the scan's barriers), then out coalesced
+  K mine[kUdItems];
+#pragma unroll
+  for (int q = 0; q < kUdItems; ++q) mine[q] = (b + q < cnt) ? s_c[b + q] : K(0);
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kUdItems; ++q)
+    if (keep_bits & (1u << q)) s_c[pos++] = mine[q];
+  __syncthreads();
+  for (u32 k = threadIdx.x; k < total; k += kUdNT) tmp[base + k] = s_c[k];
   uniq = block_sum<kUdNT>(uniq, wsum64);
   if (threadIdx.x == 0) {
-    tile_counts[tile] = carry;
+    tile_counts[tile] = total;
     atomicAdd(reinterpret_cast<unsigned long long*>(d_unique), (unsigned long long)uniq);
   }
 }

@@ -219,7 +219,7 @@ def test_error_paths():
             e.declare("T3", 3, False)
         assert ei.value.code == pkg.hisalog.HL_E_UNSUPPORTED
         with pytest.raises(pkg.HlError) as ei:
-            e.program("R(x, y) :- E(x, y), E(y, x).")  # shares two variables
+            e.program("R(x, y) :- E(x, a), E(y, b).")  # a cross product
         assert ei.value.code == pkg.hisalog.HL_E_UNSUPPORTED
         with pytest.raises(pkg.HlError) as ei:
             e.program("R(x, y) :- E(x, .")
@@ -227,7 +227,7 @@ def test_error_paths():
         with pytest.raises(pkg.HlError) as ei:
             e.run()  # no program yet
         assert ei.value.code == pkg.hisalog.HL_E_STATE
-        e.program("R(x, y) :- E(x, y).\nR(x, y) :- E(x, z), R(z, y).")
+        e.program("R(x, y) :- E(x, y).\nR(x, y) :- E(x, z), R(z, y).\nR(x, x) :- E(x, y), E(y, x).")
         e.load("E", np.array([[1, 2], [2, 3]], np.uint32))
         e.run()
         import ctypes
@@ -235,6 +235,9 @@ def test_error_paths():
         rc = e._L.hl_fetch(e._h, b"R", None, 0, ctypes.byref(n))
         assert rc == pkg.hisalog.HL_E_CAPACITY and n.value == 3
         assert e.fetch("R").tolist() == [[1, 2], [1, 3], [2, 3]]
+        e.load("E", np.array([[2, 1]], np.uint32))
+        e.run()
+        assert e.fetch("R").tolist() == [[1, 1], [1, 2], [1, 3], [2, 1], [2, 2], [2, 3]]
     say("budget exhaustion")
     wl = workloads.scaled_rmat(10, 3000, seed=8)
     with pytest.raises(pkg.HlError) as ei:
