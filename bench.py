@@ -41,9 +41,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_engine(program, edb, idb, stream, kernel_timing):
+def make_engine(program, edb, idb, stream, kernel_timing, learned=False):
     from paper_2311_02206_amd import Engine
-    e = Engine(device=0, stream=stream, kernel_timing=kernel_timing)
+    e = Engine(device=0, stream=stream, kernel_timing=kernel_timing, learned=learned)
     for name in edb:
         e.declare(name, 2, True)
     for name, ar in idb.items():
@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-verify", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the learned-index run of the same workload")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); "
@@ -208,6 +210,38 @@ def main():
                          "GBps": round(v[2] / (v[1] / 1e3) / 1e9, 1) if v[1] else None}
                     for kn, v in tot.items()},
     }
+    if not args.no_variants:
+        # the same fixpoints with the learned position index in place of the
+        # HISA hash probe and the membership search; outputs must be identical
+        log("learned-index variant")
+        lengines = {
+            "reach": make_engine(programs["reach"], reach_wl["edb"], {"Reach": 2}, stream, False,
+                                 learned=True),
+            "sg": make_engine(programs["sg"], sg_wl["edb"], {"SG": 2}, stream, False,
+                              learned=True),
+        }
+        for e in lengines.values():
+            e.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lper = {k: 0.0 for k in lengines}
+        for i in range(args.steps):
+            for k, e in lengines.items():
+                lper[k] += e.run().seconds
+        torch.cuda.synchronize()
+        lel = time.perf_counter() - t0
+        same = all(lengines[k].count(n) == engines[k].count(n) and
+                   lengines[k].iteration_counts(n, 0) == engines[k].iteration_counts(n, 0)
+                   for k, n in (("reach", "Reach"), ("sg", "SG")))
+        if not args.no_verify:
+            same = same and all(np.array_equal(lengines[k].fetch(n), engines[k].fetch(n))
+                                for k, n in (("reach", "Reach"), ("sg", "SG")))
+        line["variants"] = {"learned_index": {
+            "value": tuples / (lel / args.steps), "ms_per_step": lel / args.steps * 1e3,
+            "vs_plain": (tuples / (lel / args.steps)) / value, "identical_output": bool(same),
+            "per_workload_ms": {k: lper[k] / args.steps * 1e3 for k in lengines}}}
+        for e in lengines.values():
+            e.close()
     for e in engines.values():
         e.close()
     print(json.dumps(line), flush=True)

@@ -50,6 +50,10 @@ extern "C" {
                                paper's "Normal" column of Table 1) */
 #define HL_FLAG_KERNEL_TIMING 0x2u /* time every launch of the kernels listed
                                       under hl_kernel_stats with HIP events */
+#define HL_FLAG_LEARNED_INDEX 0x4u /* probe inner relations and test membership
+                                      in full through a learned position index
+                                      (see hl_learned_query) instead of the HISA
+                                      hash; results are identical */
 
 /* Kernels reported by hl_kernel_stats. */
 #define HL_KERNEL_RADIX_HIST 0    /* digit histogram of one radix pass */
@@ -59,7 +63,8 @@ extern "C" {
 #define HL_KERNEL_JOIN_PROBE 4    /* hash probe of every outer tuple */
 #define HL_KERNEL_JOIN_EXPAND 5   /* load-balanced expansion of the runs */
 #define HL_KERNEL_HISA_BUILD 6    /* hash index insertion */
-#define HL_KERNEL_COUNT 7
+#define HL_KERNEL_LEARNED_FIT 7   /* learned index refit (table + error bounds) */
+#define HL_KERNEL_COUNT 8
 
 /* Phases of one fixpoint, timed with HIP events (milliseconds). */
 #define HL_PHASE_INDEX_EDB 0 /* EDB dedup + HISA builds before iteration 0 */
@@ -135,6 +140,34 @@ int hl_load(hl_engine* e, const char* name, const uint32_t* rows, uint64_t n_row
 /* Same from device memory d_rows (stream-ordered on the engine's stream:
  * d_rows may be reused once the engine's stream has passed this call). */
 int hl_load_device(hl_engine* e, const char* name, const uint32_t* d_rows, uint64_t n_rows);
+
+/* Batches of independent instances of one program (an addition to the
+ * paper, whose engine runs one database at a time).  Instance k uses ids
+ * [0, id_range[k]); the engine maps them to the private range
+ * [base_k, base_k + id_range[k]) of one id space (dictionary encoding,
+ * base_k = sum of the earlier ranges, total below 2^32), and one fixpoint
+ * over the union then computes every instance's own fixpoint in one set
+ * of launches per iteration.  This is exact for every program hl_program
+ * accepts: joins match equal values only and every rule body is connected,
+ * so no derivation mixes instances.  Per-iteration counts (hl_iteration_
+ * counts) are totals over the batch.  Call once, before any load. */
+int hl_batch_layout(hl_engine* e, const uint32_t* id_range, uint32_t n_inst);
+
+/* Loads EDB rows of every instance: rows[inst_offsets[k] .. inst_offsets[k+1])
+ * (row indices; n_inst + 1 offsets, starting at 0) are instance k's rows, with
+ * instance-local ids (each must be < id_range[k]: HL_E_INVALID otherwise).
+ * The rows are copied before the call returns. */
+int hl_load_batched(hl_engine* e, const char* name, const uint32_t* rows,
+                    const uint64_t* inst_offsets);
+
+/* Size of instance `inst`'s part of relation `name` after hl_run. */
+int hl_batch_count(hl_engine* e, const char* name, uint32_t inst, uint64_t* n);
+
+/* Instance `inst`'s part of relation `name`, sorted, with instance-local ids,
+ * into host buffer rows (cap_rows rows); HL_E_CAPACITY and the needed size
+ * as for hl_fetch. */
+int hl_fetch_batched(hl_engine* e, const char* name, uint32_t inst, uint32_t* rows,
+                     uint64_t cap_rows, uint64_t* n_rows);
 
 /* Requests a HISA on relation `name` keyed by its column cols[0]
  * (Section 3: sorted array + hash index).  Only ncols == 1 is supported.
@@ -229,6 +262,18 @@ int hl_merge(hl_engine* e, const void* d_a, uint64_t na, const void* d_b, uint64
 int hl_hisa_query(hl_engine* e, const void* d_keys, uint64_t n, uint32_t key_bytes,
                   uint32_t shift, const uint32_t* d_queries, uint64_t nq, uint64_t* d_start,
                   uint32_t* d_len, uint64_t* n_runs);
+
+/* Learned position index (an addition to the paper's HISA, used by
+ * HL_FLAG_LEARNED_INDEX): fits a radix table over the top bits of n
+ * ascending keys d_keys (whose values are below 2^key_bits) with an fp32
+ * linear model per radix bucket and the bucket's exact error bound, then
+ * writes d_pos[i] = lower_bound(d_keys, d_queries[i]) (the first position
+ * whose key is >= the query; n if none) for nq queries of the key type.
+ * The answer is exact for any query below 2^key_bits: the radix table
+ * brackets it and the bound limits the window a binary search scans.
+ * n < 2^32. */
+int hl_learned_query(hl_engine* e, const void* d_keys, uint64_t n, uint32_t key_bytes,
+                     uint32_t key_bits, const void* d_queries, uint64_t nq, uint32_t* d_pos);
 
 #ifdef __cplusplus
 }

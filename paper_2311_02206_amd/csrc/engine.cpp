@@ -252,6 +252,20 @@ struct Index {
   u64 n = 0;
   Buf table;
   u64 cap = 0, runs = 0;
+  // learned position index (HL_FLAG_LEARNED_INDEX) over the same array
+  Buf lm;
+  bool lm_ok = false;
+  const void* lm_keys = nullptr;
+  u64 lm_n = 0;
+  int lm_shift = 0;
+  u32 lm_T = 0;
+  const u32* lm_table = nullptr;
+  const u32* lm_eps = nullptr;
+  template <typename K>
+  hl::LearnedView<K> view() const {
+    return hl::LearnedView<K>{static_cast<const K*>(lm_keys), lm_n, lm_shift, lm_T, lm_table,
+                              lm_eps};
+  }
 };
 
 struct Relation {
@@ -334,6 +348,10 @@ struct hl_engine {
 
   std::vector<Relation> rels;
   std::vector<Rule> rules;
+  // batch layout: instance k owns ids [base[k], base[k+1]) of the shared id
+  // space (empty: no batch)
+  std::vector<u64> batch_base;
+  std::vector<u32> batch_rows_tmp;
   std::vector<Plan> plans0, plansR;  // iteration 0 / recursive plans
   bool ran = false;
 
@@ -351,6 +369,7 @@ struct hl_engine {
   u64 reuses = 0;
   EventTimer ktimer;
   hl::LaunchTimer* kt() { return (flags & HL_FLAG_KERNEL_TIMING) ? &ktimer : nullptr; }
+  bool learned() const { return flags & HL_FLAG_LEARNED_INDEX; }
   // Device word that kernels set when a bounded wait ran out (last slot of
   // d_small; zeroed at the start of every run and primitive call).
   u32* d_err() { return reinterpret_cast<u32*>(d_small + kSmall - 1); }
@@ -675,6 +694,28 @@ struct hl_engine {
   }
 
   template <typename K>
+  void fit_model(Relation& R, int col) {
+    Index& ix = R.idx[col];
+    if (col == 0) ix.n = R.n_full;
+    const K* keys = col == 0 ? kp<K>(R.full) : kp<K>(ix.keys);
+    ix.lm_ok = false;
+    if (ix.n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "indexed relation " + R.name +
+                                                           " has 2^32 or more tuples");
+    const int bits = hl::learned_bits(ix.n, 2 * w);
+    const u64 bytes = hl::learned_bytes(bits);
+    reserve(ix.lm, bytes, bytes);
+    hl::LearnedView<K> v{};
+    HIPCK(hl::learned_fit<K>(keys, ix.n, 2 * w, bits, ix.lm.p, stream, &v, kt()));
+    ix.lm_keys = v.keys;
+    ix.lm_n = v.n;
+    ix.lm_shift = v.shift;
+    ix.lm_T = v.T;
+    ix.lm_table = v.table;
+    ix.lm_eps = v.eps;
+    ix.lm_ok = true;
+  }
+
+  template <typename K>
   void finish_index(Relation& R, int col, u64 runs) {
     Index& ix = R.idx[col];
     ix.runs = runs;
@@ -702,8 +743,14 @@ struct hl_engine {
     std::vector<std::pair<int, int>> todo;
     for (int r : which)
       for (int c = 0; c < 2; ++c)
-        if (rels[r].idx[c].used) todo.push_back({r, c});
+        if (rels[r].idx[c].used || (c == 0 && learned() && !rels[r].edb))
+          todo.push_back({r, c});
     if (todo.empty()) return;
+    if (learned()) {
+      // the learned index needs no run count: no synchronisation
+      for (auto& rc : todo) fit_model<K>(rels[rc.first], rc.second);
+      return;
+    }
     if (todo.size() > kSmall) fail(HL_E_UNSUPPORTED, "too many indexes");
     for (size_t q = 0; q < todo.size(); ++q) {
       Relation& R = rels[todo[q].first];
@@ -818,7 +865,7 @@ struct hl_engine {
       const Step& s = p.steps[q];
       Relation& I = rels[s.inner_rel];
       Index& ix = I.idx[s.inner_col];
-      if (ix.n == 0 || ix.cap == 0) return;
+      if (ix.n == 0 || (learned() ? !ix.lm_ok : ix.cap == 0)) return;
       const K* inner = s.inner_col == 0 ? kp<K>(I.full) : kp<K>(ix.keys);
       JoinSpec js = s.js;
       js.w = w;
@@ -826,9 +873,14 @@ struct hl_engine {
       reserve_grow(join_start, n * sizeof(u32));
       reserve_grow(join_len, n * sizeof(u32));
       reserve_grow(join_off, n * sizeof(u64));
-      HIPCK(hl::join_probe<K>(cur, n, js, static_cast<const Slot*>(ix.table.p), ix.cap,
-                              static_cast<u32*>(join_start.p), static_cast<u32*>(join_len.p),
-                              stream, kt()));
+      if (learned())
+        HIPCK(hl::join_probe_learned<K>(cur, n, js, ix.view<K>(),
+                                        static_cast<u32*>(join_start.p),
+                                        static_cast<u32*>(join_len.p), stream, kt()));
+      else
+        HIPCK(hl::join_probe<K>(cur, n, js, static_cast<const Slot*>(ix.table.p), ix.cap,
+                                static_cast<u32*>(join_start.p), static_cast<u32*>(join_len.p),
+                                stream, kt()));
       reserve(ws, hl::scan_workspace_bytes(n), hl::scan_workspace_bytes(n) * 2);
       HIPCK(hl::scan_u32_u64(static_cast<u32*>(join_len.p), n, static_cast<u64*>(join_off.p),
                              d_small + 1, ws.p, stream));
@@ -907,8 +959,13 @@ struct hl_engine {
               hl::unique_diff_workspace_bytes(R.n_cand) * 2);
       mark(HL_PHASE_DIFF);
       // delta is written over the sorted candidates, then takes their buffer
+      hl::LearnedView<K> mv{};
+      const bool use_model = learned() && R.n_full > 0 && R.idx[0].lm_ok &&
+                             R.idx[0].lm_keys == R.full.p && R.idx[0].lm_n == R.n_full;
+      if (use_model) mv = R.idx[0].view<K>();
       HIPCK(hl::unique_diff<K>(kp<K>(sbuf), R.n_cand, kp<K>(R.full), R.n_full, kp<K>(obuf),
-                               kp<K>(sbuf), d_small + 2 * q, ws.p, stream, kt()));
+                               kp<K>(sbuf), d_small + 2 * q, ws.p, stream, kt(),
+                               use_model ? &mv : nullptr));
       std::swap(R.delta, sbuf);
     }
     HIPCK(hipMemcpyAsync(h_small, d_small, 2 * idbs.size() * sizeof(u64), hipMemcpyDeviceToHost,
@@ -985,6 +1042,7 @@ struct hl_engine {
       R.delta_counts.clear();
       R.new_counts.clear();
       R.n_delta = R.n_cand = 0;
+      R.idx[0].lm_ok = R.idx[1].lm_ok = false;
       if (!R.edb) {
         R.n_full = 0;
         R.idx[0].n = R.idx[1].n = 0;
@@ -1019,8 +1077,52 @@ struct hl_engine {
   }
 
   template <typename K>
-  void fetch_typed(Relation& R, u32* d_rows) {
-    HIPCK(hl::unpack_rows<K>(kp<K>(R.full), R.n_full, R.arity, w, d_rows, stream));
+  void fetch_typed(Relation& R, u64 first, u64 count, u32* d_rows, u32 sub) {
+    HIPCK(hl::unpack_rows<K>(kp<K>(R.full) + first, count, R.arity, w, d_rows, stream, sub));
+  }
+
+  // Tuples of relation R whose first column lies in [lo, hi): a contiguous
+  // range of the sorted full relation (device search, one sync).
+  template <typename K>
+  std::pair<u64, u64> range_typed(Relation& R, u64 lo, u64 hi) {
+    if (R.n_full == 0) return {0, 0};
+    const u64 top = u64(1) << w;
+    if (lo >= top) return {R.n_full, R.n_full};  // no id of the range occurs
+    const K klo = lo >= top ? ~K(0) : K(K(lo) << w);
+    const K khi = hi >= top ? ~K(0) : K(K(hi) << w);
+    HIPCK(hl::key_range<K>(kp<K>(R.full), R.n_full, klo, khi, d_small, stream));
+    HIPCK(hipMemcpyAsync(h_small, d_small, 2 * sizeof(u64), hipMemcpyDeviceToHost, stream));
+    sync();
+    u64 a = h_small[0], b = h_small[1];
+    if (hi >= top) b = R.n_full;
+    return {a, b};
+  }
+
+  std::pair<u64, u64> instance_range(Relation& R, u32 inst) {
+    if (batch_base.empty()) fail(HL_E_STATE, "no batch layout");
+    if (inst + 1 >= batch_base.size()) fail(HL_E_INVALID, "instance out of range");
+    if (!ran) fail(HL_E_STATE, "fetch before hl_run");
+    const u64 lo = batch_base[inst], hi = batch_base[inst + 1];
+    return key_bytes == 4 ? range_typed<u32>(R, lo, hi) : range_typed<u64>(R, lo, hi);
+  }
+
+  void fetch_instance(const char* name, u32 inst, u32* rows, u64 cap, u64* n_rows) {
+    Relation& R = rels[find_or_fail(name)];
+    auto rg = instance_range(R, inst);
+    const u64 cnt = rg.second - rg.first;
+    if (n_rows) *n_rows = cnt;
+    if (cap < cnt) fail(HL_E_CAPACITY, "buffer holds " + std::to_string(cap) + " rows, need " +
+                                          std::to_string(cnt));
+    if (cnt == 0) return;
+    if (!rows) fail(HL_E_INVALID, "null output buffer");
+    const u64 bytes = cnt * R.arity * sizeof(u32);
+    reserve_grow(this->rows, bytes);
+    u32* dst = static_cast<u32*>(this->rows.p);
+    const u32 sub = u32(batch_base[inst]);
+    if (key_bytes == 4) fetch_typed<u32>(R, rg.first, cnt, dst, sub);
+    else fetch_typed<u64>(R, rg.first, cnt, dst, sub);
+    HIPCK(hipMemcpyAsync(rows, dst, bytes, hipMemcpyDeviceToHost, stream));
+    sync();
   }
 
   void fetch(const char* name, u32* rows, u64 cap, u64* n_rows, bool device) {
@@ -1039,8 +1141,8 @@ struct hl_engine {
       reserve_grow(this->rows, bytes);
       dst = static_cast<u32*>(this->rows.p);
     }
-    if (key_bytes == 4) fetch_typed<u32>(R, dst);
-    else fetch_typed<u64>(R, dst);
+    if (key_bytes == 4) fetch_typed<u32>(R, 0, R.n_full, dst, 0);
+    else fetch_typed<u64>(R, 0, R.n_full, dst, 0);
     if (!device) HIPCK(hipMemcpyAsync(rows, dst, bytes, hipMemcpyDeviceToHost, stream));
     sync();
   }
@@ -1196,6 +1298,64 @@ int hl_load(hl_engine* e, const char* name, const uint32_t* rows, uint64_t n_row
 
 int hl_load_device(hl_engine* e, const char* name, const uint32_t* d_rows, uint64_t n_rows) {
   return load_impl(e, name, d_rows, n_rows, true);
+}
+
+int hl_batch_layout(hl_engine* e, const uint32_t* id_range, uint32_t n_inst) {
+  return guard(e, [&] {
+    if (!id_range || n_inst == 0) fail(HL_E_INVALID, "empty batch layout");
+    if (!e->batch_base.empty()) fail(HL_E_STATE, "batch layout already set");
+    for (const Relation& R : e->rels)
+      if (R.n_raw) fail(HL_E_STATE, "batch layout after rows were loaded");
+    std::vector<u64> base(n_inst + 1, 0);
+    for (u32 k = 0; k < n_inst; ++k) base[k + 1] = base[k] + id_range[k];
+    if (base[n_inst] > (u64(1) << 32)) fail(HL_E_INVALID, "instance id ranges exceed 2^32");
+    e->batch_base = base;
+  });
+}
+
+int hl_load_batched(hl_engine* e, const char* name, const uint32_t* rows,
+                    const uint64_t* inst_offsets) {
+  int rc = guard(e, [&] {
+    if (e->batch_base.empty()) fail(HL_E_STATE, "hl_batch_layout first");
+    Relation& R = e->rels[e->find_or_fail(name)];
+    if (!R.edb) fail(HL_E_INVALID, "load into an IDB relation");
+    if (!inst_offsets) fail(HL_E_INVALID, "null offsets");
+    const u32 ni = u32(e->batch_base.size() - 1);
+    if (inst_offsets[0] != 0) fail(HL_E_INVALID, "offsets must start at 0");
+    for (u32 k = 0; k < ni; ++k)
+      if (inst_offsets[k + 1] < inst_offsets[k]) fail(HL_E_INVALID, "offsets must not decrease");
+    const u64 n = inst_offsets[ni];
+    if (n && !rows) fail(HL_E_INVALID, "null rows");
+    // dictionary encoding: instance k's id v becomes base[k] + v
+    std::vector<u32> mapped(n * R.arity);
+    for (u32 k = 0; k < ni; ++k) {
+      const u64 b = e->batch_base[k], range = e->batch_base[k + 1] - b;
+      for (u64 i = inst_offsets[k] * R.arity; i < inst_offsets[k + 1] * R.arity; ++i) {
+        if (rows[i] >= range) fail(HL_E_INVALID, "id outside its instance's range");
+        mapped[i] = u32(b + rows[i]);
+      }
+    }
+    e->batch_rows_tmp.swap(mapped);
+  });
+  if (rc != HL_OK) return rc;
+  std::vector<u32> mapped;
+  mapped.swap(e->batch_rows_tmp);
+  const u64 n = mapped.size() / 2;
+  return hl_load(e, name, mapped.data(), n);
+}
+
+int hl_batch_count(hl_engine* e, const char* name, uint32_t inst, uint64_t* n) {
+  return guard(e, [&] {
+    if (!n) fail(HL_E_INVALID, "null output");
+    Relation& R = e->rels[e->find_or_fail(name)];
+    auto rg = e->instance_range(R, inst);
+    *n = rg.second - rg.first;
+  });
+}
+
+int hl_fetch_batched(hl_engine* e, const char* name, uint32_t inst, uint32_t* rows,
+                     uint64_t cap_rows, uint64_t* n_rows) {
+  return guard(e, [&] { e->fetch_instance(name, inst, rows, cap_rows, n_rows); });
 }
 
 int hl_index(hl_engine* e, const char* name, const uint32_t* cols, uint32_t ncols) {
@@ -1405,6 +1565,40 @@ int hl_hisa_query(hl_engine* e, const void* d_keys, uint64_t n, uint32_t key_byt
       throw;
     }
     e->drop(table);
+  });
+}
+
+int hl_learned_query(hl_engine* e, const void* d_keys, uint64_t n, uint32_t key_bytes,
+                     uint32_t key_bits, const void* d_queries, uint64_t nq, uint32_t* d_pos) {
+  return guard(e, [&] {
+    if (e->device < 0) fail(HL_E_STATE, "planning-only engine (device -1)");
+    if (!valid_key_bytes(key_bytes)) fail(HL_E_INVALID, "key_bytes must be 4 or 8");
+    if (key_bits < 1 || key_bits > 8 * key_bytes) fail(HL_E_INVALID, "key_bits out of range");
+    if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "2^32 or more keys");
+    if ((n && !d_keys) || (nq && (!d_queries || !d_pos))) fail(HL_E_INVALID, "null buffer");
+    const int bits = hl::learned_bits(n, int(key_bits));
+    const u64 bytes = hl::learned_bytes(bits);
+    Buf m;
+    m.p = e->mem.alloc(bytes);
+    m.bytes = bytes;
+    try {
+      if (key_bytes == 4) {
+        hl::LearnedView<u32> v{};
+        HIPCK(hl::learned_fit<u32>(static_cast<const u32*>(d_keys), n, int(key_bits), bits, m.p,
+                                   e->stream, &v));
+        HIPCK(hl::learned_query(v, static_cast<const u32*>(d_queries), nq, d_pos, e->stream));
+      } else {
+        hl::LearnedView<u64> v{};
+        HIPCK(hl::learned_fit<u64>(static_cast<const u64*>(d_keys), n, int(key_bits), bits, m.p,
+                                   e->stream, &v));
+        HIPCK(hl::learned_query(v, static_cast<const u64*>(d_queries), nq, d_pos, e->stream));
+      }
+      e->sync();
+    } catch (...) {
+      e->drop(m);
+      throw;
+    }
+    e->drop(m);
   });
 }
 

@@ -141,14 +141,28 @@ __global__ __launch_bounds__(kNT) void swap_kernel(const K* in, u64 n, int w, K*
 
 template <typename K>
 __global__ __launch_bounds__(kNT) void unpack_kernel(const K* keys, u64 n, int arity, int w,
-                                                     u32* rows) {
+                                                     u32* rows, u32 sub) {
   const K mask = (K(1) << w) - 1;
   const u64 stride = u64(gridDim.x) * kNT;
   for (u64 i = u64(blockIdx.x) * kNT + threadIdx.x; i < n; i += stride) {
     K k = keys[i];
-    rows[i * arity] = u32(k >> w);
-    if (arity > 1) rows[i * arity + 1] = u32(k & mask);
+    rows[i * arity] = u32(k >> w) - sub;
+    if (arity > 1) rows[i * arity + 1] = u32(k & mask) - sub;
   }
+}
+
+template <typename K>
+__global__ void key_range_kernel(const K* keys, u64 n, K lo, K hi, u64* out) {
+  const int which = threadIdx.x;
+  if (which > 1) return;
+  const K x = which == 0 ? lo : hi;
+  u64 a = 0, b = n;
+  while (a < b) {
+    u64 mid = (a + b) >> 1;
+    if (keys[mid] < x) a = mid + 1;
+    else b = mid;
+  }
+  out[which] = a;
 }
 
 u32 grid_for(u64 n, u64 cap_blocks = 65536) {
@@ -221,9 +235,16 @@ hipError_t swap_cols(const K* in, u64 n, int w, K* out, hipStream_t s) {
 }
 
 template <typename K>
-hipError_t unpack_rows(const K* keys, u64 n, int arity, int w, u32* rows, hipStream_t s) {
+hipError_t unpack_rows(const K* keys, u64 n, int arity, int w, u32* rows, hipStream_t s,
+                       u32 sub) {
   if (n == 0) return hipSuccess;
-  unpack_kernel<K><<<grid_for(n), kNT, 0, s>>>(keys, n, arity, w, rows);
+  unpack_kernel<K><<<grid_for(n), kNT, 0, s>>>(keys, n, arity, w, rows, sub);
+  return hipGetLastError();
+}
+
+template <typename K>
+hipError_t key_range(const K* keys, u64 n, K lo, K hi, u64* out, hipStream_t s) {
+  key_range_kernel<K><<<1, 64, 0, s>>>(keys, n, lo, hi, out);
   return hipGetLastError();
 }
 
@@ -233,7 +254,8 @@ hipError_t unpack_rows(const K* keys, u64 n, int arity, int w, u32* rows, hipStr
                                     LaunchTimer*);                                            \
   template hipError_t pack_rows<K>(const u32*, u64, int, int, K*, hipStream_t);             \
   template hipError_t swap_cols<K>(const K*, u64, int, K*, hipStream_t);                    \
-  template hipError_t unpack_rows<K>(const K*, u64, int, int, u32*, hipStream_t);
+  template hipError_t unpack_rows<K>(const K*, u64, int, int, u32*, hipStream_t, u32);      \
+  template hipError_t key_range<K>(const K*, u64, K, K, u64*, hipStream_t);
 HL_INSTANTIATE(u32)
 HL_INSTANTIATE(u64)
 #undef HL_INSTANTIATE

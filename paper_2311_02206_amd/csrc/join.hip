@@ -83,6 +83,41 @@ __global__ __launch_bounds__(kNT) void probe_kernel(const K* outer, u64 n, int o
   }
 }
 
+template <typename K>
+__global__ __launch_bounds__(kNT) void probe_learned_kernel(const K* outer, u64 n, int outer_col,
+                                                            int w, LearnedView<K> lv, u32* start,
+                                                            u32* len) {
+  const u64 i = u64(blockIdx.x) * kNT + threadIdx.x;
+  const bool valid = i < n;
+  const K mask = (K(1) << w) - 1;
+  u32 jc = 0, prev = 0;
+  if (valid) {
+    const K k = outer[i];
+    jc = outer_col == 0 ? u32(k >> w) : u32(k & mask);
+    if (i > 0) {
+      const K kp = outer[i - 1];
+      prev = outer_col == 0 ? u32(kp >> w) : u32(kp & mask);
+    }
+  }
+  const int lane = lane_id();
+  const bool leader = valid && (lane == 0 || i == 0 || jc != prev);
+  const u64 lm = ballot(leader);
+  u32 st = 0, ln = 0;
+  if (leader) {
+    st = lm_lower_bound(lv, K(jc) << w);
+    const u32 en = (K(jc) == mask) ? u32(lv.n) : lm_lower_bound(lv, (K(jc) + 1) << w);
+    ln = en - st;
+  }
+  const u64 upto = lm & ((lane == 63) ? ~u64(0) : ((u64(2) << lane) - 1));
+  const int src = upto ? 63 - __clzll((long long)upto) : lane;
+  st = __shfl(st, src, kWave);
+  ln = __shfl(ln, src, kWave);
+  if (valid) {
+    start[i] = ln ? st : 0;
+    len[i] = ln;
+  }
+}
+
 // Merged order of outer tuple i (key off[i]) and output j (key j): the
 // outer tuple comes first when off[i] <= j.  Returns how many outer tuples
 // are among the first `diag` merged items.
@@ -256,6 +291,21 @@ hipError_t join_probe(const K* outer, u64 n, const JoinSpec& js, const Slot* tab
   return hipGetLastError();
 }
 
+template <typename K>
+hipError_t join_probe_learned(const K* outer, u64 n, const JoinSpec& js,
+                              const LearnedView<K>& lv, u32* start, u32* len, hipStream_t s,
+                              LaunchTimer* timer) {
+  if (n == 0) return hipSuccess;
+  if (js.outer_col < 0 || js.outer_col > 1 || lv.n >= (u64(1) << 32)) return hipErrorInvalidValue;
+  const u64 blocks = (n + kNT - 1) / kNT;
+  if (blocks >= (u64(1) << 31)) return hipErrorInvalidValue;
+  if (timer) timer->begin(K_JOIN_PROBE, s);
+  probe_learned_kernel<K><<<dim3(u32(blocks)), kNT, 0, s>>>(outer, n, js.outer_col, js.w, lv,
+                                                            start, len);
+  if (timer) timer->end(K_JOIN_PROBE, s, n * (sizeof(K) + 2 * sizeof(u32)));
+  return hipGetLastError();
+}
+
 u64 join_parts(u64 n_outer, u64 total) { return tiles_of(n_outer + total) + 1; }
 
 template <typename K>
@@ -296,7 +346,10 @@ hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, 
   template hipError_t join_expand<K>(const K*, u64, const u64*, const u32*, const K*, u64,  \
                                      const JoinSpec&, u64*, K*, u64*, hipStream_t,            \
                                      LaunchTimer*);                                           \
-  template hipError_t project<K>(const K*, u64, const JoinSpec&, K*, u64*, hipStream_t);
+  template hipError_t project<K>(const K*, u64, const JoinSpec&, K*, u64*, hipStream_t);   \
+  template hipError_t join_probe_learned<K>(const K*, u64, const JoinSpec&,                  \
+                                            const LearnedView<K>&, u32*, u32*, hipStream_t,  \
+                                            LaunchTimer*);
 HL_INSTANTIATE(u32)
 HL_INSTANTIATE(u64)
 #undef HL_INSTANTIATE

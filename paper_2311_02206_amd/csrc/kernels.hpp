@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "learned.hpp"
+
 namespace hl {
 
 typedef uint32_t u32;
@@ -33,7 +35,8 @@ enum KernelId {
   K_JOIN_PROBE = 4,
   K_JOIN_EXPAND = 5,
   K_HISA_BUILD = 6,
-  K_COUNT = 7
+  K_LEARNED_FIT = 7,
+  K_COUNT = 8
 };
 
 // Optional launch timer: launchers call begin() right before and end()
@@ -67,9 +70,12 @@ u64 unique_diff_workspace_bytes(u64 n);
 // out = unique(sorted) \ full.  Both inputs sorted ascending; full has no
 // duplicates.  `tmp` holds n keys.  d_counts[0] = |out|, d_counts[1] =
 // number of distinct keys in `sorted`.  n must be below 2^32.
+// With `model` (a learned index over full), the slice of full each tile
+// spans and the membership tests outside LDS go through the model.
 template <typename K>
 hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
-                       u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer = nullptr);
+                       u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer = nullptr,
+                       const LearnedView<K>* model = nullptr);
 
 // --------------------------------------------------------------- merge
 u64 merge_workspace_bytes(u64 na, u64 nb);
@@ -91,6 +97,20 @@ hipError_t hisa_build(const K* keys, u64 n, int shift, Slot* table, u64 cap, hip
 hipError_t hisa_probe(const Slot* table, u64 cap, const u32* q, u64 nq, u64* start, u32* len,
                       hipStream_t s);
 
+// -------------------------------------------------------- learned index
+// Radix bits for an index over n keys of key_bits significant bits.
+int learned_bits(u64 n, int key_bits);
+u64 learned_bytes(int radix_bits);
+// Fits the model of n sorted keys (n < 2^32) into `mem` (learned_bytes).
+template <typename K>
+hipError_t learned_fit(const K* keys, u64 n, int key_bits, int radix_bits, void* mem,
+                       hipStream_t s, LearnedView<K>* out, LaunchTimer* timer = nullptr);
+// out[i] = lower_bound(keys, q[i]) through the model.
+hipError_t learned_query(const LearnedView<u32>& lv, const u32* q, u64 nq, u32* out,
+                         hipStream_t s);
+hipError_t learned_query(const LearnedView<u64>& lv, const u64* q, u64 nq, u32* out,
+                         hipStream_t s);
+
 // ---------------------------------------------------------------- misc
 hipError_t fill_zero(void* p, u64 bytes, hipStream_t s);
 // *d_max = max(*d_max, v[i]); *d_max must be initialised.
@@ -102,7 +122,11 @@ hipError_t pack_rows(const u32* rows, u64 n, int arity, int w, K* out, hipStream
 template <typename K>
 hipError_t swap_cols(const K* in, u64 n, int w, K* out, hipStream_t s);
 template <typename K>
-hipError_t unpack_rows(const K* keys, u64 n, int arity, int w, u32* rows, hipStream_t s);
+hipError_t unpack_rows(const K* keys, u64 n, int arity, int w, u32* rows, hipStream_t s,
+                       u32 sub = 0);
+// out[0] = lower_bound(keys, lo), out[1] = lower_bound(keys, hi) (device).
+template <typename K>
+hipError_t key_range(const K* keys, u64 n, K lo, K hi, u64* out, hipStream_t s);
 
 // ---------------------------------------------------------------- join
 // Values of the current pair (c0, c1) and of the inner tuple's non-join
@@ -121,6 +145,12 @@ struct JoinSpec {
 template <typename K>
 hipError_t join_probe(const K* outer, u64 n, const JoinSpec& js, const Slot* table, u64 cap,
                       u32* start, u32* len, hipStream_t s, LaunchTimer* timer = nullptr);
+// The same probe through a learned index of the inner sorted array: the run
+// of join key jc is [lower_bound(jc << w), lower_bound((jc + 1) << w)).
+template <typename K>
+hipError_t join_probe_learned(const K* outer, u64 n, const JoinSpec& js,
+                              const LearnedView<K>& lv, u32* start, u32* len, hipStream_t s,
+                              LaunchTimer* timer = nullptr);
 u64 join_parts(u64 n_outer, u64 total);  // entries of the partition array
 // Expands every (outer, inner run) pair.  Without a filter, output j goes
 // to out[j]; with one, survivors are appended at *cursor (device, u64).

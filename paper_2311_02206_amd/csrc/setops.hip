@@ -52,10 +52,10 @@ __device__ __forceinline__ u64 upper_bound(const K* a, u64 lo, u64 hi, K x) {
 // full by walking the (LDS-staged) slice of full forward from the
 // lower bound of its first key; one block scan places the survivors, which
 // are written compacted (in order) at the tile's start in tmp.
-template <typename K>
+template <typename K, bool kModel>
 __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, const K* full,
                                                           u64 nf, K* tmp, u32* tile_counts,
-                                                          u64* d_unique) {
+                                                          u64* d_unique, LearnedView<K> lv) {
   __shared__ u64 range[2];
   __shared__ K before;
   __shared__ u32 wsum[kUdNT / kWave];
@@ -66,8 +66,15 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
   const u64 base = u64(tile) * kUdTile;
   const u32 cnt = u32((n - base) < kUdTile ? (n - base) : kUdTile);
   if (threadIdx.x == 0) {
-    range[0] = lower_bound(full, 0, nf, cand[base]);
-    range[1] = upper_bound(full, range[0], nf, cand[base + cnt - 1]);
+    const K first = cand[base], last = cand[base + cnt - 1];
+    if (kModel) {
+      range[0] = lm_lower_bound(lv, first);
+      u64 h = lm_lower_bound(lv, last);
+      range[1] = (h < nf && full[h] == last) ? h + 1 : h;
+    } else {
+      range[0] = lower_bound(full, 0, nf, first);
+      range[1] = upper_bound(full, range[0], nf, last);
+    }
     before = base > 0 ? cand[base - 1] : K(0);
   }
   for (u32 k = threadIdx.x; k < cnt; k += kUdNT) s_c[k] = cand[base + k];
@@ -99,7 +106,7 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
             while (p < m && staged[p] < c) ++p;
             member = p < m && staged[p] == c;
           } else {
-            u64 g = lower_bound(full, lo, hi, c);
+            u64 g = kModel ? u64(lm_lower_bound(lv, c)) : lower_bound(full, lo, hi, c);
             member = g < hi && full[g] == c;
           }
           if (!member) {
@@ -232,7 +239,8 @@ u64 unique_diff_workspace_bytes(u64 n) {
 
 template <typename K>
 hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
-                       u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer) {
+                       u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer,
+                       const LearnedView<K>* model) {
   zero_u64x2_kernel<<<1, 1, 0, s>>>(d_counts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n == 0) return e;
@@ -244,8 +252,14 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   u64* tile_off = reinterpret_cast<u64*>(p);
   p += align_up(nt * sizeof(u64), 256);
   if (timer) timer->begin(K_UNIQUE_DIFF, s);
-  ud_select_kernel<K><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
-                                                      d_counts + 1);
+  if (model && (model->keys != full || model->n != nf)) return hipErrorInvalidValue;
+  if (model)
+    ud_select_kernel<K, true><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
+                                                              tile_counts, d_counts + 1, *model);
+  else
+    ud_select_kernel<K, false><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
+                                                               tile_counts, d_counts + 1,
+                                                               LearnedView<K>{});
   // by definition: every candidate read once, each kept key written once;
   // the count of kept keys is not known here, so only the reads are counted
   if (timer) timer->end(K_UNIQUE_DIFF, s, n * sizeof(K));
@@ -281,9 +295,9 @@ hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipSt
 }
 
 template hipError_t unique_diff<u32>(const u32*, u64, const u32*, u64, u32*, u32*, u64*, void*,
-                                     hipStream_t, LaunchTimer*);
+                                     hipStream_t, LaunchTimer*, const LearnedView<u32>*);
 template hipError_t unique_diff<u64>(const u64*, u64, const u64*, u64, u64*, u64*, u64*, void*,
-                                     hipStream_t, LaunchTimer*);
+                                     hipStream_t, LaunchTimer*, const LearnedView<u64>*);
 template hipError_t merge<u32>(const u32*, u64, const u32*, u64, u32*, void*, hipStream_t,
                                LaunchTimer*);
 template hipError_t merge<u64>(const u64*, u64, const u64*, u64, u64*, void*, hipStream_t,

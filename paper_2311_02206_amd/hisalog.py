@@ -26,16 +26,17 @@ HL_E_CAPACITY = -5
 HL_E_UNSUPPORTED = -6
 HL_FLAG_NO_EBM = 0x1
 HL_FLAG_KERNEL_TIMING = 0x2
+HL_FLAG_LEARNED_INDEX = 0x4
 KERNELS = ("radix_hist", "radix_scatter", "unique_diff", "merge", "join_probe", "join_expand",
-           "hisa_build")
+           "hisa_build", "learned_fit")
 PHASES = ("index_edb", "join", "sort", "diff", "merge", "index")
 
 # Symbols of include/hisalog.h, in declaration order.
 EXPORTS = (
     "hl_options_init", "hl_create", "hl_destroy", "hl_declare", "hl_load", "hl_load_device",
-    "hl_index", "hl_program", "hl_run", "hl_count", "hl_fetch", "hl_fetch_device",
+    "hl_batch_layout", "hl_load_batched", "hl_batch_count", "hl_fetch_batched", "hl_index", "hl_program", "hl_run", "hl_count", "hl_fetch", "hl_fetch_device",
     "hl_iteration_counts", "hl_kernel_stats", "hl_last_error", "hl_strerror", "hl_sort_keys",
-    "hl_unique_diff", "hl_merge", "hl_hisa_query",
+    "hl_unique_diff", "hl_merge", "hl_hisa_query", "hl_learned_query",
 )
 
 
@@ -93,6 +94,10 @@ def lib() -> ctypes.CDLL:
         "hl_load": [vp, cp, vp, u64],
         "hl_load_device": [vp, cp, vp, u64],
         "hl_index": [vp, cp, pu32, u32],
+        "hl_batch_layout": [vp, vp, u32],
+        "hl_load_batched": [vp, cp, vp, vp],
+        "hl_batch_count": [vp, cp, u32, pu64],
+        "hl_fetch_batched": [vp, cp, u32, vp, u64, pu64],
         "hl_program": [vp, cp],
         "hl_run": [vp, ctypes.POINTER(Stats)],
         "hl_count": [vp, cp, pu64],
@@ -106,6 +111,7 @@ def lib() -> ctypes.CDLL:
         "hl_unique_diff": [vp, vp, u64, vp, u64, vp, pu64, pu64, u32],
         "hl_merge": [vp, vp, u64, vp, u64, vp, u32],
         "hl_hisa_query": [vp, vp, u64, u32, u32, vp, u64, vp, vp, pu64],
+        "hl_learned_query": [vp, vp, u64, u32, u32, vp, u64, vp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -150,12 +156,14 @@ class Engine:
 
     def __init__(self, device: int = 0, stream=None, arena=None, ebm: bool = True,
                  ebm_k: float = 8.0, load_factor: float = 0.8, budget_bytes: int = 0,
-                 kernel_timing: bool = False):
+                 kernel_timing: bool = False, learned: bool = False):
         L = lib()
         opt = Options()
         L.hl_options_init(ctypes.byref(opt))
         opt.device = device
-        opt.flags = (0 if ebm else HL_FLAG_NO_EBM) | (HL_FLAG_KERNEL_TIMING if kernel_timing else 0)
+        opt.flags = ((0 if ebm else HL_FLAG_NO_EBM) |
+                     (HL_FLAG_KERNEL_TIMING if kernel_timing else 0) |
+                     (HL_FLAG_LEARNED_INDEX if learned else 0))
         opt.ebm_k = ebm_k
         opt.hash_load_factor = load_factor
         opt.hbm_budget_bytes = budget_bytes
@@ -220,6 +228,35 @@ class Engine:
             arr = arr.reshape(-1, self.arity.get(name, 2))
         self._check(self._L.hl_load(self._h, name.encode(), arr.ctypes.data, arr.shape[0]),
                     "hl_load")
+
+    def batch_layout(self, id_ranges):
+        r = np.ascontiguousarray(id_ranges, dtype=np.uint32)
+        self._check(self._L.hl_batch_layout(self._h, r.ctypes.data, len(r)), "hl_batch_layout")
+
+    def load_batched(self, name: str, instances):
+        """``instances``: list of (n, 2) uint32 arrays with instance-local ids."""
+        rows = np.ascontiguousarray(np.concatenate(
+            [np.asarray(x, dtype=np.uint32).reshape(-1, 2) for x in instances]), dtype=np.uint32)
+        off = np.zeros(len(instances) + 1, dtype=np.uint64)
+        off[1:] = np.cumsum([len(np.asarray(x).reshape(-1, 2)) for x in instances])
+        self._check(self._L.hl_load_batched(self._h, name.encode(),
+                                            rows.ctypes.data if len(rows) else None,
+                                            off.ctypes.data), "hl_load_batched")
+
+    def batch_count(self, name: str, inst: int) -> int:
+        n = ctypes.c_uint64()
+        self._check(self._L.hl_batch_count(self._h, name.encode(), inst, ctypes.byref(n)),
+                    "hl_batch_count")
+        return n.value
+
+    def fetch_batched(self, name: str, inst: int) -> np.ndarray:
+        n = self.batch_count(name, inst)
+        out = np.empty((n, self.arity.get(name, 2)), dtype=np.uint32)
+        got = ctypes.c_uint64()
+        self._check(self._L.hl_fetch_batched(self._h, name.encode(), inst,
+                                             out.ctypes.data if n else None, n,
+                                             ctypes.byref(got)), "hl_fetch_batched")
+        return out
 
     def index(self, name: str, col: int):
         c = (ctypes.c_uint32 * 1)(col)
@@ -312,6 +349,19 @@ class Engine:
                                           shift, _ptr(queries), queries.numel(), _ptr(start),
                                           _ptr(length), ctypes.byref(runs)), "hl_hisa_query")
         return start, length, runs.value
+
+
+    def learned_query(self, keys, key_bits: int, queries):
+        """lower_bound positions of ``queries`` in sorted ``keys`` (CUDA
+        tensors of the same integer type) through a learned index."""
+        import torch
+        out = torch.empty(queries.numel(), dtype=torch.int32, device=keys.device)
+        self._check(self._L.hl_learned_query(self._h, _ptr(keys) if keys.numel() else None,
+                                             keys.numel(), _key_bytes(keys), key_bits,
+                                             _ptr(queries) if queries.numel() else None,
+                                             queries.numel(), _ptr(out) if queries.numel() else None),
+                    "hl_learned_query")
+        return out
 
 
 def evaluate(program: str, edb: dict, idb: dict, **engine_kw):

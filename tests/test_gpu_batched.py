@@ -1,0 +1,116 @@
+"""Batched evaluation of many independent instances in one fixpoint: each
+instance's part of the result must equal that instance evaluated alone by the
+oracle (bit-exact), for Reach and SG."""
+
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PROG = {n: open(os.path.join(ROOT, "workloads", "programs", n + ".dl")).read()
+        for n in ("reach", "sg")}
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def batched_engine(program, instances, ranges, idb, learned=False):
+    import torch
+    import paper_2311_02206_amd as pkg
+    torch.cuda.set_device(0)
+    e = pkg.Engine(device=0, stream=torch.cuda.current_stream(), learned=learned)
+    e.declare("Edge", 2, True)
+    for n in idb:
+        e.declare(n, 2, False)
+    e.batch_layout(ranges)
+    e.load_batched("Edge", instances)
+    e.program(program)
+    return e
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_batched_reach_matches_per_instance_oracle(learned):
+    say(f"batched reach, 48 instances, learned={learned}")
+    nodes, edges = workloads.batched_reach_instances(48, seed=0xC4)
+    e = batched_engine(PROG["reach"], edges, nodes, {"Reach": 2}, learned)
+    try:
+        st = e.run()
+        total = 0
+        for k in range(len(edges)):
+            want = oracle.evaluate(PROG["reach"], {"Edge": edges[k]}, {"Reach": 2})
+            got = e.fetch_batched("Reach", k)
+            assert np.array_equal(got, want.relations["Reach"]), k
+            total += len(got)
+        assert e.count("Reach") == total == st.idb_tuples
+    finally:
+        e.close()
+
+
+def test_batched_reach_iteration_totals():
+    """Per-iteration totals of the batch = sums of the instances' own
+    per-iteration deltas (BFS distance histograms), padded with zeros."""
+    say("batched reach iteration totals, 200 instances")
+    nodes, edges = workloads.batched_reach_instances(200, seed=7)
+    e = batched_engine(PROG["reach"], edges, nodes, {"Reach": 2})
+    try:
+        e.run()
+        got = e.iteration_counts("Reach", 0)
+        want = np.zeros(len(got), dtype=np.int64)
+        for k in range(len(edges)):
+            _, hist = oracle.reach_bfs_histogram(int(nodes[k]), edges[k], threads=4)
+            d = oracle.reach_deltas_from_histogram(hist)
+            assert len(d) <= len(got)
+            want[:len(d)] += d
+        assert got == want.tolist()
+    finally:
+        e.close()
+
+
+def test_batched_sg_trees():
+    say("batched sg on 30 trees")
+    trees = [workloads.random_tree(int(n), seed=int(n)) for n in np.linspace(2, 3000, 30)]
+    ranges = [len(t) + 1 for t in trees]
+    e = batched_engine(PROG["sg"], trees, ranges, {"SG": 2})
+    try:
+        e.run()
+        for k, t in enumerate(trees):
+            total, _ = oracle.sg_tree_closed_form(t) if len(t) else (0, [0])
+            got = e.fetch_batched("SG", k)
+            assert len(got) == total
+            if ranges[k] <= 600:
+                want = oracle.evaluate(PROG["sg"], {"Edge": t}, {"SG": 2})
+                assert np.array_equal(got, want.relations["SG"])
+    finally:
+        e.close()
+
+
+def test_batch_errors():
+    import torch
+    import paper_2311_02206_amd as pkg
+    say("batch errors")
+    with pkg.Engine(device=0, stream=torch.cuda.current_stream()) as e:
+        e.declare("Edge", 2, True)
+        e.declare("Reach", 2, False)
+        with pytest.raises(pkg.HlError):
+            e.load_batched("Edge", [np.array([[0, 1]], np.uint32)])  # no layout yet
+        e.batch_layout([4, 4])
+        with pytest.raises(pkg.HlError) as ei:
+            e.load_batched("Edge", [np.array([[0, 5]], np.uint32), np.zeros((0, 2), np.uint32)])
+        assert ei.value.code == pkg.hisalog.HL_E_INVALID  # id 5 outside range 4
+        e.load_batched("Edge", [np.array([[0, 1], [1, 2]], np.uint32),
+                                np.array([[3, 0]], np.uint32)])
+        e.program(PROG["reach"])
+        e.run()
+        assert e.fetch_batched("Reach", 0).tolist() == [[0, 1], [0, 2], [1, 2]]
+        assert e.fetch_batched("Reach", 1).tolist() == [[3, 0]]
+        with pytest.raises(pkg.HlError):
+            e.fetch_batched("Reach", 2)

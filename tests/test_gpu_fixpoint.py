@@ -205,6 +205,33 @@ def test_cspa_shaped_small():
                {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2})
 
 
+@pytest.mark.parametrize("case", ["reach_er1000", "sg_tree", "cspa", "wide", "nonlinear"])
+def test_learned_index_matches_plain(case):
+    """The learned position index replaces the hash probe and the membership
+    search; results must not change (and must match the oracle)."""
+    say(f"learned vs plain: {case}")
+    if case == "reach_er1000":
+        prog, edb, idb = PROG["reach"], workloads.reach_er_1000()["edb"], {"Reach": 2}
+    elif case == "sg_tree":
+        prog, edb, idb = PROG["sg"], workloads.scaled_tree(3000, seed=3)["edb"], {"SG": 2}
+    elif case == "cspa":
+        prog = PROG["cspa_shaped"]
+        edb = {"Assign": workloads.zipf_pairs(1 << 9, 300, 1.2, 0xC3, 0, orient="by_rank"),
+               "Dereference": workloads.zipf_pairs(1 << 9, 120, 1.2, 0xC3, 1, orient="by_rank")}
+        idb = {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2}
+    elif case == "wide":
+        E = workloads.reach_er_1000()["edb"]["Edge"].astype(np.uint64)
+        E = ((E * np.uint64(4294967291) + np.uint64(12345)) % np.uint64(1 << 32)).astype(np.uint32)
+        prog, edb, idb = PROG["reach"], {"Edge": E}, {"Reach": 2}
+    else:
+        prog = "T(x, y) :- E(x, y).\nT(x, y) :- T(x, z), T(z, y)."
+        edb, idb = {"E": workloads.scaled_rmat(10, 2500, seed=3)["edb"]["Edge"]}, {"T": 2}
+    rels, deltas, st, want = check_same(prog, edb, idb, learned=True)
+    r0, d0, _ = gpu_eval(prog, edb, idb)
+    for n in idb:
+        assert np.array_equal(rels[n], r0[n]) and deltas[n] == d0[n]
+
+
 def test_error_paths():
     import torch
     import paper_2311_02206_amd as pkg

@@ -139,3 +139,30 @@ def test_hisa_query(eng, kb, n):
     assert runs == len(np.unique(jk))
     assert np.array_equal(ln.cpu().numpy().astype(np.int64), want_len)
     assert np.array_equal(st.cpu().numpy(), want_start)
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("n,dist", [(0, "uniform"), (1, "uniform"), (100, "uniform"),
+                                    (100_000, "uniform"), (100_000, "clustered"),
+                                    (1_000_000, "zipf")])
+def test_learned_query(eng, kb, n, dist):
+    import torch
+    say(f"learned kb={kb} n={n} {dist}")
+    key_bits = 32 if kb == 4 else 44
+    top = (1 << key_bits) - 1
+    rng = np.random.default_rng(n + kb)
+    if dist == "uniform":
+        raw = rng.integers(0, top + 1, size=n, dtype=np.uint64)
+    elif dist == "clustered":
+        centers = rng.integers(0, top + 1, size=20, dtype=np.uint64)
+        raw = (centers[rng.integers(0, 20, size=n)] +
+               rng.integers(0, 5000, size=n, dtype=np.uint64)) & np.uint64(top)
+    else:
+        raw = (rng.zipf(1.3, size=n).astype(np.uint64) * np.uint64(977)) & np.uint64(top)
+    keys = np.unique(raw).astype(U[kb])
+    q = np.concatenate([keys, keys + 1, rng.integers(0, top + 1, size=5000, dtype=np.uint64),
+                        np.array([0, top, top - 1], dtype=np.uint64)]).astype(np.uint64)
+    q = (q & np.uint64(top)).astype(U[kb])
+    pos = eng.learned_query(to_dev(keys, kb), key_bits, to_dev(q, kb))
+    want = np.searchsorted(keys, q, side="left")
+    assert np.array_equal(pos.cpu().numpy().astype(np.int64), want)
