@@ -85,6 +85,21 @@ def verify_sg(e, edges, n_sample_rows=2000, seed=0):
     return bool(ok), total
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter passes
+    (profiles/<kernel>_traffic.json), or None when there are none or the
+    kernel's source has changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["hbm_bytes_per_launch"]
+
+
 def cpu_baseline(programs):
     """The oracle (single-threaded std::set semi-naive) on a bounded sample of
     the same workload: Reach on R-MAT scale 11 (2,048 nodes, 6,250 edges =
@@ -112,6 +127,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the learned-index run of the same workload")
+    ap.add_argument("--batched-instances", type=int, default=4096,
+                    help="independent Reach instances for the batched variant (0: skip)")
+    ap.add_argument("--one-at-a-time-sample", type=int, default=256)
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="copy this many MiB device-to-device once (a reference kernel of known "
+                         "size for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this build has no multi-GPU path); "
@@ -127,6 +148,13 @@ def main():
     stream = torch.cuda.current_stream()
     programs = {n: open(os.path.join(ROOT, "workloads", "programs", n + ".dl")).read()
                 for n in ("reach", "sg")}
+    if args.copy_calibration_mb > 0:
+        src = torch.ones(args.copy_calibration_mb << 18, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {args.copy_calibration_mb} MiB device to device")
+        del src, dst
     log("generating inputs")
     reach_wl = workloads.reach_rmat16()
     sg_wl = workloads.sg_tree_50k()
@@ -176,7 +204,8 @@ def main():
     achieved = (b_l / max(n_l, 1)) / avg_s / 1e9 if n_l else 0.0
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "launches": n_l, "avg_launch_us": round(avg_s * 1e6, 2),
+                "traffic": measured_traffic(dom), "launches": n_l,
+                "avg_launch_us": round(avg_s * 1e6, 2),
                 "algorithmic_bytes_per_launch": int(b_l / max(n_l, 1))}
 
     verified = None
@@ -200,7 +229,9 @@ def main():
         "config": {"workload": "reach_rmat16_200k+sg_tree_50k", "engine": "plain_hisa",
                    "reach_tuples": last["reach"].idb_tuples, "sg_tuples": last["sg"].idb_tuples,
                    "reach_iterations": last["reach"].iterations,
-                   "sg_iterations": last["sg"].iterations},
+                   "sg_iterations": last["sg"].iterations,
+                   "reach_candidates": last["reach"].candidates,
+                   "sg_candidates": last["sg"].candidates},
         "verified": verified,
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -215,9 +246,9 @@ def main():
         # HISA hash probe and the membership search; outputs must be identical
         log("learned-index variant")
         lengines = {
-            "reach": make_engine(programs["reach"], reach_wl["edb"], {"Reach": 2}, stream, False,
+            "reach": make_engine(programs["reach"], reach_wl["edb"], {"Reach": 2}, stream, True,
                                  learned=True),
-            "sg": make_engine(programs["sg"], sg_wl["edb"], {"SG": 2}, stream, False,
+            "sg": make_engine(programs["sg"], sg_wl["edb"], {"SG": 2}, stream, True,
                               learned=True),
         }
         for e in lengines.values():
@@ -225,9 +256,16 @@ def main():
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         lper = {k: 0.0 for k in lengines}
+        lk = {kn: [0, 0.0] for kn in KERNELS}
+        lphase = {}
         for i in range(args.steps):
             for k, e in lengines.items():
-                lper[k] += e.run().seconds
+                r = e.run()
+                lper[k] += r.seconds
+                lphase[k] = r.phase_ms
+                for kn, (n, ms, b) in e.kernel_stats().items():
+                    lk[kn][0] += n
+                    lk[kn][1] += ms
         torch.cuda.synchronize()
         lel = time.perf_counter() - t0
         same = all(lengines[k].count(n) == engines[k].count(n) and
@@ -239,12 +277,75 @@ def main():
         line["variants"] = {"learned_index": {
             "value": tuples / (lel / args.steps), "ms_per_step": lel / args.steps * 1e3,
             "vs_plain": (tuples / (lel / args.steps)) / value, "identical_output": bool(same),
-            "per_workload_ms": {k: lper[k] / args.steps * 1e3 for k in lengines}}}
+            "per_workload_ms": {k: lper[k] / args.steps * 1e3 for k in lengines},
+            "phase_ms": lphase,
+            "kernels_ms": {kn: round(v[1], 3) for kn, v in lk.items()}}}
         for e in lengines.values():
             e.close()
     for e in engines.values():
         e.close()
+    engines = {}
+    if args.batched_instances > 0:
+        try:
+            line.setdefault("variants", {})["batched"] = batched_variant(
+                stream, args.batched_instances, args.one_at_a_time_sample, max(1, args.steps),
+                programs["reach"], verify=not args.no_verify)
+        except Exception as exc:  # keep the main line whatever happens here
+            line.setdefault("variants", {})["batched"] = {"error": repr(exc)}
+    for e in engines.values():
+        e.close()
     print(json.dumps(line), flush=True)
+
+
+def batched_variant(stream, n_inst, sample, steps, program, verify=True):
+    """Batched Reach: n_inst independent instances (log-uniform 32..4096 nodes,
+    2-4x edges) in one engine, against the same instances run one at a time
+    (a sample of them, the rate extrapolated per tuple)."""
+    import torch
+    import workloads
+    from paper_2311_02206_amd import Engine
+    log(f"batched variant: generating {n_inst} instances")
+    nodes, edges = workloads.batched_reach_instances(n_inst, seed=0xC4)
+    e = Engine(device=0, stream=stream, ebm_k=1.5)
+    e.declare("Edge", 2, True)
+    e.declare("Reach", 2, False)
+    e.batch_layout(nodes)
+    e.load_batched("Edge", edges)
+    e.program(program)
+    e.run()  # warm-up
+    torch.cuda.synchronize()
+    t = 0.0
+    for _ in range(steps):
+        st = e.run()
+        t += st.seconds
+    t /= steps
+    log(f"batched: {st.idb_tuples} tuples, {st.iterations} iterations, {t * 1e3:.1f} ms")
+    sample = min(sample, n_inst)
+    one_t, one_tuples, same = 0.0, 0, True
+    for k in range(sample):
+        ek = Engine(device=0, stream=stream)
+        ek.declare("Edge", 2, True)
+        ek.declare("Reach", 2, False)
+        ek.load("Edge", edges[k])
+        ek.program(program)
+        ek.run()  # warm-up
+        sk = ek.run()
+        one_t += sk.seconds
+        one_tuples += sk.idb_tuples
+        if verify and (k < 16 or ek.count("Reach") != e.batch_count("Reach", k)):
+            same &= bool(np.array_equal(ek.fetch("Reach"), e.fetch_batched("Reach", k)))
+        ek.close()
+    value = st.idb_tuples / t
+    one_rate = one_tuples / one_t
+    out = {"workload": f"batched_reach_{n_inst}_instances", "value": value, "unit": "tuples/s",
+           "ms_per_fixpoint": t * 1e3, "tuples": st.idb_tuples, "iterations": st.iterations,
+           "key_bytes": st.key_bytes, "peak_bytes": st.peak_bytes, "ebm_k": 1.5,
+           "one_at_a_time": {"value": one_rate, "unit": "tuples/s", "sample_instances": sample,
+                             "ms": one_t * 1e3},
+           "vs_one_at_a_time": value / one_rate,
+           "sample_identical": bool(same) if verify else None}
+    e.close()
+    return out
 
 
 if __name__ == "__main__":

@@ -342,7 +342,8 @@ struct hl_engine {
   bool own_stream = false;
   u32 flags = 0;
   float ebm_k = 8.0f;
-  float load_factor = 0.8f;
+  float load_factor = 0.5f;
+  int sort_chunk_log2 = 31;
   Memory mem;
   std::string err;
 
@@ -358,10 +359,11 @@ struct hl_engine {
   // run state
   int w = 1;
   int key_bytes = 4;
-  Buf alt, tmp[2], ws, join_start, join_len, join_off, join_parts, rows;
+  Buf alt, tmp[2], ws, join_start, join_len, join_off, join_parts, rows, pend[2];
   u64* d_small = nullptr;  // device scalars
   u64* h_small = nullptr;  // pinned mirror
   static constexpr int kSmall = 512;
+  static constexpr int kChunkSlots = kSmall - 4;  // two scratch words; the last word is d_err
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, hipEvent_t>> marks;
@@ -699,8 +701,13 @@ struct hl_engine {
     if (col == 0) ix.n = R.n_full;
     const K* keys = col == 0 ? kp<K>(R.full) : kp<K>(ix.keys);
     ix.lm_ok = false;
-    if (ix.n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "indexed relation " + R.name +
-                                                           " has 2^32 or more tuples");
+    if (ix.n >= (u64(1) << 32)) {
+      // positions are 32-bit: a join inner this large is unsupported, a
+      // model only used by the set difference is skipped (binary search)
+      if (ix.used) fail(HL_E_UNSUPPORTED, "indexed relation " + R.name +
+                                              " has 2^32 or more tuples");
+      return;
+    }
     const int bits = hl::learned_bits(ix.n, 2 * w);
     const u64 bytes = hl::learned_bytes(bits);
     reserve(ix.lm, bytes, bytes);
@@ -751,7 +758,7 @@ struct hl_engine {
       for (auto& rc : todo) fit_model<K>(rels[rc.first], rc.second);
       return;
     }
-    if (todo.size() > kSmall) fail(HL_E_UNSUPPORTED, "too many indexes");
+    if (todo.size() > kChunkSlots) fail(HL_E_UNSUPPORTED, "too many indexes");
     for (size_t q = 0; q < todo.size(); ++q) {
       Relation& R = rels[todo[q].first];
       build_index<K>(R, todo[q].second, d_small + q);
@@ -927,6 +934,51 @@ struct hl_engine {
     }
   }
 
+  // Delta of a relation whose new tuples exceed one sort (2^31 keys): each
+  // chunk is sorted, cut down to its distinct tuples that are neither in
+  // full nor in the delta of the earlier chunks, and merged into that delta
+  // (the pieces are disjoint, so the merge needs no dedup).  Returns
+  // (|delta|, sum over chunks of their distinct tuples).
+  template <typename K>
+  std::pair<u64, u64> chunked_delta(Relation& R, const hl::LearnedView<K>* model) {
+    const u64 kChunk = u64(1) << sort_chunk_log2;
+    const int bits = 2 * w;
+    u64 p = 0, uniq = 0;
+    for (u64 c = 0; c < R.n_cand; c += kChunk) {
+      const u64 m = std::min(kChunk, R.n_cand - c);
+      K* chunk = kp<K>(R.cand) + c;
+      reserve_grow(alt, m * sizeof(K));
+      reserve(ws, hl::sort_workspace_bytes(m), hl::sort_workspace_bytes(m) * 2);
+      K* sorted = nullptr;
+      HIPCK(hl::radix_sort<K>(chunk, kp<K>(alt), m, bits, ws.p, stream, &sorted, kt(), d_err()));
+      K* other = sorted == chunk ? kp<K>(alt) : chunk;
+      reserve(ws, hl::unique_diff_workspace_bytes(m), hl::unique_diff_workspace_bytes(m) * 2);
+      u64* dc = d_small + kChunkSlots;  // scratch counts (not the per-relation slots)
+      u64* hc = h_small + kChunkSlots;
+      HIPCK(hl::unique_diff<K>(sorted, m, kp<K>(R.full), R.n_full, other, sorted, dc, ws.p,
+                               stream, kt(), model));
+      HIPCK(hipMemcpyAsync(hc, dc, 2 * sizeof(u64), hipMemcpyDeviceToHost, stream));
+      sync();
+      u64 d = hc[0];
+      uniq += hc[1];
+      if (p > 0 && d > 0) {
+        HIPCK(hl::unique_diff<K>(sorted, d, kp<K>(pend[0]), p, other, sorted, dc, ws.p,
+                                 stream, kt()));
+        HIPCK(hipMemcpyAsync(hc, dc, sizeof(u64), hipMemcpyDeviceToHost, stream));
+        sync();
+        d = hc[0];
+      }
+      if (d == 0) continue;
+      reserve(pend[1], (p + d) * sizeof(K), (p + d) * sizeof(K) * 2);
+      reserve(ws, hl::merge_workspace_bytes(p, d), hl::merge_workspace_bytes(p, d) * 2);
+      HIPCK(hl::merge<K>(kp<K>(pend[0]), p, sorted, d, kp<K>(pend[1]), ws.p, stream, kt()));
+      std::swap(pend[0], pend[1]);
+      p += d;
+    }
+    std::swap(R.delta, pend[0]);
+    return {p, uniq};
+  }
+
   // Sort + unique + subtraction of full for every IDB relation, then the
   // merges and index refreshes.  Returns the total delta size.
   template <typename K>
@@ -935,9 +987,10 @@ struct hl_engine {
     std::vector<int> idbs;
     for (int k = 0; k < int(rels.size()); ++k)
       if (!rels[k].edb) idbs.push_back(k);
-    if (2 * idbs.size() > kSmall) fail(HL_E_UNSUPPORTED, "too many relations");
+    if (2 * idbs.size() > kChunkSlots) fail(HL_E_UNSUPPORTED, "too many relations");
     // the deltas become the new outers: free their old contents
     mark(HL_PHASE_SORT);
+    std::vector<std::pair<size_t, std::pair<u64, u64>>> chunked;
     for (size_t q = 0; q < idbs.size(); ++q) {
       Relation& R = rels[idbs[q]];
       R.n_delta = 0;
@@ -945,8 +998,15 @@ struct hl_engine {
         HIPCK(hl::fill_zero(d_small + 2 * q, 2 * sizeof(u64), stream));
         continue;
       }
-      if (R.n_cand >= (u64(1) << 32))
-        fail(HL_E_UNSUPPORTED, "2^32 or more new tuples in one iteration");
+      if (R.n_cand > (u64(1) << sort_chunk_log2)) {
+        hl::LearnedView<K> mv{};
+        const bool use_model = learned() && R.n_full > 0 && R.idx[0].lm_ok &&
+                               R.idx[0].lm_keys == R.full.p && R.idx[0].lm_n == R.n_full;
+        if (use_model) mv = R.idx[0].view<K>();
+        chunked.push_back({q, chunked_delta<K>(R, use_model ? &mv : nullptr)});
+        HIPCK(hl::fill_zero(d_small + 2 * q, 2 * sizeof(u64), stream));
+        continue;
+      }
       reserve_grow(alt, R.n_cand * sizeof(K));
       reserve(ws, hl::sort_workspace_bytes(R.n_cand), hl::sort_workspace_bytes(R.n_cand) * 2);
       K* sorted = nullptr;
@@ -975,6 +1035,10 @@ struct hl_engine {
     sync();
     check_err();
     collect();
+    for (auto& c : chunked) {
+      h_small[2 * c.first] = c.second.first;
+      h_small[2 * c.first + 1] = c.second.second;
+    }
     u64 total = 0;
     std::vector<int> grown;
     mark(HL_PHASE_MERGE);
@@ -1182,7 +1246,7 @@ int hl_options_init(hl_options* opt) {
   if (!opt) return HL_E_INVALID;
   memset(opt, 0, sizeof(*opt));
   opt->ebm_k = 8.0f;
-  opt->hash_load_factor = 0.8f;
+  opt->hash_load_factor = 0.5f;
   return HL_OK;
 }
 
@@ -1197,6 +1261,8 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   for (u32 r : o.reserved)
     if (r) return HL_E_INVALID;
   if (o.arena && o.arena_bytes < 4096) return HL_E_INVALID;
+  if (o.sort_chunk_log2 != 0 && (o.sort_chunk_log2 < 12 || o.sort_chunk_log2 > 31))
+    return HL_E_INVALID;
   if (o.device == -1) {
     // planning-only engine: declarations and programs, no device work
     hl_engine* e = new (std::nothrow) hl_engine();
@@ -1216,6 +1282,7 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   e->flags = o.flags;
   e->ebm_k = o.ebm_k;
   e->load_factor = o.hash_load_factor;
+  e->sort_chunk_log2 = o.sort_chunk_log2 ? int(o.sort_chunk_log2) : 31;
   int rc = guard(e, [&] {
     if (o.stream) {
       e->stream = static_cast<hipStream_t>(o.stream);

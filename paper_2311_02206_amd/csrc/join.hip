@@ -177,6 +177,8 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
                                                      K* out, u64* cursor) {
   __shared__ u64 s_off[kTile];
   __shared__ u32 s_owner[kTile];
+  __shared__ u32 s_start[kTile];
+  __shared__ K s_outer[kTile];
   const u32 tile = blockIdx.x;
   const u64 d0 = u64(tile) * kTile;
   const u64 dend = n_outer + total;
@@ -184,7 +186,11 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   const u64 a0 = parts[tile], a1 = parts[tile + 1];
   const u64 b0 = d0 - a0, b1 = d1 - a1;
   const u32 la = u32(a1 - a0), lb = u32(b1 - b0);
-  for (u32 k = threadIdx.x; k < la; k += kNT) s_off[k] = off[a0 + k];
+  for (u32 k = threadIdx.x; k < la; k += kNT) {
+    s_off[k] = off[a0 + k];
+    s_start[k] = start[a0 + k];
+    s_outer[k] = outer[a0 + k];
+  }
   __syncthreads();
   // serial merge of this thread's slice of the tile's merged sequence
   {
@@ -225,9 +231,11 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
     const u64 j = b0 + k;
     if (k < lb) {
       const u32 i = s_owner[k];
-      const u64 oi = (u64(i) >= a0) ? s_off[u64(i) - a0] : off[i];
-      const u64 pos = u64(start[i]) + (j - oi);
-      const K ok = outer[i];
+      // the owner is in this tile's slice, or the run carried in from before
+      const bool here = u64(i) >= a0;
+      const u64 oi = here ? s_off[u64(i) - a0] : off[i];
+      const u64 pos = u64(here ? s_start[u64(i) - a0] : start[i]) + (j - oi);
+      const K ok = here ? s_outer[u64(i) - a0] : outer[i];
       const K c0 = ok >> js.w, c1 = ok & mask;
       const K o = inner[pos] & mask;
       const K x = pick(js.src0, c0, c1, o), y = pick(js.src1, c0, c1, o);

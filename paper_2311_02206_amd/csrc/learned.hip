@@ -22,45 +22,76 @@ namespace hl {
 namespace {
 
 constexpr int kNT = 256;
-constexpr int kEpsChunk = 32;  // keys per thread when measuring eps
 
+constexpr u32 kUnset = 0xffffffffu;
+constexpr u64 kGapPerKey = 64;  // table entries one key fills at most
+
+// table[r] = first position whose bucket is >= r.  Each key fills the
+// buckets between its predecessor's and its own, up to kGapPerKey of them;
+// longer gaps (head, tail, sparse regions) are left unset for the next pass.
 template <typename K>
-__global__ __launch_bounds__(kNT) void lm_table_kernel(const K* keys, u64 n, int shift, u32 T,
+__global__ __launch_bounds__(kNT) void lm_table_kernel(const K* keys, u64 n, int shift,
                                                        u32* table) {
   const u64 i = u64(blockIdx.x) * kNT + threadIdx.x;
   if (i >= n) return;
   const u64 b = u64(keys[i] >> shift);
   const u64 pb = i == 0 ? u64(0) : u64(keys[i - 1] >> shift) + 1;
-  // buckets pb..b start at position i (those in between are empty)
-  for (u64 r = pb; r <= b; ++r) table[r] = u32(i);
-  if (i == n - 1)
-    for (u64 r = b + 1; r <= T; ++r) table[r] = u32(n);
+  const u64 stop = (b - pb + 1 > kGapPerKey && b >= pb) ? pb + kGapPerKey - 1 : b;
+  for (u64 r = pb; r <= stop && r <= b; ++r) table[r] = u32(i);
 }
 
+// Unset entries: a binary search each (r == T is the end: n).
+template <typename K>
+__global__ __launch_bounds__(kNT) void lm_fill_kernel(const K* keys, u64 n, int shift, u64 T,
+                                                      u32* table) {
+  const u64 r = u64(blockIdx.x) * kNT + threadIdx.x;
+  if (r > T) return;
+  if (r == T) {
+    table[r] = u32(n);
+    return;
+  }
+  if (table[r] != kUnset) return;
+  const K x = K(r) << shift;
+  u64 a = 0, b = n;
+  while (a < b) {
+    const u64 mid = (a + b) >> 1;
+    if (keys[mid] < x) a = mid + 1;
+    else b = mid;
+  }
+  table[r] = u32(a);
+}
+
+__global__ __launch_bounds__(kNT) void lm_unset_kernel(u32* table, u64 cnt) {
+  const u64 stride = u64(gridDim.x) * kNT;
+  for (u64 i = u64(blockIdx.x) * kNT + threadIdx.x; i < cnt; i += stride) table[i] = kUnset;
+}
+
+// One lane per key.  Keys are sorted, so a bucket's keys are contiguous: a
+// segmented max over each wave's runs of equal bucket leaves the run's
+// maximum in its first lane, which alone updates eps.
 template <typename K>
 __global__ __launch_bounds__(kNT) void lm_eps_kernel(const K* keys, u64 n, int shift,
                                                      const u32* table, u32* eps) {
-  const u64 c = u64(blockIdx.x) * kNT + threadIdx.x;
-  const u64 i0 = c * kEpsChunk;
-  if (i0 >= n) return;
-  const u64 i1 = (i0 + kEpsChunk) < n ? i0 + kEpsChunk : n;
-  u32 cur = 0xffffffffu, best = 0;
-  for (u64 i = i0; i < i1; ++i) {
+  const u64 i = u64(blockIdx.x) * kNT + threadIdx.x;
+  const bool valid = i < n;
+  u32 r = 0xffffffffu, e = 0;
+  bool first = false;
+  if (valid) {
     const K k = keys[i];
-    const u32 r = u32(k >> shift);
-    if (r != cur) {
-      if (cur != 0xffffffffu && best) atomicMax(&eps[cur], best);
-      cur = r;
-      best = 0;
-    }
+    r = u32(k >> shift);
     const u32 lo = table[r], hi = table[r + 1];
     const float off = lm_offset(k, shift, lo, hi);
     // exact: a float and an integer below 2^32 are both exact in double
-    const double err = fabs(double(off) - double(u32(i) - lo));
-    const u32 e = u32(ceil(err));
-    best = e > best ? e : best;
+    e = u32(ceil(fabs(double(off) - double(u32(i) - lo))));
+    first = lane_id() == 0 || i == 0 || u32(keys[i - 1] >> shift) != r;
   }
-  if (best) atomicMax(&eps[cur], best);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const u32 eo = __shfl_down(e, d, kWave);
+    const u32 ro = __shfl_down(r, d, kWave);
+    if (lane_id() + d < kWave && ro == r && eo > e) e = eo;
+  }
+  if (valid && first && e) atomicMax(&eps[r], e);
 }
 
 __global__ __launch_bounds__(kNT) void lm_query_kernel(LearnedView<u32> lv, const u32* q, u64 nq,
@@ -104,11 +135,11 @@ hipError_t learned_fit(const K* keys, u64 n, int key_bits, int radix_bits, void*
     e = fill_zero(table, (T + 1) * sizeof(u32), s);
   } else {
     if (timer) timer->begin(K_LEARNED_FIT, s);
-    lm_table_kernel<K><<<dim3(u32((n + kNT - 1) / kNT)), kNT, 0, s>>>(keys, n, shift, u32(T),
-                                                                     table);
-    const u64 chunks = (n + kEpsChunk - 1) / kEpsChunk;
-    lm_eps_kernel<K><<<dim3(u32((chunks + kNT - 1) / kNT)), kNT, 0, s>>>(keys, n, shift, table,
-                                                                        eps);
+    const u64 tb = (T + 1 + kNT - 1) / kNT;
+    lm_unset_kernel<<<dim3(u32(tb < 65536 ? tb : 65536)), kNT, 0, s>>>(table, T + 1);
+    lm_table_kernel<K><<<dim3(u32((n + kNT - 1) / kNT)), kNT, 0, s>>>(keys, n, shift, table);
+    lm_fill_kernel<K><<<dim3(u32(tb)), kNT, 0, s>>>(keys, n, shift, T, table);
+    lm_eps_kernel<K><<<dim3(u32((n + kNT - 1) / kNT)), kNT, 0, s>>>(keys, n, shift, table, eps);
     if (timer) timer->end(K_LEARNED_FIT, s, 2 * n * sizeof(K) + (T + 1) * sizeof(u32));
     e = hipGetLastError();
   }

@@ -27,6 +27,8 @@ constexpr int kUdItems = 16;
 constexpr u64 kUdTile = u64(kUdNT) * kUdItems;
 constexpr u64 kUdStage = 4096;  // keys of full staged in LDS per tile
 
+__device__ __forceinline__ u32 pad(u32 i) { return i + i / kUdItems; }
+
 template <typename K>
 __device__ __forceinline__ u64 lower_bound(const K* a, u64 lo, u64 hi, K x) {
   while (lo < hi) {
@@ -52,32 +54,47 @@ __device__ __forceinline__ u64 upper_bound(const K* a, u64 lo, u64 hi, K x) {
 // full by walking the (LDS-staged) slice of full forward from the
 // lower bound of its first key; one block scan places the survivors, which
 // are written compacted (in order) at the tile's start in tmp.
+// part[t] = lower_bound(full, first candidate of tile t); part[ntiles] = nf.
+// One thread per tile, so the searches' latency overlaps across tiles.
+template <typename K, bool kModel>
+__global__ __launch_bounds__(kUdNT) void ud_partition_kernel(const K* cand, u64 n, const K* full,
+                                                             u64 nf, u64 ntiles, u64* part,
+                                                             LearnedView<K> lv) {
+  const u64 t = u64(blockIdx.x) * kUdNT + threadIdx.x;
+  if (t > ntiles) return;
+  if (t == ntiles) {
+    part[t] = nf;
+    return;
+  }
+  const K x = cand[t * kUdTile];
+  part[t] = kModel ? u64(lm_lower_bound(lv, x)) : lower_bound(full, u64(0), nf, x);
+}
+
 template <typename K, bool kModel>
 __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, const K* full,
                                                           u64 nf, K* tmp, u32* tile_counts,
-                                                          u64* d_unique, LearnedView<K> lv) {
+                                                          u64* d_unique, LearnedView<K> lv,
+                                                          const u64* part) {
   __shared__ u64 range[2];
   __shared__ K before;
   __shared__ u32 wsum[kUdNT / kWave];
   __shared__ u64 wsum64[kUdNT / kWave];
-  __shared__ K s_c[kUdTile];
+  // one padding slot per kUdItems keys: thread t reads keys t*16 .. t*16+15,
+  // which without padding would all fall in the same LDS banks
+  __shared__ K s_c[kUdTile + kUdTile / kUdItems];
   __shared__ K staged[kUdStage];
   const u32 tile = blockIdx.x;
   const u64 base = u64(tile) * kUdTile;
   const u32 cnt = u32((n - base) < kUdTile ? (n - base) : kUdTile);
   if (threadIdx.x == 0) {
-    const K first = cand[base], last = cand[base + cnt - 1];
-    if (kModel) {
-      range[0] = lm_lower_bound(lv, first);
-      u64 h = lm_lower_bound(lv, last);
-      range[1] = (h < nf && full[h] == last) ? h + 1 : h;
-    } else {
-      range[0] = lower_bound(full, 0, nf, first);
-      range[1] = upper_bound(full, range[0], nf, last);
-    }
+    // every candidate of the tile lies between the tile's first key and the
+    // next tile's first key, so its lower bound in full is in this slice
+    range[0] = part[tile];
+    const u64 h = part[tile + 1] + 1;
+    range[1] = h < nf ? h : nf;
     before = base > 0 ? cand[base - 1] : K(0);
   }
-  for (u32 k = threadIdx.x; k < cnt; k += kUdNT) s_c[k] = cand[base + k];
+  for (u32 k = threadIdx.x; k < cnt; k += kUdNT) s_c[pad(k)] = cand[base + k];
   __syncthreads();
   const u64 lo = range[0], hi = range[1];
   const u64 m = hi - lo;
@@ -90,13 +107,19 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
   u32 keep_bits = 0, nkeep = 0;
   u64 uniq = 0;
   if (b < cnt) {
-    u64 p = in_lds ? lower_bound(staged, u64(0), m, s_c[b]) : 0;
-    K prevk = b > 0 ? s_c[b - 1] : before;
+    // position of the first key in the staged slice, or (slice too large for
+    // LDS) in full itself; the thread's later keys walk forward from there
+    u64 p;
+    if (in_lds) p = lower_bound(staged, u64(0), m, s_c[pad(b)]);
+    else if (kModel) p = lm_lower_bound(lv, s_c[pad(b)]);
+    else p = lower_bound(full, lo, hi, s_c[pad(b)]);
+    if (!in_lds && p < lo) p = lo;
+    K prevk = b > 0 ? s_c[pad(b - 1)] : before;
 #pragma unroll
     for (int q = 0; q < kUdItems; ++q) {
       const u32 idx = b + q;
       if (idx < cnt) {
-        const K c = s_c[idx];
+        const K c = s_c[pad(idx)];
         const bool first = (base + idx == 0) || prevk != c;
         prevk = c;
         if (first) {
@@ -106,8 +129,12 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
             while (p < m && staged[p] < c) ++p;
             member = p < m && staged[p] == c;
           } else {
-            u64 g = kModel ? u64(lm_lower_bound(lv, c)) : lower_bound(full, lo, hi, c);
-            member = g < hi && full[g] == c;
+            // a short forward walk; fall back to a search when the gap is long
+            int steps = 0;
+            while (p < hi && full[p] < c && ++steps < 32) ++p;
+            if (p < hi && full[p] < c) p = kModel ? u64(lm_lower_bound(lv, c))
+                                                  : lower_bound(full, p, hi, c);
+            member = p < hi && full[p] == c;
           }
           if (!member) {
             keep_bits |= 1u << q;
@@ -123,13 +150,13 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
   // s_c happened before the scan's barriers), then out coalesced
   K mine[kUdItems];
 #pragma unroll
-  for (int q = 0; q < kUdItems; ++q) mine[q] = (b + q < cnt) ? s_c[b + q] : K(0);
+  for (int q = 0; q < kUdItems; ++q) mine[q] = (b + q < cnt) ? s_c[pad(b + q)] : K(0);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < kUdItems; ++q)
-    if (keep_bits & (1u << q)) s_c[pos++] = mine[q];
+    if (keep_bits & (1u << q)) s_c[pad(pos++)] = mine[q];
   __syncthreads();
-  for (u32 k = threadIdx.x; k < total; k += kUdNT) tmp[base + k] = s_c[k];
+  for (u32 k = threadIdx.x; k < total; k += kUdNT) tmp[base + k] = s_c[pad(k)];
   uniq = block_sum<kUdNT>(uniq, wsum64);
   if (threadIdx.x == 0) {
     tile_counts[tile] = total;
@@ -233,7 +260,7 @@ u64 mg_tiles(u64 n) { return (n + kMgTile - 1) / kMgTile; }
 
 u64 unique_diff_workspace_bytes(u64 n) {
   u64 nt = ud_tiles(n);
-  return align_up(nt * sizeof(u32), 256) + align_up(nt * sizeof(u64), 256) +
+  return align_up(nt * sizeof(u32), 256) + 2 * align_up((nt + 1) * sizeof(u64), 256) +
          scan_workspace_bytes(nt);
 }
 
@@ -250,16 +277,25 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   u32* tile_counts = reinterpret_cast<u32*>(p);
   p += align_up(nt * sizeof(u32), 256);
   u64* tile_off = reinterpret_cast<u64*>(p);
-  p += align_up(nt * sizeof(u64), 256);
-  if (timer) timer->begin(K_UNIQUE_DIFF, s);
+  p += align_up((nt + 1) * sizeof(u64), 256);
+  u64* part = reinterpret_cast<u64*>(p);
+  p += align_up((nt + 1) * sizeof(u64), 256);
   if (model && (model->keys != full || model->n != nf)) return hipErrorInvalidValue;
-  if (model)
+  const u32 pb = u32((nt + 1 + kUdNT - 1) / kUdNT);
+  if (timer) timer->begin(K_UNIQUE_DIFF, s);
+  if (model) {
+    ud_partition_kernel<K, true><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, part,
+                                                            *model);
     ud_select_kernel<K, true><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
-                                                              tile_counts, d_counts + 1, *model);
-  else
+                                                              tile_counts, d_counts + 1, *model,
+                                                              part);
+  } else {
+    ud_partition_kernel<K, false><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, part,
+                                                             LearnedView<K>{});
     ud_select_kernel<K, false><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
                                                                tile_counts, d_counts + 1,
-                                                               LearnedView<K>{});
+                                                               LearnedView<K>{}, part);
+  }
   // by definition: every candidate read once, each kept key written once;
   // the count of kept keys is not known here, so only the reads are counted
   if (timer) timer->end(K_UNIQUE_DIFF, s, n * sizeof(K));

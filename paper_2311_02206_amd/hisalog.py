@@ -51,7 +51,8 @@ class Options(ctypes.Structure):
         ("device", ctypes.c_int32), ("flags", ctypes.c_uint32), ("arena", ctypes.c_void_p),
         ("arena_bytes", ctypes.c_uint64), ("hbm_budget_bytes", ctypes.c_uint64),
         ("stream", ctypes.c_void_p), ("ebm_k", ctypes.c_float),
-        ("hash_load_factor", ctypes.c_float), ("reserved", ctypes.c_uint32 * 8),
+        ("hash_load_factor", ctypes.c_float), ("sort_chunk_log2", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 7),
     ]
 
 
@@ -155,8 +156,8 @@ class Engine:
     """One hisalog engine on one GPU (see include/hisalog.h)."""
 
     def __init__(self, device: int = 0, stream=None, arena=None, ebm: bool = True,
-                 ebm_k: float = 8.0, load_factor: float = 0.8, budget_bytes: int = 0,
-                 kernel_timing: bool = False, learned: bool = False):
+                 ebm_k: float = 8.0, load_factor: float = 0.5, budget_bytes: int = 0,
+                 kernel_timing: bool = False, learned: bool = False, sort_chunk_log2: int = 0):
         L = lib()
         opt = Options()
         L.hl_options_init(ctypes.byref(opt))
@@ -167,6 +168,7 @@ class Engine:
         opt.ebm_k = ebm_k
         opt.hash_load_factor = load_factor
         opt.hbm_budget_bytes = budget_bytes
+        opt.sort_chunk_log2 = sort_chunk_log2
         self._arena = arena  # keep the caller's tensor alive
         if arena is not None:
             opt.arena = _ptr(arena)

@@ -232,6 +232,19 @@ def test_learned_index_matches_plain(case):
         assert np.array_equal(rels[n], r0[n]) and deltas[n] == d0[n]
 
 
+@pytest.mark.parametrize("learned", [False, True])
+def test_chunked_new_tuples(learned):
+    """An iteration's new tuples beyond one sort chunk (forced here to 4,096
+    keys) are processed chunk by chunk; results must not change."""
+    say(f"chunked sort, learned={learned}")
+    wl = workloads.scaled_rmat(10, 3000, seed=8)
+    rels, deltas, st, want = check_same(PROG["reach"], wl["edb"], {"Reach": 2},
+                                        sort_chunk_log2=12, learned=learned)
+    assert st.candidates > 50 * 4096
+    wl = workloads.scaled_tree(2000, seed=2)
+    check_same(PROG["sg"], wl["edb"], {"SG": 2}, sort_chunk_log2=12, learned=learned)
+
+
 def test_error_paths():
     import torch
     import paper_2311_02206_amd as pkg

@@ -113,3 +113,34 @@ def test_reach_er_2p22_subcritical():
     wl = workloads.reach_er_2p22()
     st = check_reach(wl, [0, 1, 12345, (1 << 22) - 1])
     assert st.key_bytes == 8
+
+
+def test_batched_reach_4096_instances():
+    """4,096 independent Reach instances (log-uniform 32..4096 nodes, 2-4x
+    edges) in one batched fixpoint, as bench.py runs them: sampled instances
+    row by row against their own BFS closure, and every instance of a wider
+    sample by tuple count."""
+    import torch
+    import paper_2311_02206_amd as pkg
+    say("batched reach, 4096 instances")
+    nodes, edges = workloads.batched_reach_instances(4096, seed=0xC4)
+    e = pkg.Engine(device=0, stream=torch.cuda.current_stream(), ebm_k=1.5)
+    try:
+        e.declare("Edge", 2, True)
+        e.declare("Reach", 2, False)
+        e.batch_layout(nodes)
+        e.load_batched("Edge", edges)
+        e.program(PROG["reach"])
+        st = e.run()
+        say(f"  ran: {st.idb_tuples} tuples, {st.iterations} iterations, {st.seconds:.3f} s")
+        rng = np.random.default_rng(5)
+        for k in rng.choice(4096, 256, replace=False):
+            total, _ = oracle.reach_bfs_histogram(int(nodes[k]), edges[k], threads=8)
+            assert e.batch_count("Reach", int(k)) == total, k
+        for k in (0, 1, 4095, int(np.argmax(nodes))):
+            got = e.fetch_batched("Reach", k)
+            for s in (0, int(nodes[k]) // 2, int(nodes[k]) - 1):
+                lo, hi = np.searchsorted(got[:, 0], [s, s + 1])
+                assert np.array_equal(got[lo:hi, 1], oracle.reach_from(int(nodes[k]), edges[k], s))
+    finally:
+        e.close()
