@@ -46,8 +46,9 @@ extern "C" {
 
 /* ---------------------------------------------------------------- flags */
 #define HL_FLAG_NO_EBM 0x1u /* disable eager buffer management (exact-size
-                               buffers, reallocated on every growth: the
-                               paper's "Normal" column of Table 1) */
+                               buffers, reallocated on every growth, and
+                               every released block returned with hipFree:
+                               the paper's "Normal" column of Table 1) */
 #define HL_FLAG_KERNEL_TIMING 0x2u /* time every launch of the kernels listed
                                       under hl_kernel_stats with HIP events */
 #define HL_FLAG_LEARNED_INDEX 0x4u /* probe inner relations and test membership
@@ -85,8 +86,12 @@ typedef struct hl_options {
                                 by the engine); NULL: the engine allocates
                                 with hipMalloc up to hbm_budget_bytes */
   uint64_t arena_bytes;      /* size of arena */
-  uint64_t hbm_budget_bytes; /* cap on engine allocations when arena == NULL
-                                (0: no cap beyond the device) */
+  uint64_t hbm_budget_bytes; /* cap on the device memory the engine holds
+                                when arena == NULL: live buffers plus the
+                                released blocks it keeps for reuse (the
+                                latter are returned first when the cap or
+                                the device would be exceeded; 0: no cap
+                                beyond the device) */
   void* stream;              /* hipStream_t to enqueue on; NULL: own stream */
   float ebm_k;               /* growth factor k of Section 5.3: a buffer that
                                 must grow to hold |full| + |delta| is
@@ -110,7 +115,9 @@ typedef struct hl_stats {
   uint64_t idb_tuples;           /* sum over IDB relations of |full| at fixpoint */
   uint64_t candidates;           /* join outputs over all iterations */
   uint64_t peak_bytes;           /* peak device bytes held by the engine */
-  uint64_t allocations;          /* device allocations made during the run */
+  uint64_t allocations;          /* hipMalloc calls made during the run (blocks
+                                    reused from the engine's own released
+                                    blocks are not counted) */
   uint64_t ebm_reuses;           /* buffer requests served without allocating */
   double seconds;                /* wall time of hl_run (host clock) */
   double phase_ms[HL_PHASE_COUNT];

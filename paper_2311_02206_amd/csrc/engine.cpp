@@ -47,6 +47,17 @@ void hip_check(hipError_t e, const char* what) {
 // Device memory provider.  With a caller arena every buffer is carved out
 // of it (first fit, 256-byte aligned, coalescing free list); otherwise each
 // buffer is a hipMalloc, capped by the budget.
+// Device memory of one engine.  Two sources:
+//  * a caller-owned arena, carved first-fit with coalescing of free ranges;
+//  * hipMalloc under an optional budget.  Released blocks are kept in a
+//    cache and handed out again (smallest block that fits, at most twice the
+//    request), because hipMalloc of tens of GB stalls the host for seconds;
+//    the cache is emptied when the budget or the device would otherwise be
+//    exceeded, and at destruction.  With caching off every release is a
+//    hipFree (the per-iteration allocation behaviour that eager buffer
+//    management removes, kept for comparison).
+// Every user of the memory is on the engine's one stream, so a released
+// block may be reused by later stream work without a synchronisation.
 class Memory {
  public:
   void init(void* arena, u64 arena_bytes, u64 budget, hipStream_t s) {
@@ -60,10 +71,16 @@ class Memory {
       if (start < size_) free_[start] = size_ - start;
     }
   }
+  void set_caching(bool on) {
+    caching_ = on;
+    if (!on) trim(~u64(0));
+  }
 
-  void* alloc(u64 bytes) {
+  // Returns a block of at least `bytes`; its actual size goes to *got.
+  void* alloc(u64 bytes, u64* got = nullptr) {
     bytes = hl::align_up(bytes ? bytes : 1, 256);
     void* p = nullptr;
+    u64 size = bytes;
     if (base_) {
       for (auto it = free_.begin(); it != free_.end(); ++it) {
         if (it->second >= bytes) {
@@ -78,18 +95,35 @@ class Memory {
                                    std::to_string(in_use_) + " in use of " +
                                    std::to_string(size_));
     } else {
-      if (budget_ && in_use_ + bytes > budget_)
-        fail(HL_E_NOMEM, "device budget exceeded: need " + std::to_string(bytes) + " bytes");
-      hipError_t e = hipMalloc(&p, bytes);
-      if (e != hipSuccess) {
-        (void)hipGetLastError();
-        fail(HL_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+      auto it = cache_.lower_bound(bytes);
+      if (it != cache_.end() && it->first <= 2 * bytes) {
+        size = it->first;
+        p = it->second;
+        cache_.erase(it);
+        cached_ -= size;
+        ++hits_;
+      } else {
+        if (budget_ && in_use_ + cached_ + bytes > budget_)
+          trim(in_use_ + cached_ + bytes - budget_);
+        if (budget_ && in_use_ + bytes > budget_)
+          fail(HL_E_NOMEM, "device budget exceeded: need " + std::to_string(bytes) + " bytes");
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess && cached_) {
+          (void)hipGetLastError();
+          trim(~u64(0));
+          e = hipMalloc(&p, bytes);
+        }
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          fail(HL_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+        }
+        ++allocs_;
       }
     }
-    live_[p] = bytes;
-    in_use_ += bytes;
+    live_[p] = size;
+    in_use_ += size;
     peak_ = std::max(peak_, in_use_);
-    ++allocs_;
+    if (got) *got = size;
     return p;
   }
 
@@ -101,7 +135,6 @@ class Memory {
     live_.erase(it);
     in_use_ -= bytes;
     if (base_) {
-      // later stream work may reuse the range: every user is on one stream
       u64 off = static_cast<char*>(p) - base_;
       auto nx = free_.lower_bound(off);
       if (nx != free_.end() && off + bytes == nx->first) {
@@ -117,6 +150,9 @@ class Memory {
         }
       }
       free_[off] = bytes;
+    } else if (caching_) {
+      cache_.emplace(bytes, p);
+      cached_ += bytes;
     } else {
       (void)hipStreamSynchronize(stream_);
       (void)hipFree(p);
@@ -127,20 +163,40 @@ class Memory {
     std::vector<void*> ps;
     for (auto& kv : live_) ps.push_back(kv.first);
     for (void* p : ps) release(p);
+    trim(~u64(0));
   }
 
   u64 peak() const { return peak_; }
   u64 allocs() const { return allocs_; }
+  u64 cache_hits() const { return hits_; }
+  u64 held() const { return in_use_ + cached_; }
   void reset_counters() {
     peak_ = in_use_;
     allocs_ = 0;
+    hits_ = 0;
   }
 
  private:
+  // hipFree cached blocks, largest first, until `bytes` are returned.
+  void trim(u64 bytes) {
+    if (cache_.empty()) return;
+    (void)hipStreamSynchronize(stream_);
+    u64 done = 0;
+    while (!cache_.empty() && done < bytes) {
+      auto it = std::prev(cache_.end());
+      (void)hipFree(it->second);
+      done += it->first;
+      cached_ -= it->first;
+      cache_.erase(it);
+    }
+  }
+
   char* base_ = nullptr;
-  u64 size_ = 0, budget_ = 0, in_use_ = 0, peak_ = 0, allocs_ = 0;
+  u64 size_ = 0, budget_ = 0, in_use_ = 0, peak_ = 0, allocs_ = 0, hits_ = 0, cached_ = 0;
+  bool caching_ = true;
   hipStream_t stream_ = nullptr;
   std::map<u64, u64> free_;
+  std::multimap<u64, void*> cache_;
   std::unordered_map<void*, u64> live_;
 };
 
@@ -423,8 +479,7 @@ struct hl_engine {
     b.p = nullptr;
     b.bytes = 0;
     u64 sz = no_ebm ? need : std::max(need, want);
-    b.p = mem.alloc(sz);
-    b.bytes = sz;
+    b.p = mem.alloc(sz, &b.bytes);
   }
   void reserve_grow(Buf& b, u64 need) { reserve(b, need, need + need / 2); }
   // Like reserve_grow, but keeps the first `used` bytes of the buffer.
@@ -439,8 +494,7 @@ struct hl_engine {
     }
     Buf nb;
     const u64 sz = (flags & HL_FLAG_NO_EBM) ? need : need + need / 2;
-    nb.p = mem.alloc(sz);
-    nb.bytes = sz;
+    nb.p = mem.alloc(sz, &nb.bytes);
     if (used) HIPCK(hipMemcpyAsync(nb.p, b.p, used, hipMemcpyDeviceToDevice, stream));
     drop(b);
     b = nb;
@@ -744,14 +798,17 @@ struct hl_engine {
 
   // Refreshes every used index of the listed relations: column-1 copies
   // take the new delta (swapped, sorted, merged), then the hash tables are
-  // rebuilt from the run counts (one synchronisation for all of them).
+  // rebuilt from the run counts (one synchronisation for all of them), or
+  // the learned models refitted.  Only relations probed as join inners are
+  // refreshed; the set difference uses a model when one exists (a relation
+  // that is not an inner is searched directly, which costs less than a
+  // refit of its whole full relation after every merge).
   template <typename K>
   void refresh_indexes(const std::vector<int>& which) {
     std::vector<std::pair<int, int>> todo;
     for (int r : which)
       for (int c = 0; c < 2; ++c)
-        if (rels[r].idx[c].used || (c == 0 && learned() && !rels[r].edb))
-          todo.push_back({r, c});
+        if (rels[r].idx[c].used) todo.push_back({r, c});
     if (todo.empty()) return;
     if (learned()) {
       // the learned index needs no run count: no synchronisation
@@ -1291,6 +1348,7 @@ int hl_create(const hl_options* opt, hl_engine** out) {
       e->own_stream = true;
     }
     e->mem.init(o.arena, o.arena_bytes, o.hbm_budget_bytes, e->stream);
+    e->mem.set_caching(!(o.flags & HL_FLAG_NO_EBM));
     e->d_small = static_cast<u64*>(e->mem.alloc(hl_engine::kSmall * sizeof(u64)));
     HIPCK(hipHostMalloc(reinterpret_cast<void**>(&e->h_small), hl_engine::kSmall * sizeof(u64),
                         hipHostMallocDefault));

@@ -108,9 +108,11 @@ __global__ __launch_bounds__(kNT) void lm_query64_kernel(LearnedView<u64> lv, co
 
 }  // namespace
 
+// About 16 to 32 keys per bucket: the table stays small and the fit makes
+// few atomic updates, while a window search costs a few steps more.
 int learned_bits(u64 n, int key_bits) {
   int r = 4;
-  while (r < 24 && (u64(1) << (r + 2)) < n) ++r;
+  while (r < 24 && (u64(1) << (r + 4)) < n) ++r;
   return r < key_bits ? r : key_bits;
 }
 

@@ -28,20 +28,35 @@ __device__ __forceinline__ float lm_offset(K x, int shift, u32 lo, u32 hi) {
   return __fmul_rn(frac, float(hi - lo));
 }
 
-// First position whose key is >= x (n if none).
+// Positions [a, b] that hold the first position whose key is >= x: the
+// model's prediction widened by the bucket's error bound, clamped to the
+// bucket (a == b == n when x is beyond every bucket).
 template <typename K>
-__device__ __forceinline__ u32 lm_lower_bound(const LearnedView<K>& lv, K x) {
+__device__ __forceinline__ void lm_window(const LearnedView<K>& lv, K x, u64& a, u64& b) {
   const u64 r = u64(x >> lv.shift);
-  if (r >= lv.T) return u32(lv.n);
+  if (r >= lv.T) {
+    a = b = lv.n;
+    return;
+  }
   const u32 lo = lv.table[r], hi = lv.table[r + 1];
-  if (lo == hi) return lo;
+  if (lo == hi) {
+    a = b = lo;
+    return;
+  }
   const float off = lm_offset(x, lv.shift, lo, hi);
   const u64 f = u64(off);
   const u64 e = lv.eps[r];
-  u64 a = u64(lo) + (f > e ? f - e : 0);
-  u64 b = u64(lo) + f + e + 2;
+  a = u64(lo) + (f > e ? f - e : 0);
+  b = u64(lo) + f + e + 2;
   if (b > hi) b = hi;
   if (a > b) a = b;
+}
+
+// First position whose key is >= x (n if none).
+template <typename K>
+__device__ __forceinline__ u32 lm_lower_bound(const LearnedView<K>& lv, K x) {
+  u64 a, b;
+  lm_window(lv, x, a, b);
   while (a < b) {
     const u64 mid = (a + b) >> 1;
     if (lv.keys[mid] < x) a = mid + 1;

@@ -5,7 +5,7 @@
 // (Section 3.2, "Deduplication") and every tuple already in full is
 // removed, so delta and full stay disjoint.  Membership in full is a binary
 // search restricted to the slice of full spanned by the tile, staged in
-// LDS when it is small.
+// LDS when it is small, else run for all of a thread's keys in lockstep.
 //
 // merge: full := full U delta by merge path (Section 3.2, "Merge
 // operation", after Green, McColl and Bader 2012): a diagonal search splits
@@ -26,6 +26,7 @@ constexpr int kUdNT = 256;
 constexpr int kUdItems = 16;
 constexpr u64 kUdTile = u64(kUdNT) * kUdItems;
 constexpr u64 kUdStage = 4096;  // keys of full staged in LDS per tile
+constexpr int kUdLock = 8;      // keys searched in lockstep by one thread
 
 __device__ __forceinline__ u32 pad(u32 i) { return i + i / kUdItems; }
 
@@ -49,11 +50,6 @@ __device__ __forceinline__ u64 upper_bound(const K* a, u64 lo, u64 hi, K x) {
   return lo;
 }
 
-// One tile of sorted candidates: each thread takes kUdItems consecutive
-// keys, marks the first of each run of equal keys, and tests membership in
-// full by walking the (LDS-staged) slice of full forward from the
-// lower bound of its first key; one block scan places the survivors, which
-// are written compacted (in order) at the tile's start in tmp.
 // part[t] = lower_bound(full, first candidate of tile t); part[ntiles] = nf.
 // One thread per tile, so the searches' latency overlaps across tiles.
 template <typename K, bool kModel>
@@ -70,6 +66,12 @@ __global__ __launch_bounds__(kUdNT) void ud_partition_kernel(const K* cand, u64 
   part[t] = kModel ? u64(lm_lower_bound(lv, x)) : lower_bound(full, u64(0), nf, x);
 }
 
+// One tile of sorted candidates: each thread takes kUdItems consecutive
+// keys, marks the first of each run of equal keys, and tests membership in
+// the slice of full the tile spans: walking it forward in LDS when it fits
+// there, else by lockstep searches in global memory.  One block scan places
+// the survivors, which are written compacted (in order) at the tile's start
+// in tmp.
 template <typename K, bool kModel>
 __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, const K* full,
                                                           u64 nf, K* tmp, u32* tile_counts,
@@ -106,14 +108,9 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
   const u32 b = threadIdx.x * kUdItems;
   u32 keep_bits = 0, nkeep = 0;
   u64 uniq = 0;
-  if (b < cnt) {
-    // position of the first key in the staged slice, or (slice too large for
-    // LDS) in full itself; the thread's later keys walk forward from there
-    u64 p;
-    if (in_lds) p = lower_bound(staged, u64(0), m, s_c[pad(b)]);
-    else if (kModel) p = lm_lower_bound(lv, s_c[pad(b)]);
-    else p = lower_bound(full, lo, hi, s_c[pad(b)]);
-    if (!in_lds && p < lo) p = lo;
+  if (b < cnt && in_lds) {
+    // the slice is in LDS: search the thread's first key, walk forward
+    u64 p = lower_bound(staged, u64(0), m, s_c[pad(b)]);
     K prevk = b > 0 ? s_c[pad(b - 1)] : before;
 #pragma unroll
     for (int q = 0; q < kUdItems; ++q) {
@@ -124,21 +121,67 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
         prevk = c;
         if (first) {
           ++uniq;
-          bool member;
-          if (in_lds) {
-            while (p < m && staged[p] < c) ++p;
-            member = p < m && staged[p] == c;
-          } else {
-            // a short forward walk; fall back to a search when the gap is long
-            int steps = 0;
-            while (p < hi && full[p] < c && ++steps < 32) ++p;
-            if (p < hi && full[p] < c) p = kModel ? u64(lm_lower_bound(lv, c))
-                                                  : lower_bound(full, p, hi, c);
-            member = p < hi && full[p] == c;
-          }
-          if (!member) {
+          while (p < m && staged[p] < c) ++p;
+          if (!(p < m && staged[p] == c)) {
             keep_bits |= 1u << q;
             ++nkeep;
+          }
+        }
+      }
+    }
+  } else if (b < cnt) {
+    // The slice is too large for LDS, so candidates may be far apart in
+    // full.  Groups of kUdLock keys of the thread are searched together, one
+    // halving step at a time for all of them, so their global loads are in
+    // flight at once instead of forming one chain of dependent reads.
+    // Every key of a group has a search range of the same length L (the
+    // tile's slice, or the widest of the model's windows), so the steps are
+    // the same for all.
+    K prevk = b > 0 ? s_c[pad(b - 1)] : before;
+#pragma unroll 1
+    for (int g = 0; g < kUdItems; g += kUdLock) {
+      K c[kUdLock];
+      const K* at[kUdLock];
+      u64 L = m;
+#pragma unroll
+      for (int q = 0; q < kUdLock; ++q) {
+        const u32 idx = (b + g + q < cnt) ? b + g + q : cnt - 1;
+        c[q] = s_c[pad(idx)];
+        at[q] = full + lo;
+      }
+      if (kModel) {
+        u64 wa[kUdLock];
+        L = 0;
+#pragma unroll
+        for (int q = 0; q < kUdLock; ++q) {
+          u64 wb;
+          lm_window(lv, c[q], wa[q], wb);
+          L = (wb - wa[q]) > L ? (wb - wa[q]) : L;
+        }
+        // widening a window keeps the answer inside it; stay within full
+#pragma unroll
+        for (int q = 0; q < kUdLock; ++q) at[q] = full + (wa[q] < nf - L ? wa[q] : nf - L);
+      }
+      u64 len = L;
+      while (len > 1) {
+        const u64 half = len >> 1;
+#pragma unroll
+        for (int q = 0; q < kUdLock; ++q) at[q] = (at[q][half] < c[q]) ? at[q] + half : at[q];
+        len -= half;
+      }
+#pragma unroll
+      for (int q = 0; q < kUdLock; ++q) {
+        const u32 idx = b + g + q;
+        if (idx < cnt) {
+          const bool first = (base + idx == 0) || prevk != c[q];
+          prevk = c[q];
+          if (first) {
+            ++uniq;
+            const u64 pos = u64(at[q] - full) + ((L > 0 && *at[q] < c[q]) ? 1 : 0);
+            if (!(pos < nf && full[pos] == c[q])) {
+              keep_bits |= 1u << (g + q);
+              ++nkeep;
+            }
           }
         }
       }

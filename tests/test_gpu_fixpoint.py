@@ -205,6 +205,17 @@ def test_cspa_shaped_small():
                {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2})
 
 
+@pytest.mark.parametrize("learned", [False, True])
+def test_cspa_literal_2p11(learned):
+    """The CSPA-shaped program on the literal Zipf reading at 2^11 ids (781
+    Assign, 292 Dereference pairs): the largest size the std::set oracle
+    finishes in seconds."""
+    say(f"cspa literal 2^11, learned={learned}")
+    wl = workloads.cspa(11)
+    check_same(PROG["cspa_shaped"], wl["edb"],
+               {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2}, learned=learned)
+
+
 @pytest.mark.parametrize("case", ["reach_er1000", "sg_tree", "cspa", "wide", "nonlinear"])
 def test_learned_index_matches_plain(case):
     """The learned position index replaces the hash probe and the membership

@@ -7,7 +7,9 @@ are exact independent computations the oracle's pins already tie to it:
     compared row by row;
   * SG on a tree: the closed form gives the count and per-iteration deltas;
     sampled rows are checked against the same-depth definition, and the
-    output must be sorted, unique, irreflexive and symmetric.
+    output must be sorted, unique, irreflexive and symmetric;
+  * the CSPA-shaped program: naive evaluation over boolean matrices of the
+    active ids (every tuple and every per-iteration delta).
 """
 
 import os
@@ -23,7 +25,7 @@ pytestmark = pytest.mark.gpu
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 PROG = {n: open(os.path.join(ROOT, "workloads", "programs", n + ".dl")).read()
-        for n in ("reach", "sg")}
+        for n in ("reach", "sg", "cspa_shaped")}
 
 
 def say(msg):
@@ -31,11 +33,11 @@ def say(msg):
     sys.stdout.flush()
 
 
-def engine(program, edb, idb):
+def engine(program, edb, idb, learned=False):
     import torch
     import paper_2311_02206_amd as pkg
     torch.cuda.set_device(0)
-    e = pkg.Engine(device=0, stream=torch.cuda.current_stream())
+    e = pkg.Engine(device=0, stream=torch.cuda.current_stream(), learned=learned)
     for n in edb:
         e.declare(n, 2, True)
     for n, a in idb.items():
@@ -46,9 +48,9 @@ def engine(program, edb, idb):
     return e
 
 
-def check_reach(wl, sources):
+def check_reach(wl, sources, learned=False):
     E = wl["edb"]["Edge"]
-    e = engine(PROG["reach"], wl["edb"], {"Reach": 2})
+    e = engine(PROG["reach"], wl["edb"], {"Reach": 2}, learned=learned)
     try:
         st = e.run()
         say(f"  ran: {st.idb_tuples} tuples, {st.iterations} iterations, {st.seconds:.3f} s")
@@ -108,11 +110,42 @@ def test_sg_tree_50k():
         e.close()
 
 
-def test_reach_er_2p22_subcritical():
-    say("reach er 2^22 subcritical")
+@pytest.mark.parametrize("learned", [False, True])
+def test_reach_er_2p22_subcritical(learned):
+    say(f"reach er 2^22 subcritical, learned={learned}")
     wl = workloads.reach_er_2p22()
-    st = check_reach(wl, [0, 1, 12345, (1 << 22) - 1])
+    st = check_reach(wl, [0, 1, 12345, (1 << 22) - 1], learned=learned)
     assert st.key_bytes == 8
+
+
+_CSPA_WANT = {}
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_cspa_literal_2p14(learned):
+    """The CSPA-shaped program at the size bench.py times (2^14 ids, literal
+    Zipf reading, 6,250 Assign and 2,343 Dereference pairs: 9.2e6 tuples from
+    1.7e10 join candidates).  The std::set oracle would take hours; the
+    reference is the oracle's naive evaluator over boolean matrices, pinned
+    to the std::set oracle and brute force on smaller inputs."""
+    from oracle import matrix_naive
+    say(f"cspa literal 2^14, learned={learned}")
+    wl = workloads.cspa(14)
+    idb = {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2}
+    if not _CSPA_WANT:
+        _CSPA_WANT["r"] = matrix_naive.evaluate(PROG["cspa_shaped"], wl["edb"], idb)
+    want = _CSPA_WANT["r"]
+    e = engine(PROG["cspa_shaped"], wl["edb"], idb, learned=learned)
+    try:
+        st = e.run()
+        say(f"  ran: {st.idb_tuples} tuples, {st.iterations} iterations, {st.seconds:.3f} s, "
+            f"{st.candidates} candidates")
+        assert st.iterations == want.iterations
+        for n in idb:
+            assert e.iteration_counts(n, 0) == want.deltas[n], n
+            assert np.array_equal(e.fetch(n), want.relations[n]), n
+    finally:
+        e.close()
 
 
 def test_batched_reach_4096_instances():

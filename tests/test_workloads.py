@@ -16,6 +16,9 @@ def test_digests_are_stable():
     assert digest(w.rmat(10, 3000, 5)) == "5cd365a159f387cd"
     assert digest(w.random_tree(5000, 0xC2B)) == "d00fd2aaaeffb276"
     assert digest(w.zipf_pairs(1 << 12, 2000, 1.2, 0xC3, 0)) == "ea86097b9e5ec55c"
+    c = w.cspa()["edb"]
+    assert c["Assign"].shape == (6250, 2) and c["Dereference"].shape == (2343, 2)
+    assert digest(np.concatenate([c["Assign"], c["Dereference"]])) == "c1c00eaab811b86c"
     n, e = w.batched_reach_instances(8, 0xC4)
     assert n.tolist() == [84, 601, 1197, 2158, 162, 2772, 95, 85]
     assert digest(np.concatenate(e)) == "b384fb22bfa55c90"

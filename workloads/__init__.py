@@ -258,6 +258,22 @@ def reach_er_2p22():
             "edb": {"Edge": erdos_renyi(n, int(0.9 * n), 0xC5)}}
 
 
+def cspa(log2_ids: int = 14, orient: str = "literal", seed: int = 0xC3):
+    """The CSPA-shaped points-to program's EDB: Zipf(1.2) endpoints over
+    ``2^log2_ids`` variable ids, Assign and Dereference at the density of
+    400,000 and 150,000 pairs per 2^20 ids (so 6,250 and 2,343 pairs at
+    2^14).  Join candidates grow about sevenfold per doubling of the id
+    space (1.7e10 duplicates for 9.2e6 tuples at 2^14, literal reading),
+    and at 2^15 one iteration of every reading already needs more than
+    200 GB of candidates, so the default is the largest power of two where
+    the literal reading stays under 5e10 candidates and 2e9 tuples."""
+    ids = 1 << log2_ids
+    na, nd = int(400_000 * ids / (1 << 20)), int(150_000 * ids / (1 << 20))
+    return {"program": "cspa_shaped", "n_ids": ids, "orient": orient,
+            "edb": {"Assign": zipf_pairs(ids, na, 1.2, seed, 0, orient=orient),
+                    "Dereference": zipf_pairs(ids, nd, 1.2, seed, 1, orient=orient)}}
+
+
 def scaled_rmat(scale: int, n_edges: int, seed: int = 0xC2A):
     return {"program": REACH, "n_nodes": 1 << scale,
             "edb": {"Edge": rmat(scale, n_edges, seed)}}
