@@ -55,6 +55,18 @@ extern "C" {
                                       in full through a learned position index
                                       (see hl_learned_query) instead of the HISA
                                       hash; results are identical */
+#define HL_FLAG_JOIN_DEDUP 0x8u /* drop repeated join outputs inside an
+                                   expand tile: while a head relation's joins
+                                   produced at least 1.5 outputs per distinct
+                                   new tuple in the previous iteration (and in
+                                   the first one), the last join of each of
+                                   its rules groups its outer by the column
+                                   carried to the head and drops repeats
+                                   within each tile in LDS.  Results are
+                                   identical; fewer keys are sorted, at the
+                                   price of a slower expand (measured a net
+                                   loss at 2,048-slot tiles, hence off by
+                                   default) */
 
 /* Kernels reported by hl_kernel_stats. */
 #define HL_KERNEL_RADIX_HIST 0    /* digit histogram of one radix pass */
@@ -113,7 +125,9 @@ typedef struct hl_stats {
   uint32_t id_bits;              /* w: bits per column in a packed key */
   uint32_t reserved0;
   uint64_t idb_tuples;           /* sum over IDB relations of |full| at fixpoint */
-  uint64_t candidates;           /* join outputs over all iterations */
+  uint64_t candidates;           /* new tuples written for sorting over all
+                                    iterations (join outputs after filters
+                                    and in-tile dedup) */
   uint64_t peak_bytes;           /* peak device bytes held by the engine */
   uint64_t allocations;          /* hipMalloc calls made during the run (blocks
                                     reused from the engine's own released
@@ -121,6 +135,10 @@ typedef struct hl_stats {
   uint64_t ebm_reuses;           /* buffer requests served without allocating */
   double seconds;                /* wall time of hl_run (host clock) */
   double phase_ms[HL_PHASE_COUNT];
+  uint64_t join_outputs;         /* outputs of the joins (and one-atom rules)
+                                    whose results go to a head relation,
+                                    before filters and in-tile dedup;
+                                    `candidates` counts those kept */
 } hl_stats;
 
 /* Fills *opt with defaults: device 0, no arena, own stream, ebm_k 8,

@@ -334,6 +334,11 @@ struct Relation {
   u64 n_full = 0, n_delta = 0, n_cand = 0;
   Index idx[2];
   std::vector<u64> delta_counts, new_counts;
+  // in-tile dedup of the joins deriving this relation: on while they made
+  // at least 1.5 outputs per distinct new tuple (raw_cand: this iteration's
+  // outputs before filters and dedup)
+  bool dedup = true;
+  u64 raw_cand = 0;
 };
 
 // --------------------------------------------------------------- the parser
@@ -415,7 +420,7 @@ struct hl_engine {
   // run state
   int w = 1;
   int key_bytes = 4;
-  Buf alt, tmp[2], ws, join_start, join_len, join_off, join_parts, rows, pend[2];
+  Buf alt, tmp[2], ws, join_start, join_len, join_off, join_parts, rows, pend[2], grp[2];
   u64* d_small = nullptr;  // device scalars
   u64* h_small = nullptr;  // pinned mirror
   static constexpr int kSmall = 512;
@@ -905,6 +910,8 @@ struct hl_engine {
     if (p.steps.empty()) {
       JoinSpec js = p.proj;
       js.w = w;
+      H.raw_cand += n;
+      st.join_outputs += n;
       reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + n) * sizeof(K));
       const bool filtered = js.fa >= 0 || js.ea >= 0;
       if (filtered) {
@@ -934,6 +941,26 @@ struct hl_engine {
       JoinSpec js = s.js;
       js.w = w;
       if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "join outer side of 2^32 or more tuples");
+      const bool last = q + 1 == p.steps.size();
+      js.dd = (last && H.dedup && (flags & HL_FLAG_JOIN_DEDUP)) ? 1 : 0;
+      if (js.dd) {
+        // Group the outer by the column its outputs carry, so that repeats
+        // of one output come from neighbouring outer tuples and fall in one
+        // tile: a stable sort on that column's bits.  A delta or full outer
+        // is already sorted by column 0.
+        const int c = 1 - js.outer_col;
+        const int g = (js.src0 == c || js.src1 == c) ? c : js.outer_col;
+        if (!(g == 0 && q == 0)) {
+          reserve_grow(grp[0], n * sizeof(K));
+          reserve_grow(grp[1], n * sizeof(K));
+          HIPCK(hipMemcpyAsync(grp[0].p, cur, n * sizeof(K), hipMemcpyDeviceToDevice, stream));
+          reserve(ws, hl::sort_workspace_bytes(n), hl::sort_workspace_bytes(n) * 2);
+          K* grouped = nullptr;
+          HIPCK(hl::radix_sort_bits<K>(kp<K>(grp[0]), kp<K>(grp[1]), n, g == 0 ? w : 0,
+                                       g == 0 ? 2 * w : w, ws.p, stream, &grouped, kt()));
+          cur = grouped;
+        }
+      }
       reserve_grow(join_start, n * sizeof(u32));
       reserve_grow(join_len, n * sizeof(u32));
       reserve_grow(join_off, n * sizeof(u64));
@@ -952,8 +979,11 @@ struct hl_engine {
       sync();
       const u64 total = h_small[1];
       if (total == 0) return;
-      const bool last = q + 1 == p.steps.size();
-      const bool filtered = js.fa >= 0 || js.ea >= 0;
+      if (last) {
+        H.raw_cand += total;
+        st.join_outputs += total;
+      }
+      const bool filtered = js.fa >= 0 || js.ea >= 0 || js.dd;
       K* out;
       u64 base = 0;
       if (last) {
@@ -1102,6 +1132,8 @@ struct hl_engine {
     for (size_t q = 0; q < idbs.size(); ++q) {
       Relation& R = rels[idbs[q]];
       const u64 D = h_small[2 * q], U = h_small[2 * q + 1];
+      if (R.raw_cand > 0) R.dedup = double(R.raw_cand) >= 1.5 * double(U);
+      R.raw_cand = 0;
       R.n_delta = D;
       R.delta_counts.push_back(D);
       R.new_counts.push_back(U);
@@ -1163,6 +1195,8 @@ struct hl_engine {
       R.delta_counts.clear();
       R.new_counts.clear();
       R.n_delta = R.n_cand = 0;
+      R.dedup = true;
+      R.raw_cand = 0;
       R.idx[0].lm_ok = R.idx[1].lm_ok = false;
       if (!R.edb) {
         R.n_full = 0;

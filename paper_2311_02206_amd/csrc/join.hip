@@ -15,6 +15,12 @@
 //           search), so every lane emits about the same number of pairs
 //           whatever the run lengths, with coalesced reads of each run and
 //           coalesced writes.
+// When the outer is grouped by the column it carries into the output,
+// consecutive outer tuples produce outputs that share that column, and the
+// same output often comes from several of them (Reach: one target reached
+// through several middle nodes).  The expand can then drop the repeats
+// within each tile in an LDS hash set before they are written, so the sort
+// that follows moves fewer keys; the set of outputs is unchanged.
 #include "device.hpp"
 #include "kernels.hpp"
 
@@ -170,6 +176,33 @@ struct Compactor {
   }
 };
 
+// Outputs of one expand tile, deduplicated in an LDS hash set of
+// kDedupSlots keys with linear probing.  A tile emits at most kTile keys, so
+// the set is at most half full and every insertion finds its key or an
+// empty slot.  The all-ones key marks an empty slot; that one key value is
+// never dropped here (the sort and unique that follow remove its repeats).
+constexpr u32 kDedupSlots = 2 * u32(kTile);
+
+template <typename K>
+__device__ __forceinline__ bool first_in_tile(K* set, K v) {
+  const K empty = ~K(0);
+  if (v == empty) return true;
+  u32 h = mix32(u32(v) ^ u32(u64(v) >> 32)) & (kDedupSlots - 1);
+  for (u32 probe = 0; probe < kDedupSlots; ++probe) {
+    K prev;
+    if constexpr (sizeof(K) == 8)
+      prev = K(atomicCAS(reinterpret_cast<unsigned long long*>(set + h),
+                         (unsigned long long)empty, (unsigned long long)v));
+    else
+      prev = K(atomicCAS(reinterpret_cast<unsigned int*>(set + h), (unsigned int)empty,
+                         (unsigned int)v));
+    if (prev == empty) return true;
+    if (prev == v) return false;
+    h = (h + 1) & (kDedupSlots - 1);
+  }
+  return true;
+}
+
 template <typename K>
 __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer, const u64* off,
                                                      const u32* start, const K* inner,
@@ -215,12 +248,17 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
     }
   }
   __syncthreads();
-  const bool filtered = js.fa >= 0 || js.ea >= 0;
+  const bool filtered = js.fa >= 0 || js.ea >= 0 || js.dd;
   const K mask = (K(1) << js.w) - 1;
   __shared__ K s_keep[kTile];
   __shared__ u32 s_count;
   __shared__ u32 s_wsum[kNT / kWave];
   __shared__ u64 s_base;
+  // the dedup set lives in dynamic LDS, sized at launch only when js.dd
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  K* dset = reinterpret_cast<K*>(s_dyn);
+  if (js.dd)
+    for (u32 k = threadIdx.x; k < kDedupSlots; k += kNT) dset[k] = ~K(0);
   Compactor<K> cmp{s_keep, &s_count, s_wsum};
   if (threadIdx.x == 0) s_count = 0;
   __syncthreads();
@@ -242,6 +280,7 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
       v = (x << js.w) | y;
       keep = (js.fa < 0 || pick(js.fa, c0, c1, o) != pick(js.fb, c0, c1, o)) &&
              (js.ea < 0 || pick(js.ea, c0, c1, o) == pick(js.eb, c0, c1, o));
+      if (js.dd && keep) keep = first_in_tile(dset, v);
     }
     if (filtered) cmp.add(v, keep);  // block-uniform branch
     else if (k < lb) out[j] = v;
@@ -330,8 +369,9 @@ hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* s
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (timer) timer->begin(K_JOIN_EXPAND, s);
-  expand_kernel<K><<<dim3(u32(nt)), kNT, 0, s>>>(outer, n_outer, off, start, inner, total, js,
-                                                 parts, out, cursor);
+  const size_t dyn = js.dd ? kDedupSlots * sizeof(K) : 0;
+  expand_kernel<K><<<dim3(u32(nt)), kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, js,
+                                                   parts, out, cursor);
   // by definition: each inner tuple of a matched run read once, each output
   // written once, each outer tuple with its offset and run start read once
   if (timer) timer->end(K_JOIN_EXPAND, s,

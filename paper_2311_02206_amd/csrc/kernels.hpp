@@ -56,14 +56,19 @@ hipError_t scan_u32_u64(const u32* in, u64 n, u64* out, u64* d_total, void* ws, 
 
 // ---------------------------------------------------------- radix sort
 u64 sort_workspace_bytes(u64 n);
-// LSD radix sort of the low `bits` bits of n keys.  Ping-pongs between
-// `keys` and `alt`; *sorted receives whichever holds the result (the other
-// one is free afterwards).  n must be below 2^32.  If a look-back wait ran
-// out (the result is then wrong), a nonzero value is OR-ed into *d_err
-// (device memory) when d_err is given.
+// LSD radix sort of the low `bits` bits of n keys (the bits above must be
+// zero).  Ping-pongs between `keys` and `alt`; *sorted receives whichever
+// holds the result (the other one is free afterwards).  n must be below
+// 2^32.  d_err is unused (kept for a sort with bounded waits).
 template <typename K>
 hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted,
                       LaunchTimer* timer = nullptr, u32* d_err = nullptr);
+// Stable LSD radix sort on bits [lo_bit, hi_bit) of the keys only: keys
+// equal on those bits keep their input order (used to group an array by one
+// column).  Same buffers and limits as radix_sort.
+template <typename K>
+hipError_t radix_sort_bits(K* keys, K* alt, u64 n, int lo_bit, int hi_bit, void* ws,
+                           hipStream_t s, K** sorted, LaunchTimer* timer = nullptr);
 
 // --------------------------------------------- unique + set difference
 u64 unique_diff_workspace_bytes(u64 n);
@@ -139,7 +144,8 @@ struct JoinSpec {
   int src0, src1;
   int fa, fb;
   int ea, eb;
-  int w;  // id bits of a column
+  int w;   // id bits of a column
+  int dd;  // nonzero: drop outputs repeated within a tile (join_expand)
 };
 
 template <typename K>
@@ -154,6 +160,9 @@ hipError_t join_probe_learned(const K* outer, u64 n, const JoinSpec& js,
 u64 join_parts(u64 n_outer, u64 total);  // entries of the partition array
 // Expands every (outer, inner run) pair.  Without a filter, output j goes
 // to out[j]; with one, survivors are appended at *cursor (device, u64).
+// With js.dd, an output equal to an earlier output of the same tile (2,048
+// merged outer and output slots) is dropped as well, and the rest are
+// appended at *cursor: the result is the same set with fewer duplicates.
 template <typename K>
 hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* start,
                        const K* inner, u64 total, const JoinSpec& js, u64* parts, K* out,

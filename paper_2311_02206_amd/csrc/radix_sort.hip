@@ -31,28 +31,39 @@ constexpr u32 kWaveTile = kWave * kItems;
 constexpr u32 kChunk = 64;  // tiles per chunk of the column scan
 static_assert(kNT == kBuckets, "one thread per digit bucket");
 
-// Lanes of `valid` whose digit equals this lane's.
-__device__ __forceinline__ u64 peers_of(u32 d, u64 valid) {
+// Lanes of `valid` whose digit equals this lane's (digits of dbits bits:
+// the ballots of the bits above are skipped).
+__device__ __forceinline__ u64 peers_of(u32 d, u64 valid, int dbits) {
   u64 m = valid;
 #pragma unroll
   for (int b = 0; b < kBits; ++b) {
-    u64 bb = ballot((d >> b) & 1u);
-    m &= ((d >> b) & 1u) ? bb : ~bb;
+    if (b < dbits) {
+      u64 bb = ballot((d >> b) & 1u);
+      m &= ((d >> b) & 1u) ? bb : ~bb;
+    }
   }
   return m;
 }
 
+// A pass sorts on bits [shift, shift + dbits) of the key, dbits <= 8.
 template <typename K>
-__device__ __forceinline__ u32 digit(K k, int shift) {
-  return u32(k >> shift) & (kBuckets - 1);
+__device__ __forceinline__ u32 digit(K k, int shift, int dbits) {
+  return u32(k >> shift) & ((1u << dbits) - 1u);
 }
 
 // Per-tile digit histogram; counts are tile-major: counts[tile * 256 + d].
+// No ranks are needed here, so keys are counted with LDS atomic adds rather
+// than ballots.  Each quarter of a wave has its own sub-histogram (padded by
+// one word so that equal digits of different quarters fall in different
+// banks): a digit shared by every key of a wave serialises 16 lanes, not 64.
+constexpr int kSubs = kWaves * 4;
+constexpr int kSubStride = kBuckets + 1;
+
 template <typename K>
-__global__ __launch_bounds__(kNT) void rs_hist_kernel(const K* keys, u64 n, int shift, u32* counts,
-                                                      u32 ntiles) {
-  __shared__ u32 hist[kWaves * kBuckets];
-  for (int i = threadIdx.x; i < kWaves * kBuckets; i += kNT) hist[i] = 0;
+__global__ __launch_bounds__(kNT) void rs_hist_kernel(const K* keys, u64 n, int shift, int dbits,
+                                                      u32* counts, u32 ntiles) {
+  __shared__ u32 hist[kSubs * kSubStride];
+  for (int i = threadIdx.x; i < kSubs * kSubStride; i += kNT) hist[i] = 0;
   const u32 tile = xcd_tile(blockIdx.x, gridDim.x);
   const int w = threadIdx.x / kWave;
   const u64 base = u64(tile) * kTile + u64(w) * kWaveTile;
@@ -64,25 +75,17 @@ __global__ __launch_bounds__(kNT) void rs_hist_kernel(const K* keys, u64 n, int 
     key[j] = i < n ? keys[i] : K(0);
   }
   __syncthreads();
-  u32* h = hist + w * kBuckets;
-  const u64 lt = lanemask_lt();
+  u32* h = hist + (w * 4 + (lane_id() >> 4)) * kSubStride;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     u64 i = base + u64(j) * kWave + lane_id();
-    bool valid = i < n;
-    u32 d = digit(key[j], shift);
-    u64 vm = ballot(valid);
-    u64 peers = peers_of(d, vm);
-    // one lane per distinct digit adds the group's size; groups of later
-    // rounds read the value after this write (LDS is in order per wave)
-    if (valid && (peers & lt) == 0) h[d] += u32(popc(peers));
-    __builtin_amdgcn_wave_barrier();
+    if (i < n) atomicAdd(&h[digit(key[j], shift, dbits)], 1u);
   }
   __syncthreads();
   const int d = threadIdx.x;
   u32 c = 0;
 #pragma unroll
-  for (int q = 0; q < kWaves; ++q) c += hist[q * kBuckets + d];
+  for (int q = 0; q < kSubs; ++q) c += hist[q * kSubStride + d];
   counts[u64(tile) * kBuckets + d] = c;
 }
 
@@ -142,9 +145,9 @@ __global__ __launch_bounds__(kNT) void col_offsets_kernel(const u32* counts, u32
 
 template <typename K>
 __global__ __launch_bounds__(kNT) void rs_scatter_kernel(const K* in, K* out, u64 n, int shift,
-                                                         const u32* offsets, u32 ntiles) {
+                                                         int dbits, const u32* offsets,
+                                                         u32 ntiles) {
   __shared__ u32 whist[kWaves * kBuckets];
-  __shared__ u32 dstart[kBuckets];
   __shared__ u32 gbase[kBuckets];
   __shared__ u32 wsum[kWaves];
   __shared__ K tile_keys[kTile];
@@ -169,9 +172,9 @@ __global__ __launch_bounds__(kNT) void rs_scatter_kernel(const K* in, K* out, u6
   for (int j = 0; j < kItems; ++j) {
     u64 i = base + u64(j) * kWave + lane_id();
     bool valid = i < n;
-    u32 d = digit(key[j], shift);
+    u32 d = digit(key[j], shift, dbits);
     u64 vm = ballot(valid);
-    u64 peers = peers_of(d, vm);
+    u64 peers = peers_of(d, vm, dbits);
     u32 pre = valid ? h[d] : 0u;
     rank[j] = pre + u32(popc(peers & lt));
     if (valid && (peers & lt) == 0) h[d] = pre + u32(popc(peers));
@@ -189,23 +192,23 @@ __global__ __launch_bounds__(kNT) void rs_scatter_kernel(const K* in, K* out, u6
     }
     u32 tot;
     u32 ex = block_exclusive_scan<kNT>(run, wsum, tot);
-    dstart[d] = ex;
+    // each wave's slot of digit d: the digit's start in the tile plus the
+    // keys of digit d in earlier waves (one LDS read per key below)
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) whist[q * kBuckets + d] += ex;
     gbase[d] = gofs - ex;  // modular: gbase + p is the global position
   }
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     u64 i = base + u64(j) * kWave + lane_id();
-    if (i < n) {
-      u32 d = digit(key[j], shift);
-      tile_keys[dstart[d] + h[d] + rank[j]] = key[j];
-    }
+    if (i < n) tile_keys[h[digit(key[j], shift, dbits)] + rank[j]] = key[j];
   }
   __syncthreads();
   const u32 cnt = u32((n - tbase) < kTile ? (n - tbase) : kTile);
   for (u32 p = threadIdx.x; p < cnt; p += kNT) {
     K k = tile_keys[p];
-    out[u32(gbase[digit(k, shift)] + p)] = k;
+    out[u32(gbase[digit(k, shift, dbits)] + p)] = k;
   }
 }
 
@@ -221,13 +224,12 @@ u64 sort_workspace_bytes(u64 n) {
 }
 
 template <typename K>
-hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted,
-                      LaunchTimer* timer, u32* d_err) {
+hipError_t radix_sort_bits(K* keys, K* alt, u64 n, int lo_bit, int hi_bit, void* ws,
+                           hipStream_t s, K** sorted, LaunchTimer* timer) {
   *sorted = keys;
-  (void)d_err;  // this sort has no bounded waits that could run out
-  if (n <= 1 || bits <= 0) return hipSuccess;
+  if (hi_bit > int(8 * sizeof(K))) hi_bit = int(8 * sizeof(K));
+  if (n <= 1 || lo_bit < 0 || hi_bit <= lo_bit) return hipSuccess;
   if (n >= (u64(1) << 32)) return hipErrorInvalidValue;
-  if (bits > int(8 * sizeof(K))) bits = int(8 * sizeof(K));
   const u64 nt = tiles_of(n);
   const u64 nc = (nt + kChunk - 1) / kChunk;
   const u64 m = u64(kBuckets) * nt;
@@ -241,9 +243,10 @@ hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s,
   u32* total = reinterpret_cast<u32*>(p);
   K* src = keys;
   K* dst = alt;
-  for (int shift = 0; shift < bits; shift += kBits) {
+  for (int shift = lo_bit; shift < hi_bit; shift += kBits) {
+    const int dbits = (hi_bit - shift) < kBits ? (hi_bit - shift) : kBits;
     if (timer) timer->begin(K_RADIX_HIST, s);
-    rs_hist_kernel<K><<<dim3(u32(nt)), kNT, 0, s>>>(src, n, shift, counts, u32(nt));
+    rs_hist_kernel<K><<<dim3(u32(nt)), kNT, 0, s>>>(src, n, shift, dbits, counts, u32(nt));
     if (timer) timer->end(K_RADIX_HIST, s, n * sizeof(K) + m * sizeof(u32));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -253,7 +256,8 @@ hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s,
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (timer) timer->begin(K_RADIX_SCATTER, s);
-    rs_scatter_kernel<K><<<dim3(u32(nt)), kNT, 0, s>>>(src, dst, n, shift, offsets, u32(nt));
+    rs_scatter_kernel<K><<<dim3(u32(nt)), kNT, 0, s>>>(src, dst, n, shift, dbits, offsets,
+                                                       u32(nt));
     if (timer) timer->end(K_RADIX_SCATTER, s, 2 * n * sizeof(K) + m * sizeof(u32));
     e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -265,9 +269,20 @@ hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s,
   return hipSuccess;
 }
 
+template <typename K>
+hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted,
+                      LaunchTimer* timer, u32* d_err) {
+  (void)d_err;  // this sort has no bounded waits that could run out
+  return radix_sort_bits<K>(keys, alt, n, 0, bits, ws, s, sorted, timer);
+}
+
 template hipError_t radix_sort<u32>(u32*, u32*, u64, int, void*, hipStream_t, u32**,
                                     LaunchTimer*, u32*);
 template hipError_t radix_sort<u64>(u64*, u64*, u64, int, void*, hipStream_t, u64**,
                                     LaunchTimer*, u32*);
+template hipError_t radix_sort_bits<u32>(u32*, u32*, u64, int, int, void*, hipStream_t, u32**,
+                                         LaunchTimer*);
+template hipError_t radix_sort_bits<u64>(u64*, u64*, u64, int, int, void*, hipStream_t, u64**,
+                                         LaunchTimer*);
 
 }  // namespace hl

@@ -27,6 +27,7 @@ HL_E_UNSUPPORTED = -6
 HL_FLAG_NO_EBM = 0x1
 HL_FLAG_KERNEL_TIMING = 0x2
 HL_FLAG_LEARNED_INDEX = 0x4
+HL_FLAG_JOIN_DEDUP = 0x8
 KERNELS = ("radix_hist", "radix_scatter", "unique_diff", "merge", "join_probe", "join_expand",
            "hisa_build", "learned_fit")
 PHASES = ("index_edb", "join", "sort", "diff", "merge", "index")
@@ -64,6 +65,7 @@ class Stats(ctypes.Structure):
         ("peak_bytes", ctypes.c_uint64), ("allocations", ctypes.c_uint64),
         ("ebm_reuses", ctypes.c_uint64), ("seconds", ctypes.c_double),
         ("phase_ms", ctypes.c_double * len(PHASES)),
+        ("join_outputs", ctypes.c_uint64),
     ]
 
     def as_dict(self) -> dict:
@@ -150,6 +152,7 @@ class RunStats:
     ebm_reuses: int
     seconds: float
     phase_ms: dict = field(default_factory=dict)
+    join_outputs: int = 0
 
 
 class Engine:
@@ -157,14 +160,16 @@ class Engine:
 
     def __init__(self, device: int = 0, stream=None, arena=None, ebm: bool = True,
                  ebm_k: float = 8.0, load_factor: float = 0.5, budget_bytes: int = 0,
-                 kernel_timing: bool = False, learned: bool = False, sort_chunk_log2: int = 0):
+                 kernel_timing: bool = False, learned: bool = False, sort_chunk_log2: int = 0,
+                 join_dedup: bool = False):
         L = lib()
         opt = Options()
         L.hl_options_init(ctypes.byref(opt))
         opt.device = device
         opt.flags = ((0 if ebm else HL_FLAG_NO_EBM) |
                      (HL_FLAG_KERNEL_TIMING if kernel_timing else 0) |
-                     (HL_FLAG_LEARNED_INDEX if learned else 0))
+                     (HL_FLAG_LEARNED_INDEX if learned else 0) |
+                     (HL_FLAG_JOIN_DEDUP if join_dedup else 0))
         opt.ebm_k = ebm_k
         opt.hash_load_factor = load_factor
         opt.hbm_budget_bytes = budget_bytes

@@ -205,6 +205,36 @@ def test_cspa_shaped_small():
                {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2})
 
 
+@pytest.mark.parametrize("case", ["reach_rmat", "sg_tree", "cspa", "wide", "nonlinear"])
+def test_join_dedup_matches_plain(case):
+    """Dropping repeated join outputs inside a tile (HL_FLAG_JOIN_DEDUP) must
+    not change any result; it only lowers the number of keys sorted."""
+    say(f"join dedup on/off: {case}")
+    if case == "reach_rmat":
+        prog, edb, idb = PROG["reach"], workloads.scaled_rmat(11, 6000, seed=4)["edb"], {"Reach": 2}
+    elif case == "sg_tree":
+        prog, edb, idb = PROG["sg"], workloads.scaled_tree(3000, seed=3)["edb"], {"SG": 2}
+    elif case == "cspa":
+        prog, edb = PROG["cspa_shaped"], workloads.cspa(10)["edb"]
+        idb = {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2}
+    elif case == "wide":
+        E = workloads.reach_er_1000()["edb"]["Edge"].astype(np.uint64)
+        E = ((E * np.uint64(4294967291) + np.uint64(12345)) % np.uint64(1 << 32)).astype(np.uint32)
+        prog, edb, idb = PROG["reach"], {"Edge": E}, {"Reach": 2}
+    else:
+        prog = "T(x, y) :- E(x, y).\nT(x, y) :- T(x, z), T(z, y)."
+        edb, idb = {"E": workloads.scaled_rmat(10, 2500, seed=3)["edb"]["Edge"]}, {"T": 2}
+    rels, deltas, st, want = check_same(prog, edb, idb, join_dedup=True)
+    r0, d0, st0 = gpu_eval(prog, edb, idb)
+    for n in idb:
+        assert np.array_equal(rels[n], r0[n]) and deltas[n] == d0[n]
+    assert st.join_outputs == st0.join_outputs
+    assert st.candidates <= st.join_outputs
+    assert st0.candidates <= st0.join_outputs
+    if case in ("reach_rmat", "cspa", "nonlinear"):
+        assert st.candidates < st0.candidates  # duplicates were dropped
+
+
 @pytest.mark.parametrize("learned", [False, True])
 def test_cspa_literal_2p11(learned):
     """The CSPA-shaped program on the literal Zipf reading at 2^11 ids (781
