@@ -251,7 +251,6 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   const bool filtered = js.fa >= 0 || js.ea >= 0 || js.dd;
   const K mask = (K(1) << js.w) - 1;
   __shared__ K s_keep[kTile];
-  __shared__ u32 s_count;
   __shared__ u32 s_wsum[kNT / kWave];
   __shared__ u64 s_base;
   // the dedup set lives in dynamic LDS, sized at launch only when js.dd
@@ -259,33 +258,60 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   K* dset = reinterpret_cast<K*>(s_dyn);
   if (js.dd)
     for (u32 k = threadIdx.x; k < kDedupSlots; k += kNT) dset[k] = ~K(0);
-  Compactor<K> cmp{s_keep, &s_count, s_wsum};
-  if (threadIdx.x == 0) s_count = 0;
-  __syncthreads();
-  for (u32 kk = 0; kk < lb; kk += kNT) {
-    const u32 k = kk + threadIdx.x;
-    bool keep = false;
-    K v = 0;
-    const u64 j = b0 + k;
+  if (js.dd) __syncthreads();
+  // each thread's kItems outputs (strided, so reads of each inner run and
+  // the unfiltered writes are coalesced), computed with every load issued
+  // before any is used
+  K v[kItems];
+  u32 keep = 0;
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const u32 k = u32(r) * kNT + threadIdx.x;
+    v[r] = 0;
     if (k < lb) {
       const u32 i = s_owner[k];
       // the owner is in this tile's slice, or the run carried in from before
       const bool here = u64(i) >= a0;
       const u64 oi = here ? s_off[u64(i) - a0] : off[i];
-      const u64 pos = u64(here ? s_start[u64(i) - a0] : start[i]) + (j - oi);
+      const u64 pos = u64(here ? s_start[u64(i) - a0] : start[i]) + (b0 + k - oi);
       const K ok = here ? s_outer[u64(i) - a0] : outer[i];
       const K c0 = ok >> js.w, c1 = ok & mask;
       const K o = inner[pos] & mask;
       const K x = pick(js.src0, c0, c1, o), y = pick(js.src1, c0, c1, o);
-      v = (x << js.w) | y;
-      keep = (js.fa < 0 || pick(js.fa, c0, c1, o) != pick(js.fb, c0, c1, o)) &&
-             (js.ea < 0 || pick(js.ea, c0, c1, o) == pick(js.eb, c0, c1, o));
-      if (js.dd && keep) keep = first_in_tile(dset, v);
+      v[r] = (x << js.w) | y;
+      const bool pass = (js.fa < 0 || pick(js.fa, c0, c1, o) != pick(js.fb, c0, c1, o)) &&
+                        (js.ea < 0 || pick(js.ea, c0, c1, o) == pick(js.eb, c0, c1, o));
+      if (pass) keep |= 1u << r;
     }
-    if (filtered) cmp.add(v, keep);  // block-uniform branch
-    else if (k < lb) out[j] = v;
   }
-  if (filtered) cmp.flush(out, cursor, &s_base);
+  if (!filtered) {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const u32 k = u32(r) * kNT + threadIdx.x;
+      if (k < lb) out[b0 + k] = v[r];
+    }
+    return;
+  }
+  if (js.dd) {
+#pragma unroll
+    for (int r = 0; r < kItems; ++r)
+      if ((keep >> r) & 1u)
+        if (!first_in_tile(dset, v[r])) keep &= ~(1u << r);
+  }
+  // one block scan places every survivor of the tile in LDS, then one
+  // atomic claims the tile's output range
+  u32 tot;
+  u32 pos = block_exclusive_scan<kNT>(u32(__popc(keep)), s_wsum, tot);
+#pragma unroll
+  for (int r = 0; r < kItems; ++r)
+    if ((keep >> r) & 1u) s_keep[pos++] = v[r];
+  if (threadIdx.x == 0)
+    s_base = tot ? atomicAdd(reinterpret_cast<unsigned long long*>(cursor),
+                             (unsigned long long)tot)
+                 : 0;
+  __syncthreads();
+  const u64 ob = s_base;
+  for (u32 k = threadIdx.x; k < tot; k += kNT) out[ob + k] = s_keep[k];
 }
 
 template <typename K>

@@ -27,6 +27,7 @@ constexpr int kUdItems = 16;
 constexpr u64 kUdTile = u64(kUdNT) * kUdItems;
 constexpr u64 kUdStage = 4096;  // keys of full staged in LDS per tile
 constexpr int kUdLock = 8;      // keys searched in lockstep by one thread
+constexpr u64 kUdStreamMax = 8 * kUdStage;  // longest slice streamed through LDS
 
 __device__ __forceinline__ u32 pad(u32 i) { return i + i / kUdItems; }
 
@@ -68,19 +69,22 @@ __global__ __launch_bounds__(kUdNT) void ud_partition_kernel(const K* cand, u64 
 
 // One tile of sorted candidates: each thread takes kUdItems consecutive
 // keys, marks the first of each run of equal keys, and tests membership in
-// the slice of full the tile spans: walking it forward in LDS when it fits
-// there, else by lockstep searches in global memory.  One block scan places
-// the survivors, which are written compacted (in order) at the tile's start
-// in tmp.
+// the slice of full the tile spans.  A slice of up to kUdStreamMax keys is
+// streamed through LDS in chunks of kUdStage keys, and each key is resolved
+// in the first chunk whose last key is not below it (the keys of earlier
+// chunks are all smaller); a longer slice is searched in global memory by
+// lockstep searches.  One block scan places the survivors, which are written
+// compacted (in order) at the tile's start in tmp.  The tile's kept and
+// distinct counts go to tile_counts and tile_uniq.
 template <typename K, bool kModel>
 __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, const K* full,
                                                           u64 nf, K* tmp, u32* tile_counts,
-                                                          u64* d_unique, LearnedView<K> lv,
+                                                          u32* tile_uniq, LearnedView<K> lv,
                                                           const u64* part) {
   __shared__ u64 range[2];
   __shared__ K before;
   __shared__ u32 wsum[kUdNT / kWave];
-  __shared__ u64 wsum64[kUdNT / kWave];
+  __shared__ u32 wsum2[kUdNT / kWave];
   // one padding slot per kUdItems keys: thread t reads keys t*16 .. t*16+15,
   // which without padding would all fall in the same LDS banks
   __shared__ K s_c[kUdTile + kUdTile / kUdItems];
@@ -100,37 +104,73 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
   __syncthreads();
   const u64 lo = range[0], hi = range[1];
   const u64 m = hi - lo;
-  const bool in_lds = m <= kUdStage;
-  if (in_lds) {
-    for (u32 k = threadIdx.x; k < m; k += kUdNT) staged[k] = full[lo + k];
-  }
-  __syncthreads();
   const u32 b = threadIdx.x * kUdItems;
-  u32 keep_bits = 0, nkeep = 0;
-  u64 uniq = 0;
-  if (b < cnt && in_lds) {
-    // the slice is in LDS: search the thread's first key, walk forward
-    u64 p = lower_bound(staged, u64(0), m, s_c[pad(b)]);
-    K prevk = b > 0 ? s_c[pad(b - 1)] : before;
+  u32 keep_bits = 0, nkeep = 0, uniq = 0;
+  if (m <= kUdStreamMax) {
+    // first-of-run flags, then resolution chunk by chunk
+    u32 first_bits = 0;
+    if (b < cnt) {
+      K prevk = b > 0 ? s_c[pad(b - 1)] : before;
 #pragma unroll
-    for (int q = 0; q < kUdItems; ++q) {
-      const u32 idx = b + q;
-      if (idx < cnt) {
-        const K c = s_c[pad(idx)];
-        const bool first = (base + idx == 0) || prevk != c;
-        prevk = c;
-        if (first) {
-          ++uniq;
-          while (p < m && staged[p] < c) ++p;
-          if (!(p < m && staged[p] == c)) {
-            keep_bits |= 1u << q;
-            ++nkeep;
+      for (int q = 0; q < kUdItems; ++q) {
+        const u32 idx = b + q;
+        if (idx < cnt) {
+          const K c = s_c[pad(idx)];
+          if ((base + idx == 0) || prevk != c) first_bits |= 1u << q;
+          prevk = c;
+        }
+      }
+    }
+    uniq = u32(__popc(first_bits));
+    u32 pending = first_bits;  // distinct keys not yet resolved
+    // each thread holds its share of the next chunk in registers, loaded
+    // while the current chunk is searched
+    constexpr int kPer = int(kUdStage / kUdNT);
+    K next[kPer];
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const u64 i = lo + u64(r) * kUdNT + threadIdx.x;
+      next[r] = i < hi ? full[i] : K(0);
+    }
+    for (u64 c0 = lo; c0 < hi; c0 += kUdStage) {  // block-uniform trip count
+      const u32 cm = u32((hi - c0) < kUdStage ? (hi - c0) : kUdStage);
+      __syncthreads();  // the previous chunk is no longer read
+#pragma unroll
+      for (int r = 0; r < kPer; ++r) staged[r * kUdNT + threadIdx.x] = next[r];
+      __syncthreads();
+      const u64 c1 = c0 + kUdStage;
+      if (c1 < hi) {
+#pragma unroll
+        for (int r = 0; r < kPer; ++r) {
+          const u64 i = c1 + u64(r) * kUdNT + threadIdx.x;
+          next[r] = i < hi ? full[i] : K(0);
+        }
+      }
+      if (pending) {
+        const K clast = staged[cm - 1];
+        const int q0 = __ffs(pending) - 1;
+        if (s_c[pad(b + q0)] <= clast) {
+          // search the first pending key, walk forward for the others
+          u32 p = u32(lower_bound(staged, u64(0), u64(cm), s_c[pad(b + q0)]));
+          for (int q = q0; q < kUdItems; ++q) {
+            if (!(pending & (1u << q))) continue;
+            const K c = s_c[pad(b + q)];
+            if (c > clast) break;
+            while (staged[p] < c) ++p;  // stops at or before cm - 1
+            pending &= ~(1u << q);
+            if (staged[p] != c) {
+              keep_bits |= 1u << q;
+              ++nkeep;
+            }
           }
         }
       }
     }
+    // keys above the whole slice are not in full
+    keep_bits |= pending;
+    nkeep += u32(__popc(pending));
   } else if (b < cnt) {
-    // The slice is too large for LDS, so candidates may be far apart in
+    // The slice is too long to stream, so candidates may be far apart in
     // full.  Groups of kUdLock keys of the thread are searched together, one
     // halving step at a time for all of them, so their global loads are in
     // flight at once instead of forming one chain of dependent reads.
@@ -200,10 +240,10 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
     if (keep_bits & (1u << q)) s_c[pad(pos++)] = mine[q];
   __syncthreads();
   for (u32 k = threadIdx.x; k < total; k += kUdNT) tmp[base + k] = s_c[pad(k)];
-  uniq = block_sum<kUdNT>(uniq, wsum64);
+  uniq = block_sum<kUdNT>(uniq, wsum2);
   if (threadIdx.x == 0) {
     tile_counts[tile] = total;
-    atomicAdd(reinterpret_cast<unsigned long long*>(d_unique), (unsigned long long)uniq);
+    tile_uniq[tile] = uniq;
   }
 }
 
@@ -303,7 +343,7 @@ u64 mg_tiles(u64 n) { return (n + kMgTile - 1) / kMgTile; }
 
 u64 unique_diff_workspace_bytes(u64 n) {
   u64 nt = ud_tiles(n);
-  return align_up(nt * sizeof(u32), 256) + 2 * align_up((nt + 1) * sizeof(u64), 256) +
+  return 2 * align_up(nt * sizeof(u32), 256) + 2 * align_up((nt + 1) * sizeof(u64), 256) +
          scan_workspace_bytes(nt);
 }
 
@@ -319,6 +359,8 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   char* p = static_cast<char*>(ws);
   u32* tile_counts = reinterpret_cast<u32*>(p);
   p += align_up(nt * sizeof(u32), 256);
+  u32* tile_uniq = reinterpret_cast<u32*>(p);
+  p += align_up(nt * sizeof(u32), 256);
   u64* tile_off = reinterpret_cast<u64*>(p);
   p += align_up((nt + 1) * sizeof(u64), 256);
   u64* part = reinterpret_cast<u64*>(p);
@@ -330,13 +372,13 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
     ud_partition_kernel<K, true><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, part,
                                                             *model);
     ud_select_kernel<K, true><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
-                                                              tile_counts, d_counts + 1, *model,
+                                                              tile_counts, tile_uniq, *model,
                                                               part);
   } else {
     ud_partition_kernel<K, false><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, part,
                                                              LearnedView<K>{});
     ud_select_kernel<K, false><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
-                                                               tile_counts, d_counts + 1,
+                                                               tile_counts, tile_uniq,
                                                                LearnedView<K>{}, part);
   }
   // by definition: every candidate read once, each kept key written once;
@@ -345,6 +387,10 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = scan_u32_u64(tile_counts, nt, tile_off, d_counts, p, s);
+  if (e != hipSuccess) return e;
+  // the distinct count: a prefix sum whose total is all that is kept (into
+  // part, which the select no longer needs)
+  e = scan_u32_u64(tile_uniq, nt, part, d_counts + 1, p, s);
   if (e != hipSuccess) return e;
   ud_gather_kernel<K><<<dim3(u32(nt)), kUdNT, 0, s>>>(tmp, tile_counts, tile_off, out);
   return hipGetLastError();

@@ -84,7 +84,9 @@ def test_sort_special(eng, kb):
 @pytest.mark.parametrize("kb", [4, 8])
 @pytest.mark.parametrize("n,nf,span", [(0, 10, 100), (1, 0, 10), (5000, 0, 1000),
                                         (20_000, 30_000, 60_000), (100_000, 5_000, 1 << 30),
-                                        (50_000, 2_000_000, 4_000_000), (300_000, 1000, 2000)])
+                                        (50_000, 2_000_000, 4_000_000), (300_000, 1000, 2000),
+                                        (100_000, 1_500_000, 3_000_000),
+                                        (9_000, 600_000, 10_000_000)])
 def test_unique_diff(eng, kb, n, nf, span):
     import torch
     say(f"unique_diff kb={kb} n={n} nf={nf} span={span}")
