@@ -209,6 +209,9 @@ def main():
             stream, {"reach": (programs["reach"], reach_wl["edb"], {"Reach": 2}),
                      "sg": (programs["sg"], sg_wl["edb"], {"SG": 2})},
             args.steps, value, engines, verify=not args.no_verify)}
+    if not args.no_variants:
+        line["variants"]["autotuned"] = autotuned_variant(stream, specs, args.steps, value,
+                                                          engines, verify=not args.no_verify)
     for e in engines.values():
         e.close()
     engines = {}
@@ -315,6 +318,27 @@ def learned_variant(stream, specs, steps, plain_value, plain_engines, verify=Tru
     for e in lengines.values():
         e.close()
     return out
+
+
+def autotuned_variant(stream, specs, steps, plain_value, plain_engines, verify=True):
+    """The same fixpoints after hl_autotune picked each engine's settings
+    (probe method and load factor, EBM growth, in-tile dedup); the tuning
+    runs are outside the timed steps."""
+    log("autotuned variant")
+    engines = {k: make_engine(p, edb, idb, stream, False) for k, (p, edb, idb) in specs.items()}
+    try:
+        chosen = {k: e.autotune(reps=1) for k, e in engines.items()}
+        secs, per, last = timed_runs(engines, steps)
+        tuples = sum(r.idb_tuples for r in last.values())
+        names = [(k, n) for k, (_, _, idb) in specs.items() for n in idb]
+        return {"value": tuples / secs, "ms_per_step": secs * 1e3,
+                "vs_plain": tuples / secs / plain_value,
+                "identical_output": identical(engines, plain_engines, names, verify),
+                "per_workload_ms": {k: v * 1e3 for k, v in per.items()},
+                "settings": chosen}
+    finally:
+        for e in engines.values():
+            e.close()
 
 
 def plain_vs_learned(stream, workload, program, edb, idb, steps, verify, extra=None):

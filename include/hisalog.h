@@ -222,6 +222,31 @@ int hl_program(hl_engine* e, const char* text);
  * called again: IDB relations restart from empty.  stats may be NULL. */
 int hl_run(hl_engine* e, hl_stats* stats);
 
+/* Settings chosen by hl_autotune. */
+typedef struct hl_tuning {
+  float hash_load_factor;  /* load factor of the HISA hash tables */
+  float ebm_k;             /* eager buffer growth factor */
+  uint32_t flags;          /* the chosen HL_FLAG_LEARNED_INDEX and
+                              HL_FLAG_JOIN_DEDUP bits */
+  uint32_t trials;         /* settings timed (failed ones included) */
+  double best_seconds;     /* fixpoint time under the chosen setting */
+  double first_seconds;    /* fixpoint time under the engine's settings
+                              before tuning */
+} hl_tuning;
+
+/* Tunes the engine for the loaded program and data by measurement.  The
+ * settings are searched one dimension at a time, starting from the
+ * engine's own: how join inners are probed (HISA hash at load factor 0.5,
+ * at 0.8, or the learned position index), the eager buffer growth factor
+ * (1.5 or 8) and in-tile dedup of join outputs (off or on).  Each setting
+ * runs the fixpoint once to warm up and then `reps` times (at least 1),
+ * and is scored by its fastest hl_run time; a setting that runs out of
+ * device memory is skipped.  Every setting must give the same per-iteration
+ * delta sizes (HL_E_STATE otherwise: results never depend on these
+ * settings).  The fastest stays in force for later hl_run calls, and a
+ * final run under it leaves the relations computed.  out may be NULL. */
+int hl_autotune(hl_engine* e, uint32_t reps, hl_tuning* out);
+
 /* *n = number of tuples of relation `name` (after hl_run). */
 int hl_count(hl_engine* e, const char* name, uint64_t* n);
 

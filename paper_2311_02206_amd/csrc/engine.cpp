@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <limits>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -1182,6 +1183,96 @@ struct hl_engine {
     collect();
   }
 
+  // ------------------------------------------------------------ autotune
+  struct Setting {
+    float lf, k;
+    u32 fl;  // HL_FLAG_LEARNED_INDEX | HL_FLAG_JOIN_DEDUP bits
+  };
+
+  void apply(const Setting& t) {
+    load_factor = t.lf;
+    ebm_k = t.k;
+    flags = (flags & ~(HL_FLAG_LEARNED_INDEX | HL_FLAG_JOIN_DEDUP)) | t.fl;
+  }
+
+  // Fastest of `reps` timed runs after a warm-up; +inf if the device ran
+  // out of memory.  The per-iteration delta sizes go to *deltas.
+  double trial(const Setting& t, u32 reps, std::vector<std::vector<u64>>* deltas) {
+    apply(t);
+    hl_stats st{};
+    double best = std::numeric_limits<double>::infinity();
+    try {
+      run(&st);
+      for (u32 r = 0; r < reps; ++r) {
+        run(&st);
+        best = std::min(best, st.seconds);
+      }
+    } catch (const Error& x) {
+      if (x.code != HL_E_NOMEM) throw;
+      return std::numeric_limits<double>::infinity();
+    }
+    deltas->clear();
+    for (const Relation& R : rels)
+      if (!R.edb) deltas->push_back(R.delta_counts);
+    return best;
+  }
+
+  void autotune(u32 reps, hl_tuning* out) {
+    if (rules.empty()) fail(HL_E_STATE, "no program");
+    const u32 keep = HL_FLAG_LEARNED_INDEX | HL_FLAG_JOIN_DEDUP;
+    Setting best{load_factor, ebm_k, flags & keep};
+    std::vector<std::vector<u64>> ref, got;
+    u32 trials = 1;
+    double best_t = trial(best, reps, &ref);
+    const double first_t = best_t;
+    bool have_ref = best_t < std::numeric_limits<double>::infinity();
+    auto consider = [&](const Setting& t) {
+      ++trials;
+      const double v = trial(t, reps, &got);
+      if (v == std::numeric_limits<double>::infinity()) return;
+      if (!have_ref) {
+        ref = got;
+        have_ref = true;
+      } else if (got != ref) {
+        fail(HL_E_STATE, "autotune: settings gave different per-iteration deltas");
+      }
+      if (v < best_t) {
+        best_t = v;
+        best = t;
+      }
+    };
+    // 1. how join inners are probed
+    const Setting base = best;
+    for (const Setting& t : {Setting{0.5f, base.k, base.fl & ~u32(HL_FLAG_LEARNED_INDEX)},
+                             Setting{0.8f, base.k, base.fl & ~u32(HL_FLAG_LEARNED_INDEX)},
+                             Setting{base.lf, base.k, base.fl | HL_FLAG_LEARNED_INDEX}})
+      if (t.lf != base.lf || t.fl != base.fl) consider(t);
+    // 2. eager buffer growth factor
+    {
+      Setting t = best;
+      t.k = best.k > 4.0f ? 1.5f : 8.0f;
+      consider(t);
+    }
+    // 3. in-tile dedup of join outputs
+    {
+      Setting t = best;
+      t.fl ^= HL_FLAG_JOIN_DEDUP;
+      consider(t);
+    }
+    if (!have_ref) fail(HL_E_NOMEM, "autotune: every setting ran out of device memory");
+    apply(best);
+    hl_stats st{};
+    run(&st);
+    if (out) {
+      out->hash_load_factor = best.lf;
+      out->ebm_k = best.k;
+      out->flags = best.fl;
+      out->trials = trials;
+      out->best_seconds = best_t;
+      out->first_seconds = first_t;
+    }
+  }
+
   void run(hl_stats* out) {
     if (rules.empty()) fail(HL_E_STATE, "no program");
     auto t0 = std::chrono::steady_clock::now();
@@ -1545,6 +1636,13 @@ int hl_run(hl_engine* e, hl_stats* stats) {
   return guard(e, [&] {
     if (e->device < 0) fail(HL_E_STATE, "planning-only engine (device -1)");
     e->run(stats);
+  });
+}
+
+int hl_autotune(hl_engine* e, uint32_t reps, hl_tuning* out) {
+  return guard(e, [&] {
+    if (e->device < 0) fail(HL_E_STATE, "planning-only engine (device -1)");
+    e->autotune(reps < 1 ? 1 : reps, out);
   });
 }
 

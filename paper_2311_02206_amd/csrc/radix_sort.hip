@@ -143,6 +143,30 @@ __global__ __launch_bounds__(kNT) void col_offsets_kernel(const u32* counts, u32
   }
 }
 
+// All of the above in one block, for at most one chunk of tiles (small
+// sorts, where launches cost more than the work).
+__global__ __launch_bounds__(kNT) void col_single_kernel(const u32* counts, u32 ntiles,
+                                                         u32* offsets) {
+  __shared__ u32 wsum[kWaves];
+  const u32 d = threadIdx.x;
+  u32 s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  u32 t = 0;
+  for (; t + 4 <= ntiles; t += 4) {
+    s0 += counts[u64(t) * kBuckets + d];
+    s1 += counts[u64(t + 1) * kBuckets + d];
+    s2 += counts[u64(t + 2) * kBuckets + d];
+    s3 += counts[u64(t + 3) * kBuckets + d];
+  }
+  for (; t < ntiles; ++t) s0 += counts[u64(t) * kBuckets + d];
+  u32 tot;
+  u32 run = block_exclusive_scan<kNT>(s0 + s1 + s2 + s3, wsum, tot);
+  for (t = 0; t < ntiles; ++t) {
+    const u32 v = counts[u64(t) * kBuckets + d];
+    offsets[u64(t) * kBuckets + d] = run;
+    run += v;
+  }
+}
+
 template <typename K>
 __global__ __launch_bounds__(kNT) void rs_scatter_kernel(const K* in, K* out, u64 n, int shift,
                                                          int dbits, const u32* offsets,
@@ -250,9 +274,13 @@ hipError_t radix_sort_bits(K* keys, K* alt, u64 n, int lo_bit, int hi_bit, void*
     if (timer) timer->end(K_RADIX_HIST, s, n * sizeof(K) + m * sizeof(u32));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    col_reduce_kernel<<<dim3(u32(nc)), kNT, 0, s>>>(counts, u32(nt), csum);
-    col_scan_kernel<<<dim3(kBuckets), kNT, 0, s>>>(csum, u32(nc), total);
-    col_offsets_kernel<<<dim3(u32(nc)), kNT, 0, s>>>(counts, u32(nt), csum, total, offsets);
+    if (nc == 1) {
+      col_single_kernel<<<1, kNT, 0, s>>>(counts, u32(nt), offsets);
+    } else {
+      col_reduce_kernel<<<dim3(u32(nc)), kNT, 0, s>>>(counts, u32(nt), csum);
+      col_scan_kernel<<<dim3(kBuckets), kNT, 0, s>>>(csum, u32(nc), total);
+      col_offsets_kernel<<<dim3(u32(nc)), kNT, 0, s>>>(counts, u32(nt), csum, total, offsets);
+    }
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (timer) timer->begin(K_RADIX_SCATTER, s);

@@ -11,6 +11,7 @@ namespace {
 constexpr int kNT = 256;
 constexpr int kItems = 8;
 constexpr u64 kTile = kNT * kItems;
+constexpr u64 kSingleTiles = 4;  // inputs up to this many tiles scan in one block
 
 template <typename Tin>
 __global__ __launch_bounds__(kNT) void scan_reduce_kernel(const Tin* in, u64 n, u64* sums) {
@@ -26,21 +27,23 @@ __global__ __launch_bounds__(kNT) void scan_reduce_kernel(const Tin* in, u64 n, 
   if (threadIdx.x == 0) sums[blockIdx.x] = s;
 }
 
-// offsets == nullptr: a single tile starting at 0.
+// offsets == nullptr: one block scans `tiles` tiles in turn, from 0.
 template <typename Tin>
 __global__ __launch_bounds__(kNT) void scan_down_kernel(const Tin* in, u64 n, const u64* offsets,
-                                                        u64* out, u64* d_total) {
+                                                        u64* out, u64* d_total, u32 tiles = 1) {
   __shared__ u64 lds[kNT / kWave];
-  const u64 base = u64(blockIdx.x) * kTile;
   u64 carry = offsets ? offsets[blockIdx.x] : 0;
+  for (u32 q = 0; q < tiles; ++q) {
+    const u64 base = (u64(blockIdx.x) + q) * kTile;
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    u64 i = base + u64(j) * kNT + threadIdx.x;
-    u64 v = i < n ? u64(in[i]) : 0;
-    u64 tot;
-    u64 ex = block_exclusive_scan<kNT>(v, lds, tot);
-    if (i < n) out[i] = carry + ex;
-    carry += tot;
+    for (int j = 0; j < kItems; ++j) {
+      u64 i = base + u64(j) * kNT + threadIdx.x;
+      u64 v = i < n ? u64(in[i]) : 0;
+      u64 tot;
+      u64 ex = block_exclusive_scan<kNT>(v, lds, tot);
+      if (i < n) out[i] = carry + ex;
+      carry += tot;
+    }
   }
   if (d_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *d_total = carry;
 }
@@ -56,8 +59,9 @@ hipError_t scan_impl(const Tin* in, u64 n, u64* out, u64* d_total, char* ws, hip
     return hipGetLastError();
   }
   u64 nt = tiles_of(n);
-  if (nt == 1) {
-    scan_down_kernel<Tin><<<1, kNT, 0, s>>>(in, n, nullptr, out, d_total);
+  if (nt <= kSingleTiles) {
+    // small: one block, tile after tile (fewer launches than reduce + scan)
+    scan_down_kernel<Tin><<<1, kNT, 0, s>>>(in, n, nullptr, out, d_total, u32(nt));
     return hipGetLastError();
   }
   if (nt > 0x7fffffffULL) return hipErrorInvalidValue;

@@ -35,7 +35,8 @@ PHASES = ("index_edb", "join", "sort", "diff", "merge", "index")
 # Symbols of include/hisalog.h, in declaration order.
 EXPORTS = (
     "hl_options_init", "hl_create", "hl_destroy", "hl_declare", "hl_load", "hl_load_device",
-    "hl_batch_layout", "hl_load_batched", "hl_batch_count", "hl_fetch_batched", "hl_index", "hl_program", "hl_run", "hl_count", "hl_fetch", "hl_fetch_device",
+    "hl_batch_layout", "hl_load_batched", "hl_batch_count", "hl_fetch_batched", "hl_index",
+    "hl_program", "hl_run", "hl_autotune", "hl_count", "hl_fetch", "hl_fetch_device",
     "hl_iteration_counts", "hl_kernel_stats", "hl_last_error", "hl_strerror", "hl_sort_keys",
     "hl_unique_diff", "hl_merge", "hl_hisa_query", "hl_learned_query",
 )
@@ -74,6 +75,14 @@ class Stats(ctypes.Structure):
         return d
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("hash_load_factor", ctypes.c_float), ("ebm_k", ctypes.c_float),
+        ("flags", ctypes.c_uint32), ("trials", ctypes.c_uint32),
+        ("best_seconds", ctypes.c_double), ("first_seconds", ctypes.c_double),
+    ]
+
+
 _lib = None
 
 
@@ -103,6 +112,7 @@ def lib() -> ctypes.CDLL:
         "hl_fetch_batched": [vp, cp, u32, vp, u64, pu64],
         "hl_program": [vp, cp],
         "hl_run": [vp, ctypes.POINTER(Stats)],
+        "hl_autotune": [vp, u32, ctypes.POINTER(Tuning)],
         "hl_count": [vp, cp, pu64],
         "hl_fetch": [vp, cp, vp, u64, pu64],
         "hl_fetch_device": [vp, cp, vp, u64, pu64],
@@ -277,6 +287,17 @@ class Engine:
         self._check(self._L.hl_run(self._h, ctypes.byref(st)), "hl_run")
         d = st.as_dict()
         return RunStats(**d)
+
+    def autotune(self, reps: int = 1) -> dict:
+        """Measures the fixpoint under alternative settings (probe method and
+        hash load factor, eager buffer growth, in-tile join dedup), keeps the
+        fastest (see hl_autotune) and returns the choice."""
+        t = Tuning()
+        self._check(self._L.hl_autotune(self._h, reps, ctypes.byref(t)), "hl_autotune")
+        return {"hash_load_factor": round(t.hash_load_factor, 3), "ebm_k": round(t.ebm_k, 3),
+                "learned": bool(t.flags & HL_FLAG_LEARNED_INDEX),
+                "join_dedup": bool(t.flags & HL_FLAG_JOIN_DEDUP), "trials": t.trials,
+                "best_seconds": t.best_seconds, "first_seconds": t.first_seconds}
 
     def count(self, name: str) -> int:
         n = ctypes.c_uint64()

@@ -235,6 +235,40 @@ def test_join_dedup_matches_plain(case):
         assert st.candidates < st0.candidates  # duplicates were dropped
 
 
+@pytest.mark.parametrize("case", ["reach_rmat", "sg_tree", "cspa"])
+def test_autotune_keeps_results(case):
+    """The autotuner times alternative settings; whichever it keeps, the
+    relations it leaves and every later run equal the oracle's."""
+    import torch
+    import paper_2311_02206_amd as pkg
+    say(f"autotune: {case}")
+    if case == "reach_rmat":
+        prog, edb, idb = PROG["reach"], workloads.scaled_rmat(11, 6000, seed=4)["edb"], {"Reach": 2}
+    elif case == "sg_tree":
+        prog, edb, idb = PROG["sg"], workloads.scaled_tree(3000, seed=3)["edb"], {"SG": 2}
+    else:
+        prog, edb = PROG["cspa_shaped"], workloads.cspa(10)["edb"]
+        idb = {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2}
+    want = oracle.evaluate(prog, edb, idb)
+    with pkg.Engine(device=0, stream=torch.cuda.current_stream()) as e:
+        for n in edb:
+            e.declare(n, 2, True)
+        for n in idb:
+            e.declare(n, 2, False)
+        for n, rows in edb.items():
+            e.load(n, rows)
+        e.program(prog)
+        t = e.autotune(reps=1)
+        say(f"  chose {t}")
+        assert t["trials"] >= 4 and t["best_seconds"] <= t["first_seconds"]
+        assert t["hash_load_factor"] in (0.5, 0.8) and t["ebm_k"] in (1.5, 8.0)
+        for _ in range(2):
+            for n in idb:
+                assert np.array_equal(e.fetch(n), want.relations[n]), n
+                assert e.iteration_counts(n, 0) == want.deltas[n], n
+            e.run()
+
+
 @pytest.mark.parametrize("learned", [False, True])
 def test_cspa_literal_2p11(learned):
     """The CSPA-shaped program on the literal Zipf reading at 2^11 ids (781

@@ -59,6 +59,7 @@ def test_error_codes():
         assert code_of(lambda: e.program("R(x, y) :- E(x, y), E(y, x).")) == H.HL_OK
         assert code_of(lambda: e.load("E", [[1, 2]])) == H.HL_E_STATE
         assert code_of(lambda: e.run()) == H.HL_E_STATE
+        assert code_of(lambda: e.autotune()) == H.HL_E_STATE
     e = pkg.Engine(device=-1)
     assert code_of(lambda: e.declare("T", 3, False)) == H.HL_E_UNSUPPORTED
     assert code_of(lambda: e.declare("bad name", 2, False)) == H.HL_E_INVALID
