@@ -15,10 +15,11 @@ to the summed deltas); bit-exact parity of these same runs against exact
 references (per-source BFS, the closed form of SG on a tree, naive matrix
 evaluation of the CSPA-shaped program) is in tests/test_gpu_full.py.
 
-Variants on the same line: the learned position index on the same
-workload; plain vs learned on the CSPA-shaped program (2^14 ids) and on
-Reach over a 2^22-node subcritical ER graph; 4,096 batched Reach instances
-against one-at-a-time runs.
+Variants on the same line: the learned position index and the autotuned
+settings on the same workload; plain vs learned on the CSPA-shaped program
+(2^14 ids) and on Reach over a 2^22-node subcritical ER graph; eager
+buffer management off vs on; sort and merge of random arity-2 tuples at
+1e6..5e8; 4,096 batched Reach instances against one-at-a-time runs.
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
 build runs on one GPU.
@@ -224,6 +225,13 @@ def main():
                                             verify=not args.no_verify)
             except Exception as exc:  # keep the main line whatever happens here
                 line["variants"][name] = {"error": repr(exc)}
+    if not args.no_variants:
+        for name, fn in (("ebm_ablation", lambda: ebm_ablation(stream, max(1, min(args.steps, 3)))),
+                         ("table6_microbench", lambda: table6_microbench(stream))):
+            try:
+                line["variants"][name] = fn()
+            except Exception as exc:  # keep the main line whatever happens here
+                line["variants"][name] = {"error": repr(exc)}
     if args.batched_instances > 0:
         try:
             line.setdefault("variants", {})["batched"] = batched_variant(
@@ -318,6 +326,94 @@ def learned_variant(stream, specs, steps, plain_value, plain_engines, verify=Tru
     for e in lengines.values():
         e.close()
     return out
+
+
+def ebm_ablation(stream, steps):
+    """Reach with eager buffer management off (exact-size buffers, every
+    growth a new allocation and every release a hipFree: the paper's
+    "Normal" column of its EBM table) and on, on the 2^22-node ER graph (142
+    iterations, long tail) and on R-MAT 2^16."""
+    import workloads
+    from paper_2311_02206_amd import Engine
+    log("ebm ablation")
+    prog = open(os.path.join(ROOT, "workloads", "programs", "reach.dl")).read()
+    out = {}
+    for name, wl in (("reach_er_2p22", workloads.reach_er_2p22()),
+                     ("reach_rmat16", workloads.reach_rmat16())):
+        row = {}
+        for form, ebm in (("normal", False), ("eager", True)):
+            e = Engine(device=0, stream=stream, ebm=ebm)
+            try:
+                e.declare("Edge", 2, True)
+                e.declare("Reach", 2, False)
+                e.load("Edge", wl["edb"]["Edge"])
+                e.program(prog)
+                secs, _, last = timed_runs({"x": e}, steps)
+                r = last["x"]
+                row[form] = {"ms_per_fixpoint": secs * 1e3, "allocations": r.allocations,
+                             "peak_bytes": r.peak_bytes, "tuples": r.idb_tuples,
+                             "iterations": r.iterations}
+            finally:
+                e.close()
+        row["eager_speedup"] = row["normal"]["ms_per_fixpoint"] / row["eager"]["ms_per_fixpoint"]
+        out[name] = row
+    return out
+
+
+def table6_microbench(stream, reps=10):
+    """Sort and merge of random arity-2 tuples (two uniform uint32 columns,
+    packed into 64-bit keys, all 64 bits sorted), at the tuple counts of the
+    paper's CPU/GPU comparison table.  Merge: two sorted halves of N/2
+    tuples each into one array of N.  Times are per run (HIP events around
+    the call on the engine's stream) and, for comparison with the table's
+    totals, times 100."""
+    import torch
+    from paper_2311_02206_amd import Engine
+    log("table-6 microbenchmark")
+    e = Engine(device=0, stream=stream)
+    g = torch.Generator(device="cuda").manual_seed(6)
+    rows = []
+    try:
+        for n in (1_000_000, 10_000_000, 50_000_000, 100_000_000, 500_000_000):
+            src = torch.randint(-(1 << 63), (1 << 63) - 1, (n,), dtype=torch.int64,
+                                device="cuda", generator=g)
+            work = torch.empty_like(src)
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            st = []
+            for r in range(reps + 1):
+                work.copy_(src)
+                ev0.record(stream)
+                e.sort_keys(work, 64)
+                ev1.record(stream)
+                ev1.synchronize()
+                if r:
+                    st.append(ev0.elapsed_time(ev1))
+            half = n // 2
+            a = work[:half].clone()
+            b = src[half:2 * half].clone()
+            e.sort_keys(b, 64)
+            mt = []
+            for r in range(reps + 1):
+                ev0.record(stream)
+                m = e.merge(a, b)
+                ev1.record(stream)
+                ev1.synchronize()
+                if r:
+                    mt.append(ev0.elapsed_time(ev1))
+                del m
+            srt, mrg = sum(st) / len(st), sum(mt) / len(mt)
+            rows.append({"tuples": n, "sort_ms": round(srt, 3), "merge_ms": round(mrg, 3),
+                         "sort_s_per_100": round(srt / 10, 3), "merge_s_per_100": round(mrg / 10, 3),
+                         "sort_GBps": round(3 * 8 * 8 * n / (srt / 1e3) / 1e9, 1),
+                         "merge_GBps": round(2 * 8 * 2 * half / (mrg / 1e3) / 1e9, 1)})
+            log(f"  {n}: sort {srt:.2f} ms, merge {mrg:.2f} ms")
+            del src, work, a, b
+            torch.cuda.empty_cache()
+    finally:
+        e.close()
+    return {"reps": reps, "key_bits": 64, "rows": rows,
+            "note": "sort_GBps counts 8 radix passes of 24 B per key (hist read, scatter read "
+                    "and write); merge_GBps counts one read and one write per key"}
 
 
 def autotuned_variant(stream, specs, steps, plain_value, plain_engines, verify=True):
