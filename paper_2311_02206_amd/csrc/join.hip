@@ -208,9 +208,15 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
                                                      const u32* start, const K* inner,
                                                      u64 total, JoinSpec js, const u64* parts,
                                                      K* out, u64* cursor) {
-  __shared__ u64 s_off[kTile];
+  // Offsets of the tile's outer tuples relative to its first output b0: the
+  // merge path puts every one of them in [b0, b1], so 32 bits hold them.
+  // s_pool holds them and the run starts; after the block scan below (once
+  // both are no longer read) it holds the surviving outputs instead.
+  __shared__ u32 s_pool[2 * kTile];
+  static_assert(sizeof(K) * kTile <= sizeof(u32) * 2 * kTile, "survivors fit the pool");
+  u32* s_off = s_pool;
+  u32* s_start = s_pool + kTile;
   __shared__ u32 s_owner[kTile];
-  __shared__ u32 s_start[kTile];
   __shared__ K s_outer[kTile];
   const u32 tile = blockIdx.x;
   const u64 d0 = u64(tile) * kTile;
@@ -220,7 +226,7 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   const u64 b0 = d0 - a0, b1 = d1 - a1;
   const u32 la = u32(a1 - a0), lb = u32(b1 - b0);
   for (u32 k = threadIdx.x; k < la; k += kNT) {
-    s_off[k] = off[a0 + k];
+    s_off[k] = u32(off[a0 + k] - b0);
     s_start[k] = start[a0 + k];
     s_outer[k] = outer[a0 + k];
   }
@@ -234,12 +240,12 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
     u32 hi = diag < la ? diag : la;
     while (lo < hi) {
       u32 mid = (lo + hi) >> 1;
-      if (s_off[mid] <= b0 + (diag - 1 - mid)) lo = mid + 1;
+      if (s_off[mid] <= diag - 1 - mid) lo = mid + 1;
       else hi = mid;
     }
     u32 ai = lo, bi = diag - lo;
     for (int k = 0; k < kItems && diag + k < tot; ++k) {
-      if (ai < la && (bi >= lb || s_off[ai] <= b0 + bi)) {
+      if (ai < la && (bi >= lb || s_off[ai] <= bi)) {
         ++ai;
       } else {
         s_owner[bi] = u32(a0 + ai - 1);  // global index of the owning outer tuple
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   __syncthreads();
   const bool filtered = js.fa >= 0 || js.ea >= 0 || js.dd;
   const K mask = (K(1) << js.w) - 1;
-  __shared__ K s_keep[kTile];
+  K* s_keep = reinterpret_cast<K*>(s_pool);
   __shared__ u32 s_wsum[kNT / kWave];
   __shared__ u64 s_base;
   // the dedup set lives in dynamic LDS, sized at launch only when js.dd
@@ -272,8 +278,8 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
       const u32 i = s_owner[k];
       // the owner is in this tile's slice, or the run carried in from before
       const bool here = u64(i) >= a0;
-      const u64 oi = here ? s_off[u64(i) - a0] : off[i];
-      const u64 pos = u64(here ? s_start[u64(i) - a0] : start[i]) + (b0 + k - oi);
+      const u64 pos = here ? u64(s_start[u64(i) - a0]) + (k - s_off[u64(i) - a0])
+                           : u64(start[i]) + (b0 + k - off[i]);
       const K ok = here ? s_outer[u64(i) - a0] : outer[i];
       const K c0 = ok >> js.w, c1 = ok & mask;
       const K o = inner[pos] & mask;

@@ -25,9 +25,9 @@ namespace {
 constexpr int kUdNT = 256;
 constexpr int kUdItems = 16;
 constexpr u64 kUdTile = u64(kUdNT) * kUdItems;
-constexpr u64 kUdStage = 4096;  // keys of full staged in LDS per tile
+constexpr u64 kUdStage = 2048;  // keys of full staged in LDS per chunk
 constexpr int kUdLock = 8;      // keys searched in lockstep by one thread
-constexpr u64 kUdStreamMax = 8 * kUdStage;  // longest slice streamed through LDS
+constexpr u64 kUdStreamMax = 16 * kUdStage;  // longest slice streamed through LDS
 
 __device__ __forceinline__ u32 pad(u32 i) { return i + i / kUdItems; }
 
