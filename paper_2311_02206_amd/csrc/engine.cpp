@@ -340,6 +340,11 @@ struct Relation {
   // outputs before filters and dedup)
   bool dedup = true;
   u64 raw_cand = 0;
+  // new tuples already sorted, deduplicated and subtracted from full this
+  // iteration (chunked joins, oversized candidate sets); pend_uniq sums the
+  // distinct tuples of each absorbed chunk
+  Buf pend[2];
+  u64 n_pend = 0, pend_uniq = 0;
 };
 
 // --------------------------------------------------------------- the parser
@@ -421,7 +426,7 @@ struct hl_engine {
   // run state
   int w = 1;
   int key_bytes = 4;
-  Buf alt, tmp[2], ws, join_start, join_len, join_off, join_parts, rows, pend[2], grp[2];
+  Buf alt, tmp[2], ws, join_start, join_len, join_off, join_parts, rows, grp[2], jchunk;
   u64* d_small = nullptr;  // device scalars
   u64* h_small = nullptr;  // pinned mirror
   static constexpr int kSmall = 512;
@@ -984,6 +989,50 @@ struct hl_engine {
         H.raw_cand += total;
         st.join_outputs += total;
       }
+      const u64 cap = u64(1) << sort_chunk_log2;
+      if (last && total > cap) {
+        // One join's outputs exceed one sort: expand a range of tiles at a
+        // time (at most `cap` outputs) and absorb each range into the head
+        // relation's pending delta, so memory stays bounded by the range.
+        const u64 nt = hl::join_tiles(n, total);
+        reserve_grow(join_parts, hl::join_parts(n, total) * sizeof(u64));
+        u64* parts = static_cast<u64*>(join_parts.p);
+        HIPCK(hl::join_partition(static_cast<u64*>(join_off.p), n, total, parts, stream));
+        const u64 tile_out = hl::join_tile_outputs();
+        const u64 per = std::max<u64>(1, cap / tile_out);
+        reserve_grow(jchunk, per * tile_out * sizeof(K));
+        const bool filt = js.fa >= 0 || js.ea >= 0 || js.dd;
+        for (u64 t0 = 0; t0 < nt; t0 += per) {
+          const u64 tiles = std::min(per, nt - t0);
+          if (filt) {
+            h_small[0] = 0;
+            HIPCK(hipMemcpyAsync(d_cursor, h_small, sizeof(u64), hipMemcpyHostToDevice, stream));
+          }
+          HIPCK(hl::join_expand_tiles<K>(cur, n, static_cast<u64*>(join_off.p),
+                                         static_cast<u32*>(join_start.p), inner, total, js, parts,
+                                         t0, tiles, kp<K>(jchunk), d_cursor, stream, kt()));
+          u64 m;
+          if (filt) {
+            HIPCK(hipMemcpyAsync(h_small, d_cursor, sizeof(u64), hipMemcpyDeviceToHost, stream));
+            sync();
+            m = h_small[0];
+          } else {
+            // outputs of tiles [t0, t1): j(t1) - j(t0), j(t) = min(t * tile, n + total) - parts[t]
+            const u64 t1 = t0 + tiles;
+            HIPCK(hipMemcpyAsync(h_small + 2, parts + t0, sizeof(u64), hipMemcpyDeviceToHost,
+                                 stream));
+            HIPCK(hipMemcpyAsync(h_small + 3, parts + t1, sizeof(u64), hipMemcpyDeviceToHost,
+                                 stream));
+            sync();
+            const u64 j0 = std::min(t0 * tile_out, n + total) - h_small[2];
+            const u64 j1 = std::min(t1 * tile_out, n + total) - h_small[3];
+            m = j1 - j0;
+          }
+          st.candidates += m;
+          absorb<K>(H, kp<K>(jchunk), m);
+        }
+        return;
+      }
       const bool filtered = js.fa >= 0 || js.ea >= 0 || js.dd;
       K* out;
       u64 base = 0;
@@ -1022,49 +1071,73 @@ struct hl_engine {
     }
   }
 
-  // Delta of a relation whose new tuples exceed one sort (2^31 keys): each
-  // chunk is sorted, cut down to its distinct tuples that are neither in
-  // full nor in the delta of the earlier chunks, and merged into that delta
-  // (the pieces are disjoint, so the merge needs no dedup).  Returns
-  // (|delta|, sum over chunks of their distinct tuples).
+  // Model of R's full relation for the set difference, if it has a current one.
   template <typename K>
-  std::pair<u64, u64> chunked_delta(Relation& R, const hl::LearnedView<K>* model) {
-    const u64 kChunk = u64(1) << sort_chunk_log2;
+  bool diff_model(Relation& R, hl::LearnedView<K>* mv) {
+    const bool use = learned() && R.n_full > 0 && R.idx[0].lm_ok &&
+                     R.idx[0].lm_keys == R.full.p && R.idx[0].lm_n == R.n_full;
+    if (use) *mv = R.idx[0].view<K>();
+    return use;
+  }
+
+  // Absorbs m new tuples (unsorted, at `keys`, which is overwritten) into
+  // R's pending delta: they are sorted, cut down to the distinct ones that
+  // are neither in full nor already pending, and merged in (the pieces are
+  // disjoint, so the merge needs no dedup).  One synchronisation.
+  template <typename K>
+  void absorb(Relation& R, K* keys, u64 m) {
+    if (m == 0) return;
     const int bits = 2 * w;
-    u64 p = 0, uniq = 0;
-    for (u64 c = 0; c < R.n_cand; c += kChunk) {
-      const u64 m = std::min(kChunk, R.n_cand - c);
-      K* chunk = kp<K>(R.cand) + c;
-      reserve_grow(alt, m * sizeof(K));
-      reserve(ws, hl::sort_workspace_bytes(m), hl::sort_workspace_bytes(m) * 2);
-      K* sorted = nullptr;
-      HIPCK(hl::radix_sort<K>(chunk, kp<K>(alt), m, bits, ws.p, stream, &sorted, kt(), d_err()));
-      K* other = sorted == chunk ? kp<K>(alt) : chunk;
-      reserve(ws, hl::unique_diff_workspace_bytes(m), hl::unique_diff_workspace_bytes(m) * 2);
-      u64* dc = d_small + kChunkSlots;  // scratch counts (not the per-relation slots)
-      u64* hc = h_small + kChunkSlots;
-      HIPCK(hl::unique_diff<K>(sorted, m, kp<K>(R.full), R.n_full, other, sorted, dc, ws.p,
-                               stream, kt(), model));
-      HIPCK(hipMemcpyAsync(hc, dc, 2 * sizeof(u64), hipMemcpyDeviceToHost, stream));
+    reserve_grow(alt, m * sizeof(K));
+    reserve(ws, hl::sort_workspace_bytes(m), hl::sort_workspace_bytes(m) * 2);
+    K* sorted = nullptr;
+    HIPCK(hl::radix_sort<K>(keys, kp<K>(alt), m, bits, ws.p, stream, &sorted, kt(), d_err()));
+    K* other = sorted == keys ? kp<K>(alt) : keys;
+    reserve(ws, hl::unique_diff_workspace_bytes(m), hl::unique_diff_workspace_bytes(m) * 2);
+    u64* dc = d_small + kChunkSlots;  // scratch counts (not the per-relation slots)
+    u64* hc = h_small + kChunkSlots;
+    hl::LearnedView<K> mv{};
+    const bool use_model = diff_model<K>(R, &mv);
+    HIPCK(hl::unique_diff<K>(sorted, m, kp<K>(R.full), R.n_full, other, sorted, dc, ws.p, stream,
+                             kt(), use_model ? &mv : nullptr));
+    HIPCK(hipMemcpyAsync(hc, dc, 2 * sizeof(u64), hipMemcpyDeviceToHost, stream));
+    sync();
+    u64 d = hc[0];
+    R.pend_uniq += hc[1];
+    const u64 p = R.n_pend;
+    if (p > 0 && d > 0) {
+      HIPCK(hl::unique_diff<K>(sorted, d, kp<K>(R.pend[0]), p, other, sorted, dc, ws.p, stream,
+                               kt()));
+      HIPCK(hipMemcpyAsync(hc, dc, sizeof(u64), hipMemcpyDeviceToHost, stream));
       sync();
-      u64 d = hc[0];
-      uniq += hc[1];
-      if (p > 0 && d > 0) {
-        HIPCK(hl::unique_diff<K>(sorted, d, kp<K>(pend[0]), p, other, sorted, dc, ws.p,
-                                 stream, kt()));
-        HIPCK(hipMemcpyAsync(hc, dc, sizeof(u64), hipMemcpyDeviceToHost, stream));
-        sync();
-        d = hc[0];
-      }
-      if (d == 0) continue;
-      reserve(pend[1], (p + d) * sizeof(K), (p + d) * sizeof(K) * 2);
-      reserve(ws, hl::merge_workspace_bytes(p, d), hl::merge_workspace_bytes(p, d) * 2);
-      HIPCK(hl::merge<K>(kp<K>(pend[0]), p, sorted, d, kp<K>(pend[1]), ws.p, stream, kt()));
-      std::swap(pend[0], pend[1]);
-      p += d;
+      d = hc[0];
     }
-    std::swap(R.delta, pend[0]);
-    return {p, uniq};
+    if (d == 0) return;
+    if (p == 0) {
+      reserve(R.pend[0], d * sizeof(K), d * sizeof(K) * 2);
+      HIPCK(hipMemcpyAsync(R.pend[0].p, sorted, d * sizeof(K), hipMemcpyDeviceToDevice, stream));
+    } else {
+      reserve(R.pend[1], (p + d) * sizeof(K), (p + d) * sizeof(K) * 2);
+      reserve(ws, hl::merge_workspace_bytes(p, d), hl::merge_workspace_bytes(p, d) * 2);
+      HIPCK(hl::merge<K>(kp<K>(R.pend[0]), p, sorted, d, kp<K>(R.pend[1]), ws.p, stream, kt()));
+      std::swap(R.pend[0], R.pend[1]);
+    }
+    R.n_pend = p + d;
+  }
+
+  // Delta of a relation that has pending tuples or whose new tuples exceed
+  // one sort (2^sort_chunk_log2 keys): the candidates are absorbed chunk by
+  // chunk and the pending set becomes delta.  Returns (|delta|, sum over
+  // chunks of their distinct tuples).
+  template <typename K>
+  std::pair<u64, u64> chunked_delta(Relation& R) {
+    const u64 kChunk = u64(1) << sort_chunk_log2;
+    for (u64 c = 0; c < R.n_cand; c += kChunk)
+      absorb<K>(R, kp<K>(R.cand) + c, std::min(kChunk, R.n_cand - c));
+    std::swap(R.delta, R.pend[0]);
+    const std::pair<u64, u64> r{R.n_pend, R.pend_uniq};
+    R.n_pend = R.pend_uniq = 0;
+    return r;
   }
 
   // Sort + unique + subtraction of full for every IDB relation, then the
@@ -1082,16 +1155,12 @@ struct hl_engine {
     for (size_t q = 0; q < idbs.size(); ++q) {
       Relation& R = rels[idbs[q]];
       R.n_delta = 0;
-      if (R.n_cand == 0) {
+      if (R.n_cand == 0 && R.n_pend == 0) {
         HIPCK(hl::fill_zero(d_small + 2 * q, 2 * sizeof(u64), stream));
         continue;
       }
-      if (R.n_cand > (u64(1) << sort_chunk_log2)) {
-        hl::LearnedView<K> mv{};
-        const bool use_model = learned() && R.n_full > 0 && R.idx[0].lm_ok &&
-                               R.idx[0].lm_keys == R.full.p && R.idx[0].lm_n == R.n_full;
-        if (use_model) mv = R.idx[0].view<K>();
-        chunked.push_back({q, chunked_delta<K>(R, use_model ? &mv : nullptr)});
+      if (R.n_pend > 0 || R.n_cand > (u64(1) << sort_chunk_log2)) {
+        chunked.push_back({q, chunked_delta<K>(R)});
         HIPCK(hl::fill_zero(d_small + 2 * q, 2 * sizeof(u64), stream));
         continue;
       }

@@ -207,7 +207,7 @@ template <typename K>
 __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer, const u64* off,
                                                      const u32* start, const K* inner,
                                                      u64 total, JoinSpec js, const u64* parts,
-                                                     K* out, u64* cursor) {
+                                                     u64 tile0, K* out, u64* cursor) {
   // Offsets of the tile's outer tuples relative to its first output b0: the
   // merge path puts every one of them in [b0, b1], so 32 bits hold them.
   // s_pool holds them and the run starts; after the block scan below (once
@@ -218,8 +218,11 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   u32* s_start = s_pool + kTile;
   __shared__ u32 s_owner[kTile];
   __shared__ K s_outer[kTile];
-  const u32 tile = blockIdx.x;
-  const u64 d0 = u64(tile) * kTile;
+  // tiles tile0 .. tile0 + gridDim.x - 1; unfiltered outputs are written
+  // relative to the first output of tile0
+  const u64 tile = tile0 + blockIdx.x;
+  const u64 obase = tile0 * kTile - parts[tile0];
+  const u64 d0 = tile * kTile;
   const u64 dend = n_outer + total;
   const u64 d1 = (d0 + kTile) < dend ? (d0 + kTile) : dend;
   const u64 a0 = parts[tile], a1 = parts[tile + 1];
@@ -294,7 +297,7 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const u32 k = u32(r) * kNT + threadIdx.x;
-      if (k < lb) out[b0 + k] = v[r];
+      if (k < lb) out[b0 + k - obase] = v[r];
     }
     return;
   }
@@ -387,10 +390,7 @@ hipError_t join_probe_learned(const K* outer, u64 n, const JoinSpec& js,
 
 u64 join_parts(u64 n_outer, u64 total) { return tiles_of(n_outer + total) + 1; }
 
-template <typename K>
-hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* start,
-                       const K* inner, u64 total, const JoinSpec& js, u64* parts, K* out,
-                       u64* cursor, hipStream_t s, LaunchTimer* timer) {
+hipError_t join_partition(const u64* off, u64 n_outer, u64 total, u64* parts, hipStream_t s) {
   if (total == 0) return hipSuccess;
   if (n_outer >= (u64(1) << 32)) return hipErrorInvalidValue;
   const u64 nt = tiles_of(n_outer + total);
@@ -398,17 +398,46 @@ hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* s
   const u64 nparts = nt + 1;
   lbs_partition_kernel<<<dim3(u32((nparts + 255) / 256)), 256, 0, s>>>(off, n_outer, total,
                                                                        parts, nparts);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+u64 join_tiles(u64 n_outer, u64 total) { return tiles_of(n_outer + total); }
+
+u64 join_tile_outputs() { return kTile; }
+
+template <typename K>
+hipError_t join_expand_tiles(const K* outer, u64 n_outer, const u64* off, const u32* start,
+                             const K* inner, u64 total, const JoinSpec& js, const u64* parts,
+                             u64 tile0, u64 tiles, K* out, u64* cursor, hipStream_t s,
+                             LaunchTimer* timer) {
+  if (total == 0 || tiles == 0) return hipSuccess;
+  const u64 nt = tiles_of(n_outer + total);
+  if (n_outer >= (u64(1) << 32) || tile0 + tiles > nt || tiles >= (u64(1) << 31))
+    return hipErrorInvalidValue;
   if (timer) timer->begin(K_JOIN_EXPAND, s);
   const size_t dyn = js.dd ? kDedupSlots * sizeof(K) : 0;
-  expand_kernel<K><<<dim3(u32(nt)), kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, js,
-                                                   parts, out, cursor);
+  expand_kernel<K><<<dim3(u32(tiles)), kNT, dyn, s>>>(outer, n_outer, off, start, inner, total,
+                                                      js, parts, tile0, out, cursor);
   // by definition: each inner tuple of a matched run read once, each output
   // written once, each outer tuple with its offset and run start read once
-  if (timer) timer->end(K_JOIN_EXPAND, s,
-                        2 * total * sizeof(K) + n_outer * (sizeof(K) + sizeof(u64) + sizeof(u32)));
+  // (apportioned to the launch's share of the tiles)
+  if (timer) {
+    const double f = double(tiles) / double(nt);
+    timer->end(K_JOIN_EXPAND, s,
+               u64(f * double(2 * total * sizeof(K) +
+                              n_outer * (sizeof(K) + sizeof(u64) + sizeof(u32)))));
+  }
   return hipGetLastError();
+}
+
+template <typename K>
+hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* start,
+                       const K* inner, u64 total, const JoinSpec& js, u64* parts, K* out,
+                       u64* cursor, hipStream_t s, LaunchTimer* timer) {
+  hipError_t e = join_partition(off, n_outer, total, parts, s);
+  if (e != hipSuccess || total == 0) return e;
+  return join_expand_tiles<K>(outer, n_outer, off, start, inner, total, js, parts, 0,
+                              tiles_of(n_outer + total), out, cursor, s, timer);
 }
 
 template <typename K>
@@ -423,6 +452,9 @@ hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, 
 #define HL_INSTANTIATE(K)                                                                     \
   template hipError_t join_probe<K>(const K*, u64, const JoinSpec&, const Slot*, u64, u32*,  \
                                     u32*, hipStream_t, LaunchTimer*);                         \
+  template hipError_t join_expand_tiles<K>(const K*, u64, const u64*, const u32*, const K*,  \
+                                           u64, const JoinSpec&, const u64*, u64, u64, K*,   \
+                                           u64*, hipStream_t, LaunchTimer*);                 \
   template hipError_t join_expand<K>(const K*, u64, const u64*, const u32*, const K*, u64,  \
                                      const JoinSpec&, u64*, K*, u64*, hipStream_t,            \
                                      LaunchTimer*);                                           \

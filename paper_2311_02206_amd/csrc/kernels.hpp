@@ -158,6 +158,18 @@ hipError_t join_probe_learned(const K* outer, u64 n, const JoinSpec& js,
                               const LearnedView<K>& lv, u32* start, u32* len, hipStream_t s,
                               LaunchTimer* timer = nullptr);
 u64 join_parts(u64 n_outer, u64 total);  // entries of the partition array
+u64 join_tiles(u64 n_outer, u64 total);  // expand tiles (join_parts - 1)
+u64 join_tile_outputs();                 // most outputs one expand tile emits
+// Merge-path partition of the expand's tiles (parts: join_parts entries).
+hipError_t join_partition(const u64* off, u64 n_outer, u64 total, u64* parts, hipStream_t s);
+// Expands tiles tile0 .. tile0 + tiles - 1 only (parts from join_partition).
+// Unfiltered outputs go to out[j - j0], j0 the first output index of tile0;
+// filtered ones (or with js.dd) are appended at *cursor.
+template <typename K>
+hipError_t join_expand_tiles(const K* outer, u64 n_outer, const u64* off, const u32* start,
+                             const K* inner, u64 total, const JoinSpec& js, const u64* parts,
+                             u64 tile0, u64 tiles, K* out, u64* cursor, hipStream_t s,
+                             LaunchTimer* timer = nullptr);
 // Expands every (outer, inner run) pair.  Without a filter, output j goes
 // to out[j]; with one, survivors are appended at *cursor (device, u64).
 // With js.dd, an output equal to an earlier output of the same tile (2,048

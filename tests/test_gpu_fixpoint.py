@@ -310,7 +310,10 @@ def test_learned_index_matches_plain(case):
 @pytest.mark.parametrize("learned", [False, True])
 def test_chunked_new_tuples(learned):
     """An iteration's new tuples beyond one sort chunk (forced here to 4,096
-    keys) are processed chunk by chunk; results must not change."""
+    keys), and a single join's outputs beyond one chunk, are processed chunk
+    by chunk into a pending delta; results must not change.  Covers an
+    unfiltered join (Reach), filtered ones (SG), several rules deriving one
+    relation and a three-atom rule (CSPA-shaped), and in-tile dedup."""
     say(f"chunked sort, learned={learned}")
     wl = workloads.scaled_rmat(10, 3000, seed=8)
     rels, deltas, st, want = check_same(PROG["reach"], wl["edb"], {"Reach": 2},
@@ -318,6 +321,14 @@ def test_chunked_new_tuples(learned):
     assert st.candidates > 50 * 4096
     wl = workloads.scaled_tree(2000, seed=2)
     check_same(PROG["sg"], wl["edb"], {"SG": 2}, sort_chunk_log2=12, learned=learned)
+    cs = workloads.cspa(10)["edb"]
+    idb = {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2}
+    check_same(PROG["cspa_shaped"], cs, idb, sort_chunk_log2=12, learned=learned)
+    check_same(PROG["cspa_shaped"], cs, idb, sort_chunk_log2=12, learned=learned,
+               join_dedup=True)
+    wl = workloads.scaled_rmat(10, 3000, seed=8)
+    check_same(PROG["reach"], wl["edb"], {"Reach": 2}, sort_chunk_log2=13, learned=learned,
+               join_dedup=True)
 
 
 def test_error_paths():
