@@ -285,7 +285,7 @@ def timed_runs(engines, steps, cold=None):
     Warm-up repeats (at most three runs) until a run needs no new device
     allocation, so the timed runs measure the steady state of eager buffer
     management; the first run's time goes to ``cold`` (a dict) if given.
-    Returns (seconds per step, per-engine seconds, last stats)."""
+    Returns (summed median seconds, per-engine median seconds, last stats)."""
     import torch
     for k, e in engines.items():
         r = e.run()
@@ -296,13 +296,16 @@ def timed_runs(engines, steps, cold=None):
                 break
             r = e.run()
     torch.cuda.synchronize()
-    per = {k: 0.0 for k in engines}
+    runs = {k: [] for k in engines}
     last = {}
     for _ in range(steps):
         for k, e in engines.items():
             last[k] = e.run()
-            per[k] += last[k].seconds
-    return sum(per.values()) / steps, {k: v / steps for k, v in per.items()}, last
+            runs[k].append(last[k].seconds)
+    # the median run of each engine: one run that met a device allocation
+    # (which the warm-up could not exclude) does not set the figure
+    per = {k: float(np.median(v)) for k, v in runs.items()}
+    return sum(per.values()), per, last
 
 
 def identical(a, b, names, verify):
@@ -451,6 +454,7 @@ def plain_vs_learned(stream, workload, program, edb, idb, steps, verify, extra=N
             r = last["x"]
             out[form] = {"value": r.idb_tuples / secs, "unit": "tuples/s",
                          "ms_per_fixpoint": secs * 1e3, "first_run_ms": cold["x"] * 1e3,
+                         "allocations_last_run": r.allocations,
                          "tuples": r.idb_tuples,
                          "iterations": r.iterations, "join_outputs": r.join_outputs,
                          "candidates": r.candidates,

@@ -775,7 +775,7 @@ struct hl_engine {
     }
     const int bits = hl::learned_bits(ix.n, 2 * w);
     const u64 bytes = hl::learned_bytes(bits);
-    reserve(ix.lm, bytes, bytes);
+    reserve(ix.lm, bytes, 2 * bytes);  // the table doubles as the relation grows
     hl::LearnedView<K> v{};
     HIPCK(hl::learned_fit<K>(keys, ix.n, 2 * w, bits, ix.lm.p, stream, &v, kt()));
     ix.lm_keys = v.keys;

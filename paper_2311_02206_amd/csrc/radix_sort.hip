@@ -53,10 +53,11 @@ __device__ __forceinline__ u32 digit(K k, int shift, int dbits) {
 
 // Per-tile digit histogram; counts are tile-major: counts[tile * 256 + d].
 // No ranks are needed here, so keys are counted with LDS atomic adds rather
-// than ballots.  Each quarter of a wave has its own sub-histogram (padded by
-// one word so that equal digits of different quarters fall in different
-// banks): a digit shared by every key of a wave serialises 16 lanes, not 64.
-constexpr int kSubs = kWaves * 4;
+// than ballots.  Each eighth of a wave has its own sub-histogram (padded by
+// one word so that equal digits of different eighths fall in different
+// banks): a digit shared by every key of a wave serialises 8 lanes, not 64.
+constexpr int kSubsPerWave = 8;
+constexpr int kSubs = kWaves * kSubsPerWave;
 constexpr int kSubStride = kBuckets + 1;
 
 template <typename K>
@@ -75,7 +76,7 @@ __global__ __launch_bounds__(kNT) void rs_hist_kernel(const K* keys, u64 n, int 
     key[j] = i < n ? keys[i] : K(0);
   }
   __syncthreads();
-  u32* h = hist + (w * 4 + (lane_id() >> 4)) * kSubStride;
+  u32* h = hist + (w * kSubsPerWave + lane_id() / (kWave / kSubsPerWave)) * kSubStride;
 #pragma unroll
   for (int j = 0; j < kItems; ++j) {
     u64 i = base + u64(j) * kWave + lane_id();

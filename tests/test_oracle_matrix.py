@@ -144,3 +144,17 @@ def test_planted_mistakes_are_caught(monkeypatch, plant):
             return out
         monkeypatch.setattr(matrix_naive, "_eval_rule", gauss)
     assert _mismatches() > 0
+
+
+def test_cspa_2p15_fixture_is_consistent():
+    """The stored 2^15-id CSPA reference (written by
+    tests/golden/make_cspa_2p15.py from the matrix evaluator) is internally
+    consistent: every relation's size is the sum of its per-iteration
+    deltas, and the last iteration is the empty one."""
+    import json
+    fx = json.load(open(os.path.join(ROOT, "tests", "golden", "cspa_2p15.json")))
+    assert set(fx["relations"]) == set(CSPA_IDB)
+    for n, r in fx["relations"].items():
+        assert len(r["deltas"]) == fx["iterations"]
+        assert sum(r["deltas"]) == r["size"] and r["deltas"][-1] == 0
+        assert len(r["sha256"]) == 64
