@@ -81,8 +81,6 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
                                                           u64 nf, K* tmp, u32* tile_counts,
                                                           u32* tile_uniq, LearnedView<K> lv,
                                                           const u64* part) {
-  __shared__ u64 range[2];
-  __shared__ K before;
   __shared__ u32 wsum[kUdNT / kWave];
   __shared__ u32 wsum2[kUdNT / kWave];
   // one padding slot per kUdItems keys: thread t reads keys t*16 .. t*16+15,
@@ -92,18 +90,26 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
   const u32 tile = blockIdx.x;
   const u64 base = u64(tile) * kUdTile;
   const u32 cnt = u32((n - base) < kUdTile ? (n - base) : kUdTile);
-  if (threadIdx.x == 0) {
-    // every candidate of the tile lies between the tile's first key and the
-    // next tile's first key, so its lower bound in full is in this slice
-    range[0] = part[tile];
-    const u64 h = part[tile + 1] + 1;
-    range[1] = h < nf ? h : nf;
-    before = base > 0 ? cand[base - 1] : K(0);
+  // every candidate of the tile lies between the tile's first key and the
+  // next tile's first key, so its lower bound in full is in this slice.
+  // Each thread reads the bounds itself (one address for the whole block),
+  // so the first chunk of the slice can be requested together with the
+  // candidates instead of after a barrier.
+  const u64 lo = part[tile];
+  const u64 hi = (part[tile + 1] + 1) < nf ? (part[tile + 1] + 1) : nf;
+  const K before = base > 0 ? cand[base - 1] : K(0);
+  const u64 m = hi - lo;
+  constexpr int kPer = int(kUdStage / kUdNT);
+  K next[kPer];
+  if (m <= kUdStreamMax) {
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) {
+      const u64 i = lo + u64(r) * kUdNT + threadIdx.x;
+      next[r] = i < hi ? full[i] : K(0);
+    }
   }
   for (u32 k = threadIdx.x; k < cnt; k += kUdNT) s_c[pad(k)] = cand[base + k];
   __syncthreads();
-  const u64 lo = range[0], hi = range[1];
-  const u64 m = hi - lo;
   const u32 b = threadIdx.x * kUdItems;
   u32 keep_bits = 0, nkeep = 0, uniq = 0;
   if (m <= kUdStreamMax) {
@@ -124,14 +130,8 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
     uniq = u32(__popc(first_bits));
     u32 pending = first_bits;  // distinct keys not yet resolved
     // each thread holds its share of the next chunk in registers, loaded
-    // while the current chunk is searched
-    constexpr int kPer = int(kUdStage / kUdNT);
-    K next[kPer];
-#pragma unroll
-    for (int r = 0; r < kPer; ++r) {
-      const u64 i = lo + u64(r) * kUdNT + threadIdx.x;
-      next[r] = i < hi ? full[i] : K(0);
-    }
+    // while the current chunk is searched (the first one was requested
+    // above)
     for (u64 c0 = lo; c0 < hi; c0 += kUdStage) {  // block-uniform trip count
       const u32 cm = u32((hi - c0) < kUdStage ? (hi - c0) : kUdStage);
       __syncthreads();  // the previous chunk is no longer read

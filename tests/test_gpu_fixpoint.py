@@ -331,6 +331,43 @@ def test_chunked_new_tuples(learned):
                join_dedup=True)
 
 
+def test_memory_budget():
+    """Under a device budget the engine returns cached blocks to the device
+    before exceeding it and still computes the fixpoint exactly; a budget
+    too small fails with HL_E_NOMEM and leaves the engine usable."""
+    import torch
+    import paper_2311_02206_amd as pkg
+    say("memory budget")
+    wl = workloads.scaled_rmat(11, 6000, seed=4)
+    want = oracle.evaluate(PROG["reach"], wl["edb"], {"Reach": 2})
+
+    def make(budget):
+        e = pkg.Engine(device=0, stream=torch.cuda.current_stream(), budget_bytes=budget)
+        e.declare("Edge", 2, True)
+        e.declare("Reach", 2, False)
+        e.load("Edge", wl["edb"]["Edge"])
+        e.program(PROG["reach"])
+        return e
+
+    with make(0) as e:
+        peak = e.run().peak_bytes
+    with make(int(peak * 1.3)) as e:
+        for _ in range(3):
+            st = e.run()
+            assert st.peak_bytes <= int(peak * 1.3)
+            assert np.array_equal(e.fetch("Reach"), want.relations["Reach"])
+            assert e.iteration_counts("Reach", 0) == want.deltas["Reach"]
+    with make(peak // 8) as e:
+        with pytest.raises(pkg.HlError) as ei:
+            e.run()
+        assert ei.value.code == pkg.hisalog.HL_E_NOMEM
+        with pytest.raises(pkg.HlError):
+            e.run()
+    with make(int(peak * 1.3)) as e:  # a fresh engine on the same device works
+        e.run()
+        assert np.array_equal(e.fetch("Reach"), want.relations["Reach"])
+
+
 def test_error_paths():
     import torch
     import paper_2311_02206_amd as pkg
