@@ -68,17 +68,34 @@ def well_formed(e, name):
     return bool(np.all(key[1:] > key[:-1]) and len(R) == sum(e.iteration_counts(name, 0)))
 
 
+def kernel_digest(path, definitions):
+    """SHA-256 of the text that defines a kernel: each named definition
+    (from its opening line to its matching closing brace) and every
+    compile-time constant of the file."""
+    import hashlib
+    src = open(path).read()
+    parts = [ln for ln in src.splitlines() if ln.lstrip().startswith("constexpr")]
+    for d in definitions:
+        i = src.index(d)
+        j = src.index("{", i)
+        depth = 0
+        for k in range(j, len(src)):
+            depth += {"{": 1, "}": -1}.get(src[k], 0)
+            if depth == 0:
+                parts.append(src[i:k + 1])
+                break
+    return hashlib.sha256("\n".join(parts).encode()).hexdigest()
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter passes
     (profiles/<kernel>_traffic.json), or None when there are none or the
-    kernel's source has changed since they were taken."""
-    import hashlib
+    kernel's defining source text has changed since they were taken."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = open(os.path.join(ROOT, rec["source"]), "rb").read()
-    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+    if kernel_digest(os.path.join(ROOT, rec["source"]), rec["definitions"]) != rec["source_digest"]:
         return None
     return rec["hbm_bytes_per_launch"]
 

@@ -430,7 +430,7 @@ struct hl_engine {
   u64* d_small = nullptr;  // device scalars
   u64* h_small = nullptr;  // pinned mirror
   static constexpr int kSmall = 512;
-  static constexpr int kChunkSlots = kSmall - 4;  // two scratch words; the last word is d_err
+  static constexpr int kChunkSlots = kSmall - 4;  // scratch words for chunked deltas
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, hipEvent_t>> marks;
@@ -439,20 +439,6 @@ struct hl_engine {
   EventTimer ktimer;
   hl::LaunchTimer* kt() { return (flags & HL_FLAG_KERNEL_TIMING) ? &ktimer : nullptr; }
   bool learned() const { return flags & HL_FLAG_LEARNED_INDEX; }
-  // Device word that kernels set when a bounded wait ran out (last slot of
-  // d_small; zeroed at the start of every run and primitive call).
-  u32* d_err() { return reinterpret_cast<u32*>(d_small + kSmall - 1); }
-  void zero_err() { HIPCK(hl::fill_zero(d_small + kSmall - 1, sizeof(u64), stream)); }
-  // Call after a synchronisation that copied the word to h_small.
-  void check_err() {
-    if (h_small[kSmall - 1] != 0)
-      fail(HL_E_DEVICE, "radix sort look-back wait ran out (results discarded)");
-  }
-  void fetch_err() {
-    HIPCK(hipMemcpyAsync(h_small + kSmall - 1, d_small + kSmall - 1, sizeof(u64),
-                         hipMemcpyDeviceToHost, stream));
-  }
-
   // ---------------------------------------------------------------- utils
 
   int find(const std::string& n) const {
@@ -854,8 +840,7 @@ struct hl_engine {
     HIPCK(hl::swap_cols<K>(src, n_src, w, kp<K>(tmp[0]), stream));
     reserve(ws, hl::sort_workspace_bytes(n_src), hl::sort_workspace_bytes(n_src) * 2);
     K* sorted = nullptr;
-    HIPCK(hl::radix_sort<K>(kp<K>(tmp[0]), kp<K>(alt), n_src, bits, ws.p, stream, &sorted, kt(),
-                            d_err()));
+    HIPCK(hl::radix_sort<K>(kp<K>(tmp[0]), kp<K>(alt), n_src, bits, ws.p, stream, &sorted, kt()));
     if (from_scratch || ix.n == 0) {
       reserve(ix.keys, n_src * sizeof(K), u64(double(n_src) * sizeof(K) * 1.5));
       HIPCK(hipMemcpyAsync(ix.keys.p, sorted, n_src * sizeof(K), hipMemcpyDeviceToDevice, stream));
@@ -888,7 +873,7 @@ struct hl_engine {
       reserve(ws, hl::sort_workspace_bytes(R.n_raw), hl::sort_workspace_bytes(R.n_raw) * 2);
       K* sorted = nullptr;
       HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_raw, 2 * w, ws.p, stream, &sorted,
-                              kt(), d_err()));
+                              kt()));
       K* other = sorted == kp<K>(R.cand) ? kp<K>(alt) : kp<K>(R.cand);
       reserve(R.full, R.n_raw * sizeof(K), R.n_raw * sizeof(K));
       reserve(ws, hl::unique_diff_workspace_bytes(R.n_raw),
@@ -1091,7 +1076,7 @@ struct hl_engine {
     reserve_grow(alt, m * sizeof(K));
     reserve(ws, hl::sort_workspace_bytes(m), hl::sort_workspace_bytes(m) * 2);
     K* sorted = nullptr;
-    HIPCK(hl::radix_sort<K>(keys, kp<K>(alt), m, bits, ws.p, stream, &sorted, kt(), d_err()));
+    HIPCK(hl::radix_sort<K>(keys, kp<K>(alt), m, bits, ws.p, stream, &sorted, kt()));
     K* other = sorted == keys ? kp<K>(alt) : keys;
     reserve(ws, hl::unique_diff_workspace_bytes(m), hl::unique_diff_workspace_bytes(m) * 2);
     u64* dc = d_small + kChunkSlots;  // scratch counts (not the per-relation slots)
@@ -1169,7 +1154,7 @@ struct hl_engine {
       K* sorted = nullptr;
       mark(HL_PHASE_SORT);
       HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_cand, bits, ws.p, stream, &sorted,
-                              kt(), d_err()));
+                              kt()));
       Buf& sbuf = (sorted == kp<K>(R.cand)) ? R.cand : alt;
       Buf& obuf = (sorted == kp<K>(R.cand)) ? alt : R.cand;
       reserve(ws, hl::unique_diff_workspace_bytes(R.n_cand),
@@ -1187,10 +1172,8 @@ struct hl_engine {
     }
     HIPCK(hipMemcpyAsync(h_small, d_small, 2 * idbs.size() * sizeof(u64), hipMemcpyDeviceToHost,
                          stream));
-    fetch_err();
     mark(-1);
     sync();
-    check_err();
     collect();
     for (auto& c : chunked) {
       h_small[2 * c.first] = c.second.first;
@@ -1246,9 +1229,7 @@ struct hl_engine {
       d = close_iteration<K>();
       ++st.iterations;
     }
-    fetch_err();
     sync();
-    check_err();
     collect();
   }
 
@@ -1364,7 +1345,6 @@ struct hl_engine {
         R.idx[0].cap = R.idx[1].cap = 0;
       }
     }
-    zero_err();
     // key width: ids of every IDB tuple come from the EDBs (range restriction)
     HIPCK(hl::fill_zero(d_small, sizeof(u64), stream));
     for (Relation& R : rels)
@@ -1784,24 +1764,21 @@ int hl_sort_keys(hl_engine* e, void* d_keys, uint64_t n, uint32_t key_bytes, uin
     if (b > int(8 * key_bytes)) fail(HL_E_INVALID, "bits exceed the key width");
     e->reserve_grow(e->alt, n * key_bytes);
     e->reserve(e->ws, hl::sort_workspace_bytes(n), hl::sort_workspace_bytes(n));
-    e->zero_err();
     void* sorted = nullptr;
     if (key_bytes == 4) {
       u32* s = nullptr;
       HIPCK(hl::radix_sort<u32>(static_cast<u32*>(d_keys), static_cast<u32*>(e->alt.p), n, b,
-                                e->ws.p, e->stream, &s, nullptr, e->d_err()));
+                                e->ws.p, e->stream, &s, nullptr));
       sorted = s;
     } else {
       u64* s = nullptr;
       HIPCK(hl::radix_sort<u64>(static_cast<u64*>(d_keys), static_cast<u64*>(e->alt.p), n, b,
-                                e->ws.p, e->stream, &s, nullptr, e->d_err()));
+                                e->ws.p, e->stream, &s, nullptr));
       sorted = s;
     }
     if (sorted != d_keys)
       HIPCK(hipMemcpyAsync(d_keys, sorted, n * key_bytes, hipMemcpyDeviceToDevice, e->stream));
-    e->fetch_err();
     e->sync();
-    e->check_err();
   });
 }
 

@@ -59,10 +59,10 @@ u64 sort_workspace_bytes(u64 n);
 // LSD radix sort of the low `bits` bits of n keys (the bits above must be
 // zero).  Ping-pongs between `keys` and `alt`; *sorted receives whichever
 // holds the result (the other one is free afterwards).  n must be below
-// 2^32.  d_err is unused (kept for a sort with bounded waits).
+// 2^32.
 template <typename K>
 hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted,
-                      LaunchTimer* timer = nullptr, u32* d_err = nullptr);
+                      LaunchTimer* timer = nullptr);
 // Stable LSD radix sort on bits [lo_bit, hi_bit) of the keys only: keys
 // equal on those bits keep their input order (used to group an array by one
 // column).  Same buffers and limits as radix_sort.

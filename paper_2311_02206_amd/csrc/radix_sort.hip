@@ -300,15 +300,14 @@ hipError_t radix_sort_bits(K* keys, K* alt, u64 n, int lo_bit, int hi_bit, void*
 
 template <typename K>
 hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted,
-                      LaunchTimer* timer, u32* d_err) {
-  (void)d_err;  // this sort has no bounded waits that could run out
+                      LaunchTimer* timer) {
   return radix_sort_bits<K>(keys, alt, n, 0, bits, ws, s, sorted, timer);
 }
 
 template hipError_t radix_sort<u32>(u32*, u32*, u64, int, void*, hipStream_t, u32**,
-                                    LaunchTimer*, u32*);
+                                    LaunchTimer*);
 template hipError_t radix_sort<u64>(u64*, u64*, u64, int, void*, hipStream_t, u64**,
-                                    LaunchTimer*, u32*);
+                                    LaunchTimer*);
 template hipError_t radix_sort_bits<u32>(u32*, u32*, u64, int, int, void*, hipStream_t, u32**,
                                          LaunchTimer*);
 template hipError_t radix_sort_bits<u64>(u64*, u64*, u64, int, int, void*, hipStream_t, u64**,
