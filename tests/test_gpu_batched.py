@@ -127,3 +127,33 @@ def test_batch_errors():
         assert e.fetch_batched("Reach", 1).tolist() == [[3, 0]]
         with pytest.raises(pkg.HlError):
             e.fetch_batched("Reach", 2)
+
+
+def test_batched_empty_and_tiny_instances():
+    """Instances with no edges, a single node, a self-loop only, and a
+    cycle, side by side: each instance's result is its own closure, and
+    instances never mix (the closure of the union is the union of the
+    closures when no id is shared)."""
+    import torch
+    import paper_2311_02206_amd as pkg
+    say("batched: empty and tiny instances")
+    ranges = [5, 1, 3, 4, 1]
+    edges = [np.zeros((0, 2), np.uint32),                     # no edges
+             np.zeros((0, 2), np.uint32),                     # one node, no edges
+             np.array([[2, 2]], np.uint32),                   # a self-loop only
+             np.array([[0, 1], [1, 2], [2, 3], [3, 0]], np.uint32),  # a 4-cycle
+             np.array([[0, 0]], np.uint32)]                   # one node with a loop
+    with pkg.Engine(device=0, stream=torch.cuda.current_stream()) as e:
+        e.declare("Edge", 2, True)
+        e.declare("Reach", 2, False)
+        e.batch_layout(ranges)
+        e.load_batched("Edge", edges)
+        e.program(PROG["reach"])
+        for _ in range(2):
+            e.run()
+            for k, ed in enumerate(edges):
+                want = oracle.evaluate(PROG["reach"], {"Edge": ed}, {"Reach": 2}).relations["Reach"]
+                got = e.fetch_batched("Reach", k)
+                assert np.array_equal(got, want), k
+                assert e.batch_count("Reach", k) == len(want)
+        assert e.count("Reach") == 1 + 16 + 1
