@@ -17,9 +17,10 @@ evaluation of the CSPA-shaped program) is in tests/test_gpu_full.py.
 
 Variants on the same line: the learned position index and the autotuned
 settings on the same workload; plain vs learned on the CSPA-shaped program
-(2^14 ids) and on Reach over a 2^22-node subcritical ER graph; eager
-buffer management off vs on; sort and merge of random arity-2 tuples at
-1e6..5e8; 4,096 batched Reach instances against one-at-a-time runs.
+(2^14 ids), on Reach over a 2^22-node subcritical ER graph and on the
+nonlinear closure of that graph; eager buffer management off vs on; sort
+and merge of random arity-2 tuples at 1e6..5e8; 4,096 batched Reach
+instances against one-at-a-time runs.
 
 Prints one JSON line (see the keys below).  --gpus N > 1 is refused: this
 build runs on one GPU.
@@ -236,7 +237,8 @@ def main():
     log("kernel-timed pass")
     line["roofline"], line["kernels"] = kernel_pass(stream, specs, runs=2)
     if not args.no_variants:
-        for name, fn in (("cspa", cspa_variant), ("reach_er_2p22", er_variant)):
+        for name, fn in (("cspa", cspa_variant), ("reach_er_2p22", er_variant),
+                         ("nonlinear_er_2p22", nonlinear_variant)):
             try:
                 line["variants"][name] = fn(stream, max(1, min(args.steps, 3)),
                                             verify=not args.no_verify)
@@ -488,6 +490,18 @@ def plain_vs_learned(stream, workload, program, edb, idb, steps, verify, extra=N
         for d in engines.values():
             d["x"].close()
     return out
+
+
+def nonlinear_variant(stream, steps, verify=True):
+    """The nonlinear closure T(x,y) :- T(x,z), T(z,y) on the 2^22-node ER
+    graph: the growing relation is the join's inner, so its index is
+    refreshed after every merge (hash rebuild, or model refit)."""
+    import workloads
+    log("nonlinear closure variant")
+    wl = workloads.reach_er_2p22()
+    prog = "T(x, y) :- E(x, y).\nT(x, y) :- T(x, z), T(z, y)."
+    return plain_vs_learned(stream, "nonlinear_closure_er_2p22_0.9x", prog,
+                            {"E": wl["edb"]["Edge"]}, {"T": 2}, steps, verify)
 
 
 def cspa_variant(stream, steps, verify=True):

@@ -9,7 +9,9 @@ Contents:
     Datalog (Section 2, semi-naive evaluation; Section 5.1, the fixpoint
     workflow), with a naive mode as a second algorithm;
   * ``reach_bfs_histogram`` / ``reach_from``: per-source breadth-first search
-    for transitive closure, an independent checker of Reach (Section 1);
+    for transitive closure, an independent checker of Reach (Section 1),
+    with the per-iteration delta sizes it implies for the linear and for
+    the nonlinear (doubling) closure program;
   * ``sg_tree_closed_form``: the same-generation relation of a rooted tree in
     closed form, an independent checker of SG (Section 2).
 """
@@ -169,6 +171,26 @@ def reach_deltas_from_histogram(hist) -> list:
     histogram: iteration i derives the pairs at distance exactly i+1, and the
     final iteration is the empty one."""
     return [int(x) for x in hist[1:]] + [0]
+
+
+def doubling_deltas_from_histogram(hist) -> list:
+    """Per-iteration delta sizes of the nonlinear closure
+    T(x, y) :- E(x, y).  T(x, y) :- T(x, z), T(z, y).
+    under Jacobi semi-naive evaluation, from the shortest-distance
+    histogram: iteration 0 holds the pairs at distance 1, and after
+    iteration i the relation holds exactly the pairs at distance <= 2^i
+    (a path of length in (2^(i-1), 2^i] splits into two paths of length at
+    most 2^(i-1), at least one of them longer than 2^(i-2), i.e. new in
+    iteration i-1), so iteration i adds distances 2^(i-1)+1 .. 2^i.  The
+    final iteration is the empty one."""
+    hist = [int(x) for x in hist]
+    out = [hist[1] if len(hist) > 1 else 0]
+    lo = 2
+    while lo < len(hist):
+        hi = 2 * (lo - 1)  # distances lo .. hi = 2^(i-1)+1 .. 2^i
+        out.append(sum(hist[lo:hi + 1]))
+        lo = hi + 1
+    return out + [0] if out[-1] else out
 
 
 def sg_tree_closed_form(edges: np.ndarray):

@@ -118,6 +118,33 @@ def test_reach_er_2p22_subcritical(learned):
     assert st.key_bytes == 8
 
 
+NONLINEAR = "T(x, y) :- E(x, y).\nT(x, y) :- T(x, z), T(z, y)."
+
+
+@pytest.mark.parametrize("learned", [False, True])
+def test_nonlinear_closure_er_2p22(learned):
+    """The nonlinear closure on the 2^22-node ER graph, where the growing
+    relation is itself the join's inner (hash rebuilt, or model refitted,
+    after every merge): count and per-iteration deltas from the distance
+    histogram (doubling), sampled sources row by row."""
+    say(f"nonlinear closure er 2^22, learned={learned}")
+    wl = workloads.reach_er_2p22()
+    E = wl["edb"]["Edge"]
+    e = engine(NONLINEAR, {"E": E}, {"T": 2}, learned=learned)
+    try:
+        st = e.run()
+        say(f"  ran: {st.idb_tuples} tuples, {st.iterations} iterations, {st.seconds:.3f} s")
+        total, hist = oracle.reach_bfs_histogram(wl["n_nodes"], E)
+        assert e.count("T") == total
+        assert e.iteration_counts("T", 0) == oracle.doubling_deltas_from_histogram(hist)
+        T = e.fetch("T")
+        for s in (0, 1, 12345, (1 << 22) - 1):
+            lo, hi = np.searchsorted(T[:, 0], [s, s + 1])
+            assert np.array_equal(T[lo:hi, 1], oracle.reach_from(wl["n_nodes"], E, s)), s
+    finally:
+        e.close()
+
+
 _CSPA_WANT = {}
 
 

@@ -405,3 +405,34 @@ def test_pins_pass_unplanted():
 @pytest.mark.parametrize("plant", [1, 3, 4, 5, 6])
 def test_planted_mistake_is_caught(plant):
     assert not pins_pass(plant)
+
+
+NONLINEAR = "T(x, y) :- E(x, y).\nT(x, y) :- T(x, z), T(z, y)."
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_doubling_deltas_match_semi_naive(seed):
+    """The nonlinear closure's per-iteration deltas implied by the distance
+    histogram (after iteration i exactly the pairs at distance <= 2^i)
+    equal the std::set evaluator's, and so does the final relation."""
+    E = workloads.erdos_renyi(300, 330 + 40 * seed, seed)
+    res = oracle.evaluate(NONLINEAR, {"E": E}, {"T": 2})
+    total, hist = oracle.reach_bfs_histogram(300, E)
+    assert len(res.relations["T"]) == total
+    assert res.deltas["T"] == oracle.doubling_deltas_from_histogram(hist)
+
+
+def test_doubling_deltas_on_a_path():
+    """A directed path of n nodes: distance d has n - d pairs, so iteration
+    i adds the distances 2^(i-1)+1 .. 2^i."""
+    for n in (2, 3, 5, 9, 33):
+        res = oracle.evaluate(NONLINEAR, {"E": path(n)}, {"T": 2})
+        want = [n - 1]
+        lo = 2
+        while lo <= n - 1:
+            hi = min(2 * (lo - 1), n - 1)
+            want.append(sum(n - d for d in range(lo, hi + 1)))
+            lo = hi + 1
+        assert res.deltas["T"] == want + [0]
+        _, hist = oracle.reach_bfs_histogram(n, path(n))
+        assert oracle.doubling_deltas_from_histogram(hist) == want + [0]
