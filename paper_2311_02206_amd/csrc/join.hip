@@ -111,8 +111,22 @@ __global__ __launch_bounds__(kNT) void probe_learned_kernel(const K* outer, u64 
   u32 st = 0, ln = 0;
   if (leader) {
     st = lm_lower_bound(lv, K(jc) << w);
-    const u32 en = (K(jc) == mask) ? u32(lv.n) : lm_lower_bound(lv, (K(jc) + 1) << w);
-    ln = en - st;
+    // the run's end: gallop forward from its start (runs are short, so
+    // this stays within a cache line or two of the start), then bisect
+    if (st < lv.n && K(lv.keys[st] >> w) == K(jc)) {
+      u64 good = st, step = 1;  // keys[good] is in the run
+      while (good + step < lv.n && K(lv.keys[good + step] >> w) == K(jc)) {
+        good += step;
+        step <<= 1;
+      }
+      u64 lo = good + 1, hi = (good + step < lv.n) ? good + step : lv.n;  // end in [lo, hi]
+      while (lo < hi) {
+        const u64 mid = (lo + hi) >> 1;
+        if (K(lv.keys[mid] >> w) == K(jc)) lo = mid + 1;
+        else hi = mid;
+      }
+      ln = u32(lo - st);
+    }
   }
   const u64 upto = lm & ((lane == 63) ? ~u64(0) : ((u64(2) << lane) - 1));
   const int src = upto ? 63 - __clzll((long long)upto) : lane;
