@@ -67,6 +67,28 @@ extern "C" {
                                    price of a slower expand (measured a net
                                    loss at 2,048-slot tiles, hence off by
                                    default) */
+#define HL_FLAG_FUSED 0x10u /* run small iterations of the recursive stratum
+                               as one fused launch: a single workgroup joins
+                               every delta with its inner indexes, sorts,
+                               deduplicates and subtracts full in LDS, and a
+                               merge reads its sizes from device memory, so
+                               an iteration costs a few launches and one
+                               synchronisation instead of dozens of each.
+                               Applies when every join inner is an EDB
+                               relation (Reach, same-generation and the
+                               like; at most 4 IDB relations, 4 rule
+                               variants, 2 joins per rule), eager buffer
+                               management is on, and the last iteration's
+                               output rate predicts that the candidates fit
+                               in LDS (8,192 64-bit or 16,384 32-bit keys
+                               on a 160 KB-LDS device); an iteration whose
+                               candidates do not fit is rerun on the
+                               multi-kernel path.  Results are identical */
+#define HL_FLAG_HIP_GRAPH 0x20u /* HL_FLAG_FUSED, with each fused iteration
+                                   (its launches and the copy of its counts
+                                   to the host) captured once in a HIP graph
+                                   and replayed while its buffers and grid
+                                   stay the same */
 
 /* Kernels reported by hl_kernel_stats. */
 #define HL_KERNEL_RADIX_HIST 0    /* digit histogram of one radix pass */
@@ -86,7 +108,8 @@ extern "C" {
 #define HL_PHASE_DIFF 3      /* dedup + subtraction of full (delta) */
 #define HL_PHASE_MERGE 4     /* full := full U delta */
 #define HL_PHASE_INDEX 5     /* index refresh of probed full relations */
-#define HL_PHASE_COUNT 6
+#define HL_PHASE_FUSED 6     /* fused iterations (HL_FLAG_FUSED), all steps */
+#define HL_PHASE_COUNT 7
 
 typedef struct hl_engine hl_engine;
 
@@ -115,7 +138,12 @@ typedef struct hl_options {
   uint32_t sort_chunk_log2;  /* an iteration's new tuples are sorted in chunks
                                 of at most 2^sort_chunk_log2 keys (12..31;
                                 0: 31) */
-  uint32_t reserved[7];      /* must be zero */
+  uint32_t fused_capacity;   /* candidate keys a fused iteration holds in LDS
+                                (HL_FLAG_FUSED): a power of two from 1,024 up
+                                to what the device's LDS allows; 0: the
+                                largest that fits.  Larger is not faster
+                                per iteration; it lets more iterations fuse */
+  uint32_t reserved[6];      /* must be zero */
 } hl_options;
 
 typedef struct hl_stats {
@@ -123,7 +151,8 @@ typedef struct hl_stats {
                                     EDB-only rules) and the final empty one */
   uint32_t key_bytes;            /* 4 or 8: packed key width chosen at run */
   uint32_t id_bits;              /* w: bits per column in a packed key */
-  uint32_t reserved0;
+  uint32_t fused_iterations;     /* iterations run by the fused launch
+                                    (HL_FLAG_FUSED) */
   uint64_t idb_tuples;           /* sum over IDB relations of |full| at fixpoint */
   uint64_t candidates;           /* new tuples written for sorting over all
                                     iterations (join outputs after filters
@@ -139,6 +168,11 @@ typedef struct hl_stats {
                                     whose results go to a head relation,
                                     before filters and in-tile dedup;
                                     `candidates` counts those kept */
+  uint32_t fused_overflows;      /* fused launches whose candidates did not
+                                    fit (each such iteration was rerun on the
+                                    multi-kernel path) */
+  uint32_t graph_captures;       /* HIP graphs captured (HL_FLAG_HIP_GRAPH);
+                                    the other fused iterations replayed one */
 } hl_stats;
 
 /* Fills *opt with defaults: device 0, no arena, own stream, ebm_k 8,

@@ -345,6 +345,10 @@ struct Relation {
   // distinct tuples of each absorbed chunk
   Buf pend[2];
   u64 n_pend = 0, pend_uniq = 0;
+  // fused iterations: the next delta, the merge's partition points, and
+  // the tail run of recent deltas kept beside full (ping-pong pair)
+  Buf fz_next, fz_parts, fz_tail[2];
+  u64 n_tail = 0;
 };
 
 // --------------------------------------------------------------- the parser
@@ -411,6 +415,7 @@ struct hl_engine {
   float ebm_k = 8.0f;
   float load_factor = 0.5f;
   int sort_chunk_log2 = 31;
+  u32 fused_capacity = 0;  // 0: the largest that fits
   Memory mem;
   std::string err;
 
@@ -436,6 +441,21 @@ struct hl_engine {
   std::vector<std::pair<int, hipEvent_t>> marks;
   hl_stats st{};
   u64 reuses = 0;
+  // fused small iterations (HL_FLAG_FUSED / HL_FLAG_HIP_GRAPH)
+  u64* d_fz = nullptr;  // hl::kFusedCountWords device words
+  u64* h_fz = nullptr;  // pinned mirror
+  bool fz_plans = false;           // the recursive plans qualify
+  bool fz_live = false;            // device counts carry over from the last iteration
+  int fz_key_bytes = 0;            // key width the LDS capacities were set for
+  u32 fz_cap_c = 0, fz_cap_t = 0;  // LDS capacities in keys
+  u64 fz_fail_at = ~u64(0);        // smallest total delta that overflowed in this run
+  u64 last_in = 0, last_out = 0;   // last iteration: outer delta tuples, join outputs
+  struct FzGraph {
+    std::vector<unsigned char> key;
+    hipGraphExec_t exec = nullptr;
+  };
+  std::vector<FzGraph> fz_graphs;
+  u64 fz_iterations = 0, fz_captures = 0, fz_overflows = 0;
   EventTimer ktimer;
   hl::LaunchTimer* kt() { return (flags & HL_FLAG_KERNEL_TIMING) ? &ktimer : nullptr; }
   bool learned() const { return flags & HL_FLAG_LEARNED_INDEX; }
@@ -724,6 +744,16 @@ struct hl_engine {
     for (auto* ps : {&plans0, &plansR})
       for (auto& p : *ps)
         for (auto& s : p.steps) rels[s.inner_rel].idx[s.inner_col].used = true;
+    // fused iterations: every inner of the recursive rules is an EDB index
+    // (built once), so an iteration touches no index of its own outputs
+    int idb = 0;
+    for (auto& R : rels) idb += R.edb ? 0 : 1;
+    fz_plans = idb >= 1 && idb <= hl::kFusedMaxRels && !plansR.empty() &&
+               plansR.size() <= size_t(hl::kFusedMaxPlans);
+    for (auto& p : plansR) {
+      fz_plans &= p.outer_delta && p.steps.size() <= size_t(hl::kFusedMaxSteps);
+      for (auto& s : p.steps) fz_plans &= rels[s.inner_rel].edb;
+    }
   }
 
   // ----------------------------------------------------------------- run
@@ -1215,6 +1245,256 @@ struct hl_engine {
     return total;
   }
 
+  // ------------------------------------------------- fused iterations
+
+  bool fused_on() const {
+    return (flags & (HL_FLAG_FUSED | HL_FLAG_HIP_GRAPH)) && !(flags & HL_FLAG_NO_EBM) && fz_plans;
+  }
+
+  // LDS capacities for key type K: the largest power-of-two candidate
+  // buffer (and half of it for a first join's result) that fits the
+  // device's LDS per workgroup.
+  template <typename K>
+  void fused_setup() {
+    if (fz_key_bytes == int(sizeof(K))) return;
+    int lds = 0;
+    HIPCK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device));
+    const u64 avail = u64(lds) > 1024 ? u64(lds) - 1024 : 0;  // static LDS of the kernel
+    u32 c = 0;
+    for (u32 t = 2; t <= 16384; t <<= 1)
+      if (hl::fused_lds_bytes<K>(t, t / 2) <= avail) c = t;
+    if (c < 1024) fail(HL_E_UNSUPPORTED, "fused iterations need more LDS per workgroup");
+    if (fused_capacity) {
+      if (fused_capacity > c)
+        fail(HL_E_UNSUPPORTED, "fused_capacity exceeds the LDS of one workgroup");
+      c = fused_capacity;
+    }
+    HIPCK(hl::fused_prepare<K>(c, c / 2));
+    fz_cap_c = c;
+    fz_cap_t = c / 2;
+    fz_key_bytes = int(sizeof(K));
+  }
+
+  // Tail runs hold at most this many keys (2 MB of 64-bit keys, so the
+  // membership searches into a tail stay in L2).
+  static constexpr u64 kTailKeys = u64(1) << 18;
+
+  // Folds every tail run into its full relation (one merge each).
+  template <typename K>
+  void flush_tails() {
+    bool any = false;
+    for (Relation& R : rels) {
+      if (R.edb || R.n_tail == 0) continue;
+      if (!any) mark(HL_PHASE_MERGE);
+      any = true;
+      const u64 F = R.n_full, T = R.n_tail;
+      if (F == 0) {
+        reserve(R.full, T * sizeof(K), u64(ebm_k * double(T) * sizeof(K)));
+        HIPCK(hipMemcpyAsync(R.full.p, R.fz_tail[0].p, T * sizeof(K), hipMemcpyDeviceToDevice,
+                             stream));
+      } else {
+        reserve(R.full_spare, (F + T) * sizeof(K), u64((double(F) + ebm_k * double(T)) * sizeof(K)));
+        reserve(ws, hl::merge_workspace_bytes(F, T), hl::merge_workspace_bytes(F, T) * 2);
+        HIPCK(hl::merge<K>(kp<K>(R.full), F, kp<K>(R.fz_tail[0]), T, kp<K>(R.full_spare), ws.p,
+                           stream, kt()));
+        std::swap(R.full, R.full_spare);
+      }
+      R.n_full = F + T;
+      R.idx[0].n = R.n_full;
+      R.n_tail = 0;
+    }
+    if (any) mark(-1);
+    fz_live = false;
+  }
+
+  void drop_graphs() {
+    for (auto& g : fz_graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    fz_graphs.clear();
+  }
+
+  // Whether the next iteration should try the fused path: the last
+  // iteration's join outputs per outer tuple predict the candidates.
+  bool fused_next(u64 sum_delta) const {
+    if (!fused_on() || sum_delta == 0 || sum_delta >= fz_fail_at) return false;
+    const double rate = last_in ? double(last_out) / double(last_in) : 1.0;
+    return double(sum_delta) * std::max(rate, 1.0) <= 0.75 * double(fz_cap_c);
+  }
+
+  // One iteration of the recursive stratum as a fused launch plus
+  // device-sized merges.  Returns false, with the state unchanged, when the
+  // candidates did not fit (the caller then runs the multi-kernel path);
+  // otherwise *total receives the total delta size.
+  template <typename K>
+  bool fused_iteration(u64* total) {
+    fused_setup<K>();
+    std::vector<int> idbs, slot(rels.size(), -1);
+    for (int k = 0; k < int(rels.size()); ++k)
+      if (!rels[k].edb) {
+        slot[k] = int(idbs.size());
+        idbs.push_back(k);
+      }
+    const u64 C = fz_cap_c;
+    hl::FusedIteration<K> it{};
+    it.nrels = int(idbs.size());
+    it.w = w;
+    for (const Plan& p : plansR) {
+      hl::FusedPlan<K> fp{};
+      fp.outer = slot[p.outer_rel];
+      fp.head = slot[p.head];
+      fp.nsteps = int(p.steps.size());
+      bool empty_inner = false;
+      if (p.steps.empty()) {
+        fp.steps[0].js = p.proj;
+        fp.steps[0].js.w = w;
+      }
+      for (size_t q = 0; q < p.steps.size(); ++q) {
+        const Step& s = p.steps[q];
+        Relation& I = rels[s.inner_rel];
+        Index& ix = I.idx[s.inner_col];
+        if (ix.n == 0 || (learned() ? !ix.lm_ok : ix.cap == 0)) empty_inner = true;
+        hl::FusedStep<K>& fs = fp.steps[q];
+        fs.inner = s.inner_col == 0 ? kp<K>(I.full) : kp<K>(ix.keys);
+        if (learned()) fs.lv = ix.view<K>();
+        else {
+          fs.table = static_cast<const Slot*>(ix.table.p);
+          fs.cap = ix.cap;
+        }
+        fs.js = s.js;
+        fs.js.w = w;
+        fs.js.dd = 0;
+      }
+      if (!empty_inner) it.plans[it.nplans++] = fp;  // an empty inner joins nothing
+    }
+    // a tail that could outgrow its buffer this iteration is folded into
+    // full first
+    for (int r : idbs)
+      if (rels[r].n_tail + C > kTailKeys) {
+        flush_tails<K>();
+        break;
+      }
+    std::vector<u64> max_out(idbs.size());
+    for (size_t r = 0; r < idbs.size(); ++r) {
+      Relation& R = rels[idbs[r]];
+      reserve(R.fz_next, C * sizeof(K), C * sizeof(K));
+      for (Buf& t : R.fz_tail) reserve(t, kTailKeys * sizeof(K), kTailKeys * sizeof(K));
+      // the merge grid covers 8 more full-capacity deltas, so a captured
+      // graph serves several iterations
+      max_out[r] = std::min<u64>(kTailKeys, (R.n_tail + C + 8 * C - 1) / (8 * C) * (8 * C));
+      const u64 parts = (hl::fused_merge_tiles(kTailKeys) + 1) * sizeof(u64);
+      reserve(R.fz_parts, parts, parts);
+      it.delta_in[r] = kp<K>(R.delta);
+      it.full[r] = kp<K>(R.full);
+      it.tail[r] = kp<K>(R.fz_tail[0]);
+      it.delta_out[r] = kp<K>(R.fz_next);
+    }
+    it.counts = d_fz;
+    if (!fz_live) {
+      for (int k = 0; k < hl::kFusedCountWords; ++k) h_fz[k] = 0;
+      for (size_t r = 0; r < idbs.size(); ++r) {
+        h_fz[r * hl::kFusedSlots + 0] = rels[idbs[r]].n_delta;
+        h_fz[r * hl::kFusedSlots + 1] = rels[idbs[r]].n_full;
+        h_fz[r * hl::kFusedSlots + 6] = rels[idbs[r]].n_tail;
+      }
+      HIPCK(hipMemcpyAsync(d_fz, h_fz, hl::kFusedCountWords * sizeof(u64), hipMemcpyHostToDevice,
+                           stream));
+    }
+    auto enqueue = [&] {
+      HIPCK(hl::fused_iteration<K>(it, fz_cap_c, fz_cap_t, stream));
+      for (size_t r = 0; r < idbs.size(); ++r) {
+        Relation& R = rels[idbs[r]];
+        HIPCK(hl::fused_merge<K>(kp<K>(R.fz_tail[0]), kp<K>(R.fz_next), d_fz, int(r), max_out[r],
+                                 static_cast<u64*>(R.fz_parts.p), kp<K>(R.fz_tail[1]), stream));
+      }
+      HIPCK(hl::fused_advance(d_fz, it.nrels, stream));
+      HIPCK(hipMemcpyAsync(h_fz, d_fz, hl::kFusedCountWords * sizeof(u64), hipMemcpyDeviceToHost,
+                           stream));
+    };
+    mark(HL_PHASE_FUSED);
+    if (flags & HL_FLAG_HIP_GRAPH) {
+      // the graph is keyed by everything its launches capture: the
+      // iteration's description, the merge targets and grids
+      std::vector<unsigned char> key(sizeof(it));
+      std::memcpy(key.data(), &it, sizeof(it));
+      auto add = [&](const void* p, size_t n) {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        key.insert(key.end(), b, b + n);
+      };
+      for (size_t r = 0; r < idbs.size(); ++r) {
+        const void* ptrs[2] = {rels[idbs[r]].fz_tail[1].p, rels[idbs[r]].fz_parts.p};
+        add(ptrs, sizeof(ptrs));
+        add(&max_out[r], sizeof(u64));
+      }
+      add(&fz_cap_c, sizeof(fz_cap_c));
+      FzGraph* g = nullptr;
+      for (auto& c : fz_graphs)
+        if (c.key == key) g = &c;
+      if (!g) {
+        if (fz_graphs.size() >= 4) {
+          (void)hipGraphExecDestroy(fz_graphs.front().exec);
+          fz_graphs.erase(fz_graphs.begin());
+        }
+        hipGraph_t graph = nullptr;
+        HIPCK(hipStreamBeginCapture(stream, hipStreamCaptureModeRelaxed));
+        try {
+          enqueue();
+        } catch (...) {
+          (void)hipStreamEndCapture(stream, &graph);
+          if (graph) (void)hipGraphDestroy(graph);
+          throw;
+        }
+        HIPCK(hipStreamEndCapture(stream, &graph));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCK(ie);
+        fz_graphs.push_back(FzGraph{std::move(key), exec});
+        g = &fz_graphs.back();
+        ++fz_captures;
+      }
+      HIPCK(hipGraphLaunch(g->exec, stream));
+    } else {
+      enqueue();
+    }
+    mark(-1);
+    sync();
+    collect();
+    if (h_fz[hl::kFusedOverflow] != 0) {
+      u64 sum = 0;
+      for (int r : idbs) sum += rels[r].n_delta;
+      fz_fail_at = std::min(fz_fail_at, sum);
+      fz_live = false;
+      ++fz_overflows;
+      return false;
+    }
+    ++fz_iterations;
+    u64 in = 0, out = 0, d = 0;
+    for (size_t r = 0; r < idbs.size(); ++r) {
+      Relation& R = rels[idbs[r]];
+      const u64* c = h_fz + r * hl::kFusedSlots;
+      in += R.n_delta;
+      out += c[5];
+      st.candidates += c[4];
+      st.join_outputs += c[5];
+      R.delta_counts.push_back(c[2]);
+      R.new_counts.push_back(c[3]);
+      R.raw_cand = 0;
+      R.n_cand = 0;
+      std::swap(R.delta, R.fz_next);
+      R.n_delta = c[2];
+      if (c[2] > 0) {
+        std::swap(R.fz_tail[0], R.fz_tail[1]);
+        R.n_tail += c[2];
+      }
+      d += c[2];
+    }
+    last_in = in;
+    last_out = out;
+    fz_live = true;
+    *total = d;
+    return true;
+  }
+
   template <typename K>
   void run_typed() {
     mark(HL_PHASE_INDEX_EDB);
@@ -1223,12 +1503,28 @@ struct hl_engine {
     for (const Plan& p : plans0) run_plan<K>(p);
     u64 d = close_iteration<K>();
     st.iterations = 1;
+    if (fused_on()) fused_setup<K>();
     while (d != 0) {
+      if (fused_next(d)) {
+        u64 t = 0;
+        if (fused_iteration<K>(&t)) {
+          d = t;
+          ++st.iterations;
+          continue;
+        }
+      }
+      flush_tails<K>();
+      u64 in = 0;
+      for (const Plan& p : plansR) in += rels[p.outer_rel].n_delta;
+      const u64 out0 = st.join_outputs;
       mark(HL_PHASE_JOIN);
       for (const Plan& p : plansR) run_plan<K>(p);
+      last_in = in;
+      last_out = st.join_outputs - out0;
       d = close_iteration<K>();
       ++st.iterations;
     }
+    flush_tails<K>();
     sync();
     collect();
   }
@@ -1328,6 +1624,11 @@ struct hl_engine {
     auto t0 = std::chrono::steady_clock::now();
     st = hl_stats{};
     reuses = 0;
+    fz_live = false;
+    fz_fail_at = ~u64(0);
+    last_in = last_out = 0;
+    fz_iterations = fz_captures = fz_overflows = 0;
+    drop_graphs();
     ktimer.reset();
     mem.reset_counters();
     marks.clear();
@@ -1336,6 +1637,7 @@ struct hl_engine {
       R.delta_counts.clear();
       R.new_counts.clear();
       R.n_delta = R.n_cand = 0;
+      R.n_tail = 0;
       R.dedup = true;
       R.raw_cand = 0;
       R.idx[0].lm_ok = R.idx[1].lm_ok = false;
@@ -1361,6 +1663,9 @@ struct hl_engine {
     else run_typed<u64>();
     st.key_bytes = key_bytes;
     st.id_bits = w;
+    st.fused_iterations = u32(fz_iterations);
+    st.fused_overflows = u32(fz_overflows);
+    st.graph_captures = u32(fz_captures);
     for (Relation& R : rels)
       if (!R.edb) st.idb_tuples += R.n_full;
     st.peak_bytes = mem.peak();
@@ -1494,6 +1799,9 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   if (o.arena && o.arena_bytes < 4096) return HL_E_INVALID;
   if (o.sort_chunk_log2 != 0 && (o.sort_chunk_log2 < 12 || o.sort_chunk_log2 > 31))
     return HL_E_INVALID;
+  if (o.fused_capacity != 0 &&
+      (o.fused_capacity < 1024 || (o.fused_capacity & (o.fused_capacity - 1)) != 0))
+    return HL_E_INVALID;
   if (o.device == -1) {
     // planning-only engine: declarations and programs, no device work
     hl_engine* e = new (std::nothrow) hl_engine();
@@ -1514,6 +1822,7 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   e->ebm_k = o.ebm_k;
   e->load_factor = o.hash_load_factor;
   e->sort_chunk_log2 = o.sort_chunk_log2 ? int(o.sort_chunk_log2) : 31;
+  e->fused_capacity = o.fused_capacity;
   int rc = guard(e, [&] {
     if (o.stream) {
       e->stream = static_cast<hipStream_t>(o.stream);
@@ -1525,6 +1834,9 @@ int hl_create(const hl_options* opt, hl_engine** out) {
     e->mem.set_caching(!(o.flags & HL_FLAG_NO_EBM));
     e->d_small = static_cast<u64*>(e->mem.alloc(hl_engine::kSmall * sizeof(u64)));
     HIPCK(hipHostMalloc(reinterpret_cast<void**>(&e->h_small), hl_engine::kSmall * sizeof(u64),
+                        hipHostMallocDefault));
+    e->d_fz = static_cast<u64*>(e->mem.alloc(hl::kFusedCountWords * sizeof(u64)));
+    HIPCK(hipHostMalloc(reinterpret_cast<void**>(&e->h_fz), hl::kFusedCountWords * sizeof(u64),
                         hipHostMallocDefault));
   });
   if (rc != HL_OK) {
@@ -1543,9 +1855,11 @@ void hl_destroy(hl_engine* e) {
   }
   (void)hipSetDevice(e->device);
   if (e->stream) (void)hipStreamSynchronize(e->stream);
+  e->drop_graphs();
   e->mem.release_all();
   for (hipEvent_t ev : e->ev_pool) (void)hipEventDestroy(ev);
   if (e->h_small) (void)hipHostFree(e->h_small);
+  if (e->h_fz) (void)hipHostFree(e->h_fz);
   if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
   delete e;
 }

@@ -183,4 +183,72 @@ hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* s
 template <typename K>
 hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, hipStream_t s);
 
+// --------------------------------------------------- fused iteration
+// One workgroup runs every rule of the stratum for a small iteration (see
+// fused.hip).  Relations are numbered 0 .. nrels-1 (the IDB relations);
+// each owns kFusedSlots words of `counts` (device memory):
+//   [0] |delta| read this iteration   [1] |full|
+//   [2] |new delta| written           [3] distinct new tuples
+//   [4] new tuples after filters      [5] join outputs before filters
+//   [6] |tail|: a small sorted run of recent deltas kept beside full (full
+//       and tail are disjoint; the relation is their union)
+// and counts[kFusedOverflow] is set to 1 when the candidates of a head (or
+// a first join's result) exceed the LDS capacity; then every [2] is 0 and
+// nothing else of the iteration is valid.
+constexpr int kFusedThreads = 1024;
+constexpr int kFusedMaxRels = 4;
+constexpr int kFusedMaxPlans = 4;
+constexpr int kFusedMaxSteps = 2;
+constexpr int kFusedSlots = 8;
+constexpr int kFusedOverflow = kFusedMaxRels * kFusedSlots;
+constexpr int kFusedCountWords = kFusedOverflow + 1;
+
+template <typename K>
+struct FusedStep {
+  const K* inner;       // the inner relation's sorted array
+  const Slot* table;    // its hash index, or null: probe through lv
+  u64 cap;
+  LearnedView<K> lv;
+  JoinSpec js;          // dd is ignored
+};
+
+template <typename K>
+struct FusedPlan {
+  int outer;   // relation whose delta is the outer side
+  int head;    // relation the outputs go to
+  int nsteps;  // 0: a body of one atom, projected by steps[0].js
+  FusedStep<K> steps[kFusedMaxSteps];
+};
+
+template <typename K>
+struct FusedIteration {
+  int nrels, nplans, w;
+  FusedPlan<K> plans[kFusedMaxPlans];
+  const K* delta_in[kFusedMaxRels];
+  const K* full[kFusedMaxRels];
+  const K* tail[kFusedMaxRels];
+  K* delta_out[kFusedMaxRels];  // room for cap_c keys each
+  u64* counts;                  // kFusedCountWords words
+};
+
+// LDS of one launch: cap_c candidate keys (a power of two), cap_t keys of
+// a first join's result, and per-thread staging.
+template <typename K>
+u64 fused_lds_bytes(u32 cap_c, u32 cap_t);
+// Allows the launch's dynamic LDS size (call once before fused_iteration).
+template <typename K>
+hipError_t fused_prepare(u32 cap_c, u32 cap_t);
+template <typename K>
+hipError_t fused_iteration(const FusedIteration<K>& it, u32 cap_c, u32 cap_t, hipStream_t s);
+// out = merge(tail, new delta) of relation r, sizes from counts[r][6] and
+// counts[r][2]; the grid covers max_out outputs, and `parts` holds
+// fused_merge_tiles(max_out) + 1 words.  Nothing runs after an overflow or
+// for an empty delta.
+u64 fused_merge_tiles(u64 max_out);
+template <typename K>
+hipError_t fused_merge(const K* tail, const K* delta, const u64* counts, int r, u64 max_out,
+                       u64* parts, K* out, hipStream_t s);
+// counts[r][6] += counts[r][2]; counts[r][0] = counts[r][2] (no overflow).
+hipError_t fused_advance(u64* counts, int nrels, hipStream_t s);
+
 }  // namespace hl

@@ -28,9 +28,11 @@ HL_FLAG_NO_EBM = 0x1
 HL_FLAG_KERNEL_TIMING = 0x2
 HL_FLAG_LEARNED_INDEX = 0x4
 HL_FLAG_JOIN_DEDUP = 0x8
+HL_FLAG_FUSED = 0x10
+HL_FLAG_HIP_GRAPH = 0x20
 KERNELS = ("radix_hist", "radix_scatter", "unique_diff", "merge", "join_probe", "join_expand",
            "hisa_build", "learned_fit")
-PHASES = ("index_edb", "join", "sort", "diff", "merge", "index")
+PHASES = ("index_edb", "join", "sort", "diff", "merge", "index", "fused")
 
 # Symbols of include/hisalog.h, in declaration order.
 EXPORTS = (
@@ -54,23 +56,24 @@ class Options(ctypes.Structure):
         ("arena_bytes", ctypes.c_uint64), ("hbm_budget_bytes", ctypes.c_uint64),
         ("stream", ctypes.c_void_p), ("ebm_k", ctypes.c_float),
         ("hash_load_factor", ctypes.c_float), ("sort_chunk_log2", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 7),
+        ("fused_capacity", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 6),
     ]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [
         ("iterations", ctypes.c_uint32), ("key_bytes", ctypes.c_uint32),
-        ("id_bits", ctypes.c_uint32), ("reserved0", ctypes.c_uint32),
+        ("id_bits", ctypes.c_uint32), ("fused_iterations", ctypes.c_uint32),
         ("idb_tuples", ctypes.c_uint64), ("candidates", ctypes.c_uint64),
         ("peak_bytes", ctypes.c_uint64), ("allocations", ctypes.c_uint64),
         ("ebm_reuses", ctypes.c_uint64), ("seconds", ctypes.c_double),
         ("phase_ms", ctypes.c_double * len(PHASES)),
         ("join_outputs", ctypes.c_uint64),
+        ("fused_overflows", ctypes.c_uint32), ("graph_captures", ctypes.c_uint32),
     ]
 
     def as_dict(self) -> dict:
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("phase_ms", "reserved0")}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "phase_ms"}
         d["phase_ms"] = dict(zip(PHASES, list(self.phase_ms)))
         return d
 
@@ -163,6 +166,9 @@ class RunStats:
     seconds: float
     phase_ms: dict = field(default_factory=dict)
     join_outputs: int = 0
+    fused_iterations: int = 0
+    fused_overflows: int = 0
+    graph_captures: int = 0
 
 
 class Engine:
@@ -171,7 +177,8 @@ class Engine:
     def __init__(self, device: int = 0, stream=None, arena=None, ebm: bool = True,
                  ebm_k: float = 8.0, load_factor: float = 0.5, budget_bytes: int = 0,
                  kernel_timing: bool = False, learned: bool = False, sort_chunk_log2: int = 0,
-                 join_dedup: bool = False):
+                 join_dedup: bool = False, fused: bool = False, hip_graph: bool = False,
+                 fused_capacity: int = 0):
         L = lib()
         opt = Options()
         L.hl_options_init(ctypes.byref(opt))
@@ -179,11 +186,14 @@ class Engine:
         opt.flags = ((0 if ebm else HL_FLAG_NO_EBM) |
                      (HL_FLAG_KERNEL_TIMING if kernel_timing else 0) |
                      (HL_FLAG_LEARNED_INDEX if learned else 0) |
-                     (HL_FLAG_JOIN_DEDUP if join_dedup else 0))
+                     (HL_FLAG_JOIN_DEDUP if join_dedup else 0) |
+                     (HL_FLAG_FUSED if fused else 0) |
+                     (HL_FLAG_HIP_GRAPH if hip_graph else 0))
         opt.ebm_k = ebm_k
         opt.hash_load_factor = load_factor
         opt.hbm_budget_bytes = budget_bytes
         opt.sort_chunk_log2 = sort_chunk_log2
+        opt.fused_capacity = fused_capacity
         self._arena = arena  # keep the caller's tensor alive
         if arena is not None:
             opt.arena = _ptr(arena)

@@ -23,11 +23,11 @@ def say(msg):
     sys.stdout.flush()
 
 
-def batched_engine(program, instances, ranges, idb, learned=False):
+def batched_engine(program, instances, ranges, idb, learned=False, **kw):
     import torch
     import paper_2311_02206_amd as pkg
     torch.cuda.set_device(0)
-    e = pkg.Engine(device=0, stream=torch.cuda.current_stream(), learned=learned)
+    e = pkg.Engine(device=0, stream=torch.cuda.current_stream(), learned=learned, **kw)
     e.declare("Edge", 2, True)
     for n in idb:
         e.declare(n, 2, False)
@@ -51,13 +51,16 @@ def small_batch():
     return _SMALL["nodes"], _SMALL["edges"], _SMALL["want"]
 
 
-@pytest.mark.parametrize("learned", [False, True])
-def test_batched_reach_matches_per_instance_oracle(learned):
-    say(f"batched reach, 64 instances, learned={learned}")
+@pytest.mark.parametrize("mode", ["plain", "learned", "fused_graph"])
+def test_batched_reach_matches_per_instance_oracle(mode):
+    say(f"batched reach, 64 instances, {mode}")
     nodes, edges, want = small_batch()
-    e = batched_engine(PROG["reach"], edges, nodes, {"Reach": 2}, learned)
+    kw = {"fused": True, "hip_graph": True} if mode == "fused_graph" else {}
+    e = batched_engine(PROG["reach"], edges, nodes, {"Reach": 2}, mode == "learned", **kw)
     try:
         st = e.run()
+        if mode == "fused_graph":
+            assert st.fused_iterations > 0
         total = 0
         for k in range(len(edges)):
             got = e.fetch_batched("Reach", k)

@@ -40,3 +40,67 @@ def test_create_without_gpu_reports_device_error():
     with pytest.raises(pkg.HlError) as ei:
         pkg.Engine()
     assert ei.value.code == pkg.hisalog.HL_E_DEVICE
+
+
+STRUCTS = {"hl_options": "Options", "hl_stats": "Stats", "hl_tuning": "Tuning"}
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """The ctypes mirrors of the option, statistics and tuning structs have
+    the header's size and field offsets (checked by compiling the header
+    with the host C compiler)."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "hisalog.h"',
+             "int main(void) {"]
+    for cname, pyname in STRUCTS.items():
+        py = getattr(pkg.hisalog, pyname)
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'  printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    want = {}
+    for line in out.splitlines():
+        s, f, v = line.split()
+        want[(s, f)] = int(v)
+    for cname, pyname in STRUCTS.items():
+        py = getattr(pkg.hisalog, pyname)
+        assert ctypes.sizeof(py) == want[(cname, "size")], cname
+        for f, _ in py._fields_:
+            assert getattr(py, f).offset == want[(cname, f)], (cname, f)
+
+
+def test_fused_flags_and_capacity_are_checked_on_a_planning_engine():
+    """hl_create rejects a fused capacity that is not a power of two of at
+    least 1,024, and accepts the fused flags (a planning-only engine needs
+    no GPU)."""
+    import ctypes
+    h = pkg.hisalog
+    L = pkg.lib()
+
+    def create(flags, cap):
+        opt = h.Options()
+        L.hl_options_init(ctypes.byref(opt))
+        opt.device = -1
+        opt.flags = flags
+        opt.fused_capacity = cap
+        e = ctypes.c_void_p()
+        rc = L.hl_create(ctypes.byref(opt), ctypes.byref(e))
+        if rc == 0:
+            L.hl_destroy(e)
+        return rc
+
+    assert create(h.HL_FLAG_FUSED | h.HL_FLAG_HIP_GRAPH, 0) == 0
+    assert create(h.HL_FLAG_FUSED, 4096) == 0
+    assert create(h.HL_FLAG_FUSED, 1000) == h.HL_E_INVALID
+    assert create(h.HL_FLAG_FUSED, 512) == h.HL_E_INVALID
