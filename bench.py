@@ -47,9 +47,9 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def make_engine(program, edb, idb, stream, kernel_timing, learned=False):
+def make_engine(program, edb, idb, stream, kernel_timing, learned=False, **kw):
     from paper_2311_02206_amd import Engine
-    e = Engine(device=0, stream=stream, kernel_timing=kernel_timing, learned=learned)
+    e = Engine(device=0, stream=stream, kernel_timing=kernel_timing, learned=learned, **kw)
     for name in edb:
         e.declare(name, 2, True)
     for name, ar in idb.items():
@@ -459,14 +459,22 @@ def autotuned_variant(stream, specs, steps, plain_value, plain_engines, verify=T
             e.close()
 
 
-def plain_vs_learned(stream, workload, program, edb, idb, steps, verify, extra=None):
-    """One fixpoint timed on the plain HISA engine and on the learned-index
-    engine; the two outputs must be identical."""
+LEARNED_FORMS = (("plain", {}), ("learned_index", {"learned": True}))
+ALL_FORMS = LEARNED_FORMS + (("fused_graph", {"fused": True, "hip_graph": True}),
+                             ("learned_fused_graph", {"learned": True, "fused": True,
+                                                      "hip_graph": True}))
+
+
+def plain_vs_learned(stream, workload, program, edb, idb, steps, verify, extra=None,
+                     forms=LEARNED_FORMS):
+    """One fixpoint timed on the plain HISA engine and on each other form
+    (learned index; fused small iterations from HIP graphs; both); every
+    output must be identical to the plain engine's."""
     out = {"workload": workload}
     engines = {}
     try:
-        for form, learned in (("plain", False), ("learned_index", True)):
-            e = make_engine(program, edb, idb, stream, False, learned=learned)
+        for form, kw in forms:
+            e = make_engine(program, edb, idb, stream, False, **kw)
             engines[form] = {"x": e}
             cold = {}
             secs, _, last = timed_runs({"x": e}, steps, cold)
@@ -478,12 +486,17 @@ def plain_vs_learned(stream, workload, program, edb, idb, steps, verify, extra=N
                          "iterations": r.iterations, "join_outputs": r.join_outputs,
                          "candidates": r.candidates,
                          "key_bytes": r.key_bytes, "peak_bytes": r.peak_bytes,
+                         "fused_iterations": r.fused_iterations,
+                         "graph_captures": r.graph_captures,
                          "phase_ms": r.phase_ms}
             if verify and not well_formed(e, next(iter(idb))):
                 out[form]["well_formed"] = False
         out["learned_vs_plain"] = out["learned_index"]["value"] / out["plain"]["value"]
-        out["identical_output"] = identical(engines["plain"], engines["learned_index"],
-                                            [("x", n) for n in idb], verify)
+        for form, _ in forms[2:]:
+            out[form + "_vs_plain"] = out[form]["value"] / out["plain"]["value"]
+        out["identical_output"] = all(identical(engines["plain"], engines[form],
+                                                [("x", n) for n in idb], verify)
+                                      for form, _ in forms[1:])
         if extra:
             out.update(extra)
     finally:
@@ -525,32 +538,44 @@ def er_variant(stream, steps, verify=True):
     wl = workloads.reach_er_2p22()
     prog = open(os.path.join(ROOT, "workloads", "programs", "reach.dl")).read()
     return plain_vs_learned(stream, "reach_er_2p22_0.9x", prog, wl["edb"], {"Reach": 2},
-                            steps, verify)
+                            steps, verify, forms=ALL_FORMS)
 
 
 def batched_variant(stream, n_inst, sample, steps, program, verify=True):
     """Batched Reach: n_inst independent instances (log-uniform 32..4096 nodes,
-    2-4x edges) in one engine, against the same instances run one at a time
+    2-4x edges) in one engine, with fused small iterations replayed from HIP
+    graphs and without them, against the same instances run one at a time
     (a sample of them, the rate extrapolated per tuple)."""
     import torch
     import workloads
     from paper_2311_02206_amd import Engine
     log(f"batched variant: generating {n_inst} instances")
     nodes, edges = workloads.batched_reach_instances(n_inst, seed=0xC4)
-    e = Engine(device=0, stream=stream, ebm_k=1.5)
-    e.declare("Edge", 2, True)
-    e.declare("Reach", 2, False)
-    e.batch_layout(nodes)
-    e.load_batched("Edge", edges)
-    e.program(program)
-    e.run()  # warm-up
-    torch.cuda.synchronize()
-    t = 0.0
-    for _ in range(steps):
-        st = e.run()
-        t += st.seconds
-    t /= steps
-    log(f"batched: {st.idb_tuples} tuples, {st.iterations} iterations, {t * 1e3:.1f} ms")
+    forms = {}
+    e = None
+    for form, kw in (("plain", {}), ("fused_graph", {"fused": True, "hip_graph": True})):
+        if e is not None:
+            e.close()
+        e = Engine(device=0, stream=stream, ebm_k=1.5, **kw)
+        e.declare("Edge", 2, True)
+        e.declare("Reach", 2, False)
+        e.batch_layout(nodes)
+        e.load_batched("Edge", edges)
+        e.program(program)
+        e.run()  # warm-up
+        torch.cuda.synchronize()
+        t = 0.0
+        for _ in range(steps):
+            st = e.run()
+            t += st.seconds
+        t /= steps
+        log(f"batched {form}: {st.idb_tuples} tuples, {st.iterations} iterations, "
+            f"{st.fused_iterations} fused, {t * 1e3:.1f} ms")
+        forms[form] = {"value": st.idb_tuples / t, "ms_per_fixpoint": t * 1e3,
+                       "fused_iterations": st.fused_iterations,
+                       "graph_captures": st.graph_captures,
+                       "counts": e.iteration_counts("Reach", 0)}
+    # e is the fused engine: its output is checked against one-at-a-time runs
     sample = min(sample, n_inst)
     one_t, one_tuples, same = 0.0, 0, True
     for k in range(sample):
@@ -566,11 +591,14 @@ def batched_variant(stream, n_inst, sample, steps, program, verify=True):
         if verify and (k < 16 or ek.count("Reach") != e.batch_count("Reach", k)):
             same &= bool(np.array_equal(ek.fetch("Reach"), e.fetch_batched("Reach", k)))
         ek.close()
-    value = st.idb_tuples / t
+    value = forms["fused_graph"]["value"]
     one_rate = one_tuples / one_t
+    same_forms = forms["plain"].pop("counts") == forms["fused_graph"].pop("counts")
     out = {"workload": f"batched_reach_{n_inst}_instances", "value": value, "unit": "tuples/s",
-           "ms_per_fixpoint": t * 1e3, "tuples": st.idb_tuples, "iterations": st.iterations,
-           "key_bytes": st.key_bytes, "peak_bytes": st.peak_bytes, "ebm_k": 1.5,
+           "engine": "batched, fused small iterations from HIP graphs",
+           "ms_per_fixpoint": forms["fused_graph"]["ms_per_fixpoint"], "tuples": st.idb_tuples,
+           "iterations": st.iterations, "key_bytes": st.key_bytes, "peak_bytes": st.peak_bytes,
+           "ebm_k": 1.5, "forms": forms, "forms_same_deltas": bool(same_forms),
            "one_at_a_time": {"value": one_rate, "unit": "tuples/s", "sample_instances": sample,
                              "ms": one_t * 1e3},
            "vs_one_at_a_time": value / one_rate,

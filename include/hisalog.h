@@ -260,8 +260,9 @@ int hl_run(hl_engine* e, hl_stats* stats);
 typedef struct hl_tuning {
   float hash_load_factor;  /* load factor of the HISA hash tables */
   float ebm_k;             /* eager buffer growth factor */
-  uint32_t flags;          /* the chosen HL_FLAG_LEARNED_INDEX and
-                              HL_FLAG_JOIN_DEDUP bits */
+  uint32_t flags;          /* the chosen HL_FLAG_LEARNED_INDEX,
+                              HL_FLAG_JOIN_DEDUP, HL_FLAG_FUSED and
+                              HL_FLAG_HIP_GRAPH bits */
   uint32_t trials;         /* settings timed (failed ones included) */
   double best_seconds;     /* fixpoint time under the chosen setting */
   double first_seconds;    /* fixpoint time under the engine's settings
@@ -272,7 +273,9 @@ typedef struct hl_tuning {
  * settings are searched one dimension at a time, starting from the
  * engine's own: how join inners are probed (HISA hash at load factor 0.5,
  * at 0.8, or the learned position index), the eager buffer growth factor
- * (1.5 or 8) and in-tile dedup of join outputs (off or on).  Each setting
+ * (1.5 or 8), in-tile dedup of join outputs (off or on) and, where the
+ * recursive rules qualify, fused small iterations (off, on, or on and
+ * replayed from HIP graphs).  Each setting
  * runs the fixpoint once to warm up and then `reps` times (at least 1),
  * and is scored by its fastest hl_run time; a setting that runs out of
  * device memory is skipped.  Every setting must give the same per-iteration

@@ -1102,6 +1102,7 @@ struct hl_engine {
   template <typename K>
   void absorb(Relation& R, K* keys, u64 m) {
     if (m == 0) return;
+    flush_tail<K>(R);  // the membership test below searches full only
     const int bits = 2 * w;
     reserve_grow(alt, m * sizeof(K));
     reserve(ws, hl::sort_workspace_bytes(m), hl::sort_workspace_bytes(m) * 2);
@@ -1209,6 +1210,37 @@ struct hl_engine {
       h_small[2 * c.first] = c.second.first;
       h_small[2 * c.first + 1] = c.second.second;
     }
+    // relations with a tail run: drop the new tuples the tail already holds
+    // (a second membership pass over the delta, one more synchronisation)
+    {
+      bool any = false;
+      for (size_t q = 0; q < idbs.size(); ++q) {
+        Relation& R = rels[idbs[q]];
+        const u64 D = h_small[2 * q];
+        bool was_chunked = false;
+        for (auto& c : chunked) was_chunked |= c.first == q;
+        if (R.n_tail == 0 || D == 0 || was_chunked) continue;
+        if (!any) mark(HL_PHASE_DIFF);
+        any = true;
+        reserve_grow(tmp[0], D * sizeof(K));
+        reserve(ws, hl::unique_diff_workspace_bytes(D), hl::unique_diff_workspace_bytes(D) * 2);
+        HIPCK(hl::unique_diff<K>(kp<K>(R.delta), D, kp<K>(R.fz_tail[0]), R.n_tail, kp<K>(tmp[0]),
+                                 kp<K>(R.delta), d_small + 2 * q, ws.p, stream, kt()));
+      }
+      if (any) {
+        // relations without a second pass keep their counts on the device,
+        // except the chunked ones (zeroed there); distinct counts stay the
+        // first pass's
+        const std::vector<u64> first(h_small, h_small + 2 * idbs.size());
+        HIPCK(hipMemcpyAsync(h_small, d_small, 2 * idbs.size() * sizeof(u64),
+                             hipMemcpyDeviceToHost, stream));
+        mark(-1);
+        sync();
+        collect();
+        for (size_t q = 0; q < idbs.size(); ++q) h_small[2 * q + 1] = first[2 * q + 1];
+        for (auto& c : chunked) h_small[2 * c.first] = first[2 * c.first];
+      }
+    }
     u64 total = 0;
     std::vector<int> grown;
     mark(HL_PHASE_MERGE);
@@ -1224,6 +1256,37 @@ struct hl_engine {
       total += D;
       if (D == 0) continue;
       const u64 F = R.n_full;
+      if (tail_ok(R) && F * sizeof(K) >= kTailMinFullBytes && (R.n_tail + D) * 8 <= F) {
+        // small delta against a large full: merge it into the tail run only
+        const u64 T = R.n_tail;
+        if (T == 0) {
+          reserve(R.fz_tail[0], D * sizeof(K), u64(ebm_k * double(D) * sizeof(K)));
+          HIPCK(hipMemcpyAsync(R.fz_tail[0].p, R.delta.p, D * sizeof(K), hipMemcpyDeviceToDevice,
+                               stream));
+        } else {
+          reserve(R.fz_tail[1], (T + D) * sizeof(K), u64((double(T) + ebm_k * double(D)) * sizeof(K)));
+          reserve(ws, hl::merge_workspace_bytes(T, D), hl::merge_workspace_bytes(T, D) * 2);
+          HIPCK(hl::merge<K>(kp<K>(R.fz_tail[0]), T, kp<K>(R.delta), D, kp<K>(R.fz_tail[1]), ws.p,
+                             stream, kt()));
+          std::swap(R.fz_tail[0], R.fz_tail[1]);
+        }
+        R.n_tail = T + D;
+        grown.push_back(idbs[q]);
+        continue;
+      }
+      if (R.n_tail > 0) {
+        // the tail takes the delta, then folds into full
+        const u64 T = R.n_tail;
+        reserve(R.fz_tail[1], (T + D) * sizeof(K), u64((double(T) + ebm_k * double(D)) * sizeof(K)));
+        reserve(ws, hl::merge_workspace_bytes(T, D), hl::merge_workspace_bytes(T, D) * 2);
+        HIPCK(hl::merge<K>(kp<K>(R.fz_tail[0]), T, kp<K>(R.delta), D, kp<K>(R.fz_tail[1]), ws.p,
+                           stream, kt()));
+        std::swap(R.fz_tail[0], R.fz_tail[1]);
+        R.n_tail = T + D;
+        flush_tail<K>(R);
+        grown.push_back(idbs[q]);
+        continue;
+      }
       if (F == 0) {
         reserve(R.full, D * sizeof(K), u64(ebm_k * double(D) * sizeof(K)));
         HIPCK(hipMemcpyAsync(R.full.p, R.delta.p, D * sizeof(K), hipMemcpyDeviceToDevice, stream));
@@ -1275,11 +1338,40 @@ struct hl_engine {
     fz_key_bytes = int(sizeof(K));
   }
 
-  // Tail runs hold at most this many keys (2 MB of 64-bit keys, so the
-  // membership searches into a tail stay in L2).
+  // A fused iteration's tail run holds at most this many keys (2 MB of
+  // 64-bit keys, so its membership searches stay in L2); a longer tail left
+  // by the multi-kernel path is folded into full first.
   static constexpr u64 kTailKeys = u64(1) << 18;
+  // On the multi-kernel path a relation keeps a tail run once its full
+  // holds this many bytes and the tail stays within an eighth of it.  The
+  // tail costs a second membership pass per iteration (about 100 us of
+  // dependent searches, whatever its size), so it pays only where
+  // rewriting full costs several times that.
+  static constexpr u64 kTailMinFullBytes = u64(512) << 20;
 
-  // Folds every tail run into its full relation (one merge each).
+  // Folds R's tail run into its full relation (one merge).
+  template <typename K>
+  void flush_tail(Relation& R) {
+    if (R.n_tail == 0) return;
+    const u64 F = R.n_full, T = R.n_tail;
+    if (F == 0) {
+      reserve(R.full, T * sizeof(K), u64(ebm_k * double(T) * sizeof(K)));
+      HIPCK(hipMemcpyAsync(R.full.p, R.fz_tail[0].p, T * sizeof(K), hipMemcpyDeviceToDevice,
+                           stream));
+    } else {
+      reserve(R.full_spare, (F + T) * sizeof(K), u64((double(F) + ebm_k * double(T)) * sizeof(K)));
+      reserve(ws, hl::merge_workspace_bytes(F, T), hl::merge_workspace_bytes(F, T) * 2);
+      HIPCK(hl::merge<K>(kp<K>(R.full), F, kp<K>(R.fz_tail[0]), T, kp<K>(R.full_spare), ws.p,
+                         stream, kt()));
+      std::swap(R.full, R.full_spare);
+    }
+    R.n_full = F + T;
+    R.idx[0].n = R.n_full;
+    R.n_tail = 0;
+    fz_live = false;  // the fused path's device counts describe the old split
+  }
+
+  // Folds every tail run into its full relation.
   template <typename K>
   void flush_tails() {
     bool any = false;
@@ -1287,24 +1379,15 @@ struct hl_engine {
       if (R.edb || R.n_tail == 0) continue;
       if (!any) mark(HL_PHASE_MERGE);
       any = true;
-      const u64 F = R.n_full, T = R.n_tail;
-      if (F == 0) {
-        reserve(R.full, T * sizeof(K), u64(ebm_k * double(T) * sizeof(K)));
-        HIPCK(hipMemcpyAsync(R.full.p, R.fz_tail[0].p, T * sizeof(K), hipMemcpyDeviceToDevice,
-                             stream));
-      } else {
-        reserve(R.full_spare, (F + T) * sizeof(K), u64((double(F) + ebm_k * double(T)) * sizeof(K)));
-        reserve(ws, hl::merge_workspace_bytes(F, T), hl::merge_workspace_bytes(F, T) * 2);
-        HIPCK(hl::merge<K>(kp<K>(R.full), F, kp<K>(R.fz_tail[0]), T, kp<K>(R.full_spare), ws.p,
-                           stream, kt()));
-        std::swap(R.full, R.full_spare);
-      }
-      R.n_full = F + T;
-      R.idx[0].n = R.n_full;
-      R.n_tail = 0;
+      flush_tail<K>(R);
     }
     if (any) mark(-1);
-    fz_live = false;
+  }
+
+  // Whether R may keep a tail run on the multi-kernel path: no join probes
+  // it (its indexes would have to cover the tail), and eager buffers are on.
+  bool tail_ok(const Relation& R) const {
+    return !R.edb && !R.idx[0].used && !R.idx[1].used && !(flags & HL_FLAG_NO_EBM);
   }
 
   void drop_graphs() {
@@ -1377,7 +1460,9 @@ struct hl_engine {
     for (size_t r = 0; r < idbs.size(); ++r) {
       Relation& R = rels[idbs[r]];
       reserve(R.fz_next, C * sizeof(K), C * sizeof(K));
-      for (Buf& t : R.fz_tail) reserve(t, kTailKeys * sizeof(K), kTailKeys * sizeof(K));
+      // the current tail keeps its contents; the other one is the merge target
+      reserve_keep(R.fz_tail[0], R.n_tail * sizeof(K), kTailKeys * sizeof(K));
+      reserve(R.fz_tail[1], kTailKeys * sizeof(K), kTailKeys * sizeof(K));
       // the merge grid covers 8 more full-capacity deltas, so a captured
       // graph serves several iterations
       max_out[r] = std::min<u64>(kTailKeys, (R.n_tail + C + 8 * C - 1) / (8 * C) * (8 * C));
@@ -1513,7 +1598,7 @@ struct hl_engine {
           continue;
         }
       }
-      flush_tails<K>();
+      fz_live = false;
       u64 in = 0;
       for (const Plan& p : plansR) in += rels[p.outer_rel].n_delta;
       const u64 out0 = st.join_outputs;
@@ -1532,13 +1617,15 @@ struct hl_engine {
   // ------------------------------------------------------------ autotune
   struct Setting {
     float lf, k;
-    u32 fl;  // HL_FLAG_LEARNED_INDEX | HL_FLAG_JOIN_DEDUP bits
+    u32 fl;  // kTunedFlags bits
   };
+  static constexpr u32 kTunedFlags =
+      HL_FLAG_LEARNED_INDEX | HL_FLAG_JOIN_DEDUP | HL_FLAG_FUSED | HL_FLAG_HIP_GRAPH;
 
   void apply(const Setting& t) {
     load_factor = t.lf;
     ebm_k = t.k;
-    flags = (flags & ~(HL_FLAG_LEARNED_INDEX | HL_FLAG_JOIN_DEDUP)) | t.fl;
+    flags = (flags & ~kTunedFlags) | t.fl;
   }
 
   // Fastest of `reps` timed runs after a warm-up; +inf if the device ran
@@ -1565,8 +1652,7 @@ struct hl_engine {
 
   void autotune(u32 reps, hl_tuning* out) {
     if (rules.empty()) fail(HL_E_STATE, "no program");
-    const u32 keep = HL_FLAG_LEARNED_INDEX | HL_FLAG_JOIN_DEDUP;
-    Setting best{load_factor, ebm_k, flags & keep};
+    Setting best{load_factor, ebm_k, flags & kTunedFlags};
     std::vector<std::vector<u64>> ref, got;
     u32 trials = 1;
     double best_t = trial(best, reps, &ref);
@@ -1604,6 +1690,17 @@ struct hl_engine {
       Setting t = best;
       t.fl ^= HL_FLAG_JOIN_DEDUP;
       consider(t);
+    }
+    // 4. fused small iterations, launched directly or from a HIP graph
+    // (only where the recursive plans qualify)
+    if (fz_plans && !(flags & HL_FLAG_NO_EBM)) {
+      const Setting b = best;
+      const u32 fz = HL_FLAG_FUSED | HL_FLAG_HIP_GRAPH;
+      for (u32 f : {0u, u32(HL_FLAG_FUSED), fz}) {
+        Setting t = b;
+        t.fl = (b.fl & ~fz) | f;
+        if (t.fl != b.fl) consider(t);
+      }
     }
     if (!have_ref) fail(HL_E_NOMEM, "autotune: every setting ran out of device memory");
     apply(best);

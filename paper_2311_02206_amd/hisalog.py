@@ -306,7 +306,9 @@ class Engine:
         self._check(self._L.hl_autotune(self._h, reps, ctypes.byref(t)), "hl_autotune")
         return {"hash_load_factor": round(t.hash_load_factor, 3), "ebm_k": round(t.ebm_k, 3),
                 "learned": bool(t.flags & HL_FLAG_LEARNED_INDEX),
-                "join_dedup": bool(t.flags & HL_FLAG_JOIN_DEDUP), "trials": t.trials,
+                "join_dedup": bool(t.flags & HL_FLAG_JOIN_DEDUP),
+                "fused": bool(t.flags & (HL_FLAG_FUSED | HL_FLAG_HIP_GRAPH)),
+                "hip_graph": bool(t.flags & HL_FLAG_HIP_GRAPH), "trials": t.trials,
                 "best_seconds": t.best_seconds, "first_seconds": t.first_seconds}
 
     def count(self, name: str) -> int:

@@ -33,11 +33,11 @@ def say(msg):
     sys.stdout.flush()
 
 
-def engine(program, edb, idb, learned=False):
+def engine(program, edb, idb, learned=False, **kw):
     import torch
     import paper_2311_02206_amd as pkg
     torch.cuda.set_device(0)
-    e = pkg.Engine(device=0, stream=torch.cuda.current_stream(), learned=learned)
+    e = pkg.Engine(device=0, stream=torch.cuda.current_stream(), learned=learned, **kw)
     for n in edb:
         e.declare(n, 2, True)
     for n, a in idb.items():
@@ -48,9 +48,9 @@ def engine(program, edb, idb, learned=False):
     return e
 
 
-def check_reach(wl, sources, learned=False):
+def check_reach(wl, sources, learned=False, **kw):
     E = wl["edb"]["Edge"]
-    e = engine(PROG["reach"], wl["edb"], {"Reach": 2}, learned=learned)
+    e = engine(PROG["reach"], wl["edb"], {"Reach": 2}, learned=learned, **kw)
     try:
         st = e.run()
         say(f"  ran: {st.idb_tuples} tuples, {st.iterations} iterations, {st.seconds:.3f} s")
@@ -110,12 +110,26 @@ def test_sg_tree_50k():
         e.close()
 
 
-@pytest.mark.parametrize("learned", [False, True])
-def test_reach_er_2p22_subcritical(learned):
-    say(f"reach er 2^22 subcritical, learned={learned}")
+ER_MODES = {
+    "plain": {},
+    "learned": {"learned": True},
+    # every option on: learned index, fused small iterations from HIP graphs
+    "all_on": {"learned": True, "fused": True, "hip_graph": True},
+    # new tuples sorted in 2^20-key chunks: chunked iterations fold the
+    # tail run into full before their membership tests
+    "chunked": {"sort_chunk_log2": 20},
+}
+
+
+@pytest.mark.parametrize("mode", list(ER_MODES))
+def test_reach_er_2p22_subcritical(mode):
+    say(f"reach er 2^22 subcritical, {mode}")
     wl = workloads.reach_er_2p22()
-    st = check_reach(wl, [0, 1, 12345, (1 << 22) - 1], learned=learned)
+    kw = dict(ER_MODES[mode])
+    st = check_reach(wl, [0, 1, 12345, (1 << 22) - 1], **kw)
     assert st.key_bytes == 8
+    if mode == "all_on":
+        assert st.fused_iterations > 30 and st.graph_captures >= 1
 
 
 NONLINEAR = "T(x, y) :- E(x, y).\nT(x, y) :- T(x, z), T(z, y)."
