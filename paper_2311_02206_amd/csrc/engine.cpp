@@ -455,6 +455,7 @@ struct hl_engine {
     hipGraphExec_t exec = nullptr;
   };
   std::vector<FzGraph> fz_graphs;
+  Buf fz_scratch;  // per-workgroup runs of the fused launch
   u64 fz_iterations = 0, fz_captures = 0, fz_overflows = 0;
   EventTimer ktimer;
   hl::LaunchTimer* kt() { return (flags & HL_FLAG_KERNEL_TIMING) ? &ktimer : nullptr; }
@@ -1474,6 +1475,8 @@ struct hl_engine {
       it.delta_out[r] = kp<K>(R.fz_next);
     }
     it.counts = d_fz;
+    const u64 scratch = hl::fused_scratch_bytes<K>(fz_cap_c, it.nrels);
+    reserve(fz_scratch, scratch, scratch);
     if (!fz_live) {
       for (int k = 0; k < hl::kFusedCountWords; ++k) h_fz[k] = 0;
       for (size_t r = 0; r < idbs.size(); ++r) {
@@ -1485,7 +1488,7 @@ struct hl_engine {
                            stream));
     }
     auto enqueue = [&] {
-      HIPCK(hl::fused_iteration<K>(it, fz_cap_c, fz_cap_t, stream));
+      HIPCK(hl::fused_iteration<K>(it, fz_cap_c, fz_cap_t, fz_scratch.p, stream));
       for (size_t r = 0; r < idbs.size(); ++r) {
         Relation& R = rels[idbs[r]];
         HIPCK(hl::fused_merge<K>(kp<K>(R.fz_tail[0]), kp<K>(R.fz_next), d_fz, int(r), max_out[r],
@@ -1511,6 +1514,7 @@ struct hl_engine {
         add(&max_out[r], sizeof(u64));
       }
       add(&fz_cap_c, sizeof(fz_cap_c));
+      add(&fz_scratch.p, sizeof(fz_scratch.p));
       FzGraph* g = nullptr;
       for (auto& c : fz_graphs)
         if (c.key == key) g = &c;

@@ -32,6 +32,7 @@ namespace {
 constexpr int kFNT = kFusedThreads;  // one workgroup of 1024 threads
 constexpr int kFWaves = kFNT / kWave;
 constexpr int kLock = 4;  // membership searches in flight per thread
+static_assert(kFusedGroups < kFNT, "one finishing thread per phase-A workgroup");
 
 template <typename K>
 __device__ __forceinline__ K fz_pick(int src, K c0, K c1, K o) {
@@ -137,9 +138,14 @@ __device__ __forceinline__ void fz_drop_members(const K* a, u64 n, const K* key,
     if (keep[r] && lo[r] < n && a[lo[r]] == key[r]) keep[r] = false;
 }
 
+// Phase A: workgroup g of G takes the g-th slice of every delta, joins it,
+// sorts and deduplicates its candidates in LDS, and tests each distinct one
+// against full and the tail.  It writes two sorted runs per head: the
+// candidates that are new (survivors) and those already present, and its
+// counts.  Duplicates across workgroups remain; phase B removes them.
 template <typename K>
-__global__ __launch_bounds__(kFNT) void fused_iteration_kernel(FusedIteration<K> it, u32 cap_c,
-                                                               u32 cap_t) {
+__global__ __launch_bounds__(kFNT) void fused_join_kernel(FusedIteration<K> it, u32 cap_c,
+                                                          u32 cap_t, FusedScratch<K> sc) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
   K* cand = reinterpret_cast<K*>(s_dyn);     // cap_c keys: one head's new tuples
   K* tmpb = cand + cap_c;                    // cap_t keys: a first join's result
@@ -150,6 +156,7 @@ __global__ __launch_bounds__(kFNT) void fused_iteration_kernel(FusedIteration<K>
   u64* cnt = it.counts;
   const int w = it.w;
   const K mask = (K(1) << w) - 1;
+  const u32 G = gridDim.x, g = blockIdx.x;
 
   for (int h = 0; h < it.nrels; ++h) {
     u32 m = 0;       // candidates of head h in cand
@@ -157,8 +164,10 @@ __global__ __launch_bounds__(kFNT) void fused_iteration_kernel(FusedIteration<K>
     for (int pi = 0; pi < it.nplans; ++pi) {
       const FusedPlan<K>& p = it.plans[pi];
       if (p.head != h) continue;
-      const K* cur = it.delta_in[p.outer];
-      u32 n = u32(cnt[p.outer * kFusedSlots + 0]);
+      const u64 n_all = cnt[p.outer * kFusedSlots + 0];
+      const u64 lo_i = n_all * g / G, hi_i = n_all * (g + 1) / G;
+      const K* cur = it.delta_in[p.outer] + lo_i;
+      u32 n = u32(hi_i - lo_i);
       if (p.nsteps == 0) {
         const JoinSpec& js = p.steps[0].js;
         for (u32 b = 0; b < n; b += kFNT) {
@@ -245,15 +254,17 @@ __global__ __launch_bounds__(kFNT) void fused_iteration_kernel(FusedIteration<K>
       for (u32 k = m + threadIdx.x; k < p2; k += kFNT) cand[k] = ~K(0);
       __syncthreads();
       if (m > 1) fz_bitonic(cand, p2);
-      // unique, then drop what full or the tail holds: kLock binary
+      // unique, then split by membership in full or the tail: kLock binary
       // searches per thread advance in lockstep so their dependent loads
       // overlap
       const K* full = it.full[h];
       const u64 nf = cnt[h * kFusedSlots + 1];
       const K* tail = it.tail[h];
       const u64 ntl = cnt[h * kFusedSlots + 6];
-      u32 d = 0, uniq = 0;
-      K* out = it.delta_out[h];
+      const u64 slot = u64(h) * G + g;
+      K* surv = sc.surv + slot * cap_c;
+      K* pres = sc.pres + slot * cap_c;
+      u32 ns = 0, np = 0;
       for (u32 b = 0; b < m; b += kFNT * kLock) {
         K key[kLock];
         bool first[kLock], keep[kLock];
@@ -268,23 +279,134 @@ __global__ __launch_bounds__(kFNT) void fused_iteration_kernel(FusedIteration<K>
         fz_drop_members(tail, ntl, key, keep);
 #pragma unroll
         for (int r = 0; r < kLock; ++r) {
-          u32 tu;
-          (void)block_exclusive_scan<kFNT>(first[r] ? 1u : 0u, s_wsum, tu);
-          uniq += tu;
           u32 tot;
-          const u32 pos = block_exclusive_scan<kFNT>(keep[r] ? 1u : 0u, s_wsum, tot);
-          if (keep[r]) out[d + pos] = key[r];
-          d += tot;
+          u32 pos = block_exclusive_scan<kFNT>(keep[r] ? 1u : 0u, s_wsum, tot);
+          if (keep[r]) surv[ns + pos] = key[r];
+          ns += tot;
+          const bool old = first[r] && !keep[r];
+          pos = block_exclusive_scan<kFNT>(old ? 1u : 0u, s_wsum, tot);
+          if (old) pres[np + pos] = key[r];
+          np += tot;
         }
       }
       if (threadIdx.x == 0) {
-        cnt[h * kFusedSlots + 2] = d;
-        cnt[h * kFusedSlots + 3] = uniq;
-        cnt[h * kFusedSlots + 4] = m;
-        cnt[h * kFusedSlots + 5] = raw;
+        u64* c = sc.counts + slot * 4;
+        c[0] = ns;
+        c[1] = np;
+        c[2] = m;
+        c[3] = raw;
       }
       __syncthreads();
     }
+  }
+  return;
+overflow:
+  if (threadIdx.x == 0) cnt[kFusedOverflow] = 1;
+}
+
+// Copies the sorted runs of head h from every phase-A workgroup into
+// dst[0, total): `off` holds the G + 1 run offsets (exclusive prefix of the
+// run lengths, in LDS).  Each output position finds its run by a binary
+// search of the offsets, so all runs are copied at once.
+template <typename K>
+__device__ void fz_gather(const K* runs, int h, u32 G, u32 cap, const u32* off, K* dst) {
+  const u32 total = off[G];
+  for (u32 k = threadIdx.x; k < total; k += kFNT) {
+    u32 lo = 0, hi = G;  // off[lo] <= k < off[hi]
+    while (hi - lo > 1) {
+      const u32 mid = (lo + hi) >> 1;
+      if (off[mid] <= k) lo = mid;
+      else hi = mid;
+    }
+    dst[k] = runs[(u64(h) * G + lo) * cap + (k - off[lo])];
+  }
+  __syncthreads();
+}
+
+// Exclusive prefix of the phase-A run lengths of head h (`which`: 0
+// survivors, 1 present) into off[0, G]; every thread must call it.
+__device__ __forceinline__ u32 fz_offsets(const u64* counts, int h, u32 G, int which, u32* off,
+                                          u32* wsum) {
+  const u32 g = threadIdx.x;
+  const u32 n = g < G ? u32(counts[(u64(h) * G + g) * 4 + which]) : 0u;
+  u32 total;
+  const u32 x = block_exclusive_scan<kFNT>(n, wsum, total);
+  if (g <= G) off[g] = x;
+  __syncthreads();
+  return total;
+}
+
+// Number of distinct keys in the sorted a[0, n); every thread must call it.
+template <typename K>
+__device__ u32 fz_count_distinct(const K* a, u32 n, u32* wsum) {
+  u32 d = 0;
+  for (u32 b = 0; b < n; b += kFNT) {
+    const u32 i = b + threadIdx.x;
+    const bool first = i < n && (i == 0 || a[i - 1] != a[i]);
+    d += block_sum<kFNT>(first ? 1u : 0u, wsum);
+  }
+  return d;
+}
+
+// Phase B, one workgroup: the survivors of all workgroups are sorted and
+// deduplicated into each head's new delta; the distinct count adds the
+// distinct present candidates.  After an overflow in either phase no
+// relation gets a delta.
+template <typename K>
+__global__ __launch_bounds__(kFNT) void fused_finish_kernel(FusedIteration<K> it, u32 cap_c,
+                                                            u32 G, FusedScratch<K> sc) {
+  extern __shared__ __align__(16) unsigned char s_dyn[];
+  K* buf = reinterpret_cast<K*>(s_dyn);  // cap_c keys
+  __shared__ u32 s_wsum[kFWaves];
+  __shared__ u32 s_off[kFusedGroups + 1];
+  __shared__ u64 s_sum[2][kFWaves];
+  u64* cnt = it.counts;
+  if (cnt[kFusedOverflow] != 0) goto overflow;
+  for (int h = 0; h < it.nrels; ++h) {
+    // candidates and join outputs: sums over the workgroups
+    u64 m = 0, raw = 0;
+    {
+      const u32 g = threadIdx.x;
+      const u64 mg = g < G ? sc.counts[(u64(h) * G + g) * 4 + 2] : 0;
+      const u64 rg = g < G ? sc.counts[(u64(h) * G + g) * 4 + 3] : 0;
+      m = block_sum<kFNT>(mg, s_sum[0]);
+      raw = block_sum<kFNT>(rg, s_sum[1]);
+    }
+    u32 n = fz_offsets(sc.counts, h, G, 0, s_off, s_wsum);
+    if (n > cap_c) goto overflow;
+    fz_gather(sc.surv, h, G, cap_c, s_off, buf);
+    u32 p2 = 2;
+    while (p2 < n) p2 <<= 1;
+    for (u32 k = n + threadIdx.x; k < p2; k += kFNT) buf[k] = ~K(0);
+    __syncthreads();
+    if (n > 1) fz_bitonic(buf, p2);
+    K* out = it.delta_out[h];
+    u32 d = 0;
+    for (u32 b = 0; b < n; b += kFNT) {
+      const u32 i = b + threadIdx.x;
+      const bool first = i < n && (i == 0 || buf[i - 1] != buf[i]);
+      u32 tot;
+      const u32 pos = block_exclusive_scan<kFNT>(first ? 1u : 0u, s_wsum, tot);
+      if (first) out[d + pos] = buf[i];
+      d += tot;
+    }
+    __syncthreads();
+    n = fz_offsets(sc.counts, h, G, 1, s_off, s_wsum);
+    if (n > cap_c) goto overflow;
+    fz_gather(sc.pres, h, G, cap_c, s_off, buf);
+    p2 = 2;
+    while (p2 < n) p2 <<= 1;
+    for (u32 k = n + threadIdx.x; k < p2; k += kFNT) buf[k] = ~K(0);
+    __syncthreads();
+    if (n > 1) fz_bitonic(buf, p2);
+    const u32 dp = fz_count_distinct(buf, n, s_wsum);
+    if (threadIdx.x == 0) {
+      cnt[h * kFusedSlots + 2] = d;
+      cnt[h * kFusedSlots + 3] = u64(d) + dp;
+      cnt[h * kFusedSlots + 4] = m;
+      cnt[h * kFusedSlots + 5] = raw;
+    }
+    __syncthreads();
   }
   if (threadIdx.x == 0) cnt[kFusedOverflow] = 0;
   return;
@@ -391,18 +513,29 @@ u64 fused_lds_bytes(u32 cap_c, u32 cap_t) {
 }
 
 template <typename K>
+u64 fused_scratch_bytes(u32 cap_c, int nrels) {
+  const u64 runs = u64(nrels) * kFusedGroups * cap_c * sizeof(K);
+  return 2 * align_up(runs, 256) + align_up(u64(nrels) * kFusedGroups * 4 * sizeof(u64), 256);
+}
+
+template <typename K>
 hipError_t fused_prepare(u32 cap_c, u32 cap_t) {
-  const u64 bytes = fused_lds_bytes<K>(cap_c, cap_t);
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_iteration_kernel<K>),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes));
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_join_kernel<K>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     int(fused_lds_bytes<K>(cap_c, cap_t)));
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_finish_kernel<K>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(u64(cap_c) * sizeof(K)));
 }
 
 u64 fused_merge_tiles(u64 n) { return (n + kFMTile - 1) / kFMTile; }
 
 template <typename K>
-hipError_t fused_iteration(const FusedIteration<K>& it, u32 cap_c, u32 cap_t, hipStream_t s) {
+hipError_t fused_iteration(const FusedIteration<K>& it, u32 cap_c, u32 cap_t, void* scratch,
+                           hipStream_t s) {
   if (it.nrels < 1 || it.nrels > kFusedMaxRels || it.nplans < 0 || it.nplans > kFusedMaxPlans ||
-      cap_c < 2 || (cap_c & (cap_c - 1)) != 0 || !it.counts)
+      cap_c < 2 || (cap_c & (cap_c - 1)) != 0 || !it.counts || !scratch)
     return hipErrorInvalidValue;
   for (int p = 0; p < it.nplans; ++p) {
     const FusedPlan<K>& pl = it.plans[p];
@@ -412,7 +545,17 @@ hipError_t fused_iteration(const FusedIteration<K>& it, u32 cap_c, u32 cap_t, hi
     for (int q = 0; q < pl.nsteps; ++q)
       if (!pl.steps[q].inner || (!pl.steps[q].table && !pl.steps[q].lv.keys)) return hipErrorInvalidValue;
   }
-  fused_iteration_kernel<K><<<1, kFNT, fused_lds_bytes<K>(cap_c, cap_t), s>>>(it, cap_c, cap_t);
+  FusedScratch<K> sc;
+  char* p = static_cast<char*>(scratch);
+  const u64 runs = align_up(u64(it.nrels) * kFusedGroups * cap_c * sizeof(K), 256);
+  sc.surv = reinterpret_cast<K*>(p);
+  sc.pres = reinterpret_cast<K*>(p + runs);
+  sc.counts = reinterpret_cast<u64*>(p + 2 * runs);
+  fused_join_kernel<K><<<kFusedGroups, kFNT, fused_lds_bytes<K>(cap_c, cap_t), s>>>(it, cap_c,
+                                                                                   cap_t, sc);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  fused_finish_kernel<K><<<1, kFNT, u64(cap_c) * sizeof(K), s>>>(it, cap_c, kFusedGroups, sc);
   return hipGetLastError();
 }
 
@@ -438,8 +581,10 @@ hipError_t fused_advance(u64* counts, int nrels, hipStream_t s) {
 
 #define HL_INSTANTIATE(K)                                                                      \
   template u64 fused_lds_bytes<K>(u32, u32);                                                   \
+  template u64 fused_scratch_bytes<K>(u32, int);                                               \
   template hipError_t fused_prepare<K>(u32, u32);                                              \
-  template hipError_t fused_iteration<K>(const FusedIteration<K>&, u32, u32, hipStream_t);     \
+  template hipError_t fused_iteration<K>(const FusedIteration<K>&, u32, u32, void*,            \
+                                         hipStream_t);                                         \
   template hipError_t fused_merge<K>(const K*, const K*, const u64*, int, u64, u64*, K*,       \
                                      hipStream_t);
 HL_INSTANTIATE(u32)

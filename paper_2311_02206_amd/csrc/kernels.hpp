@@ -231,15 +231,31 @@ struct FusedIteration {
   u64* counts;                  // kFusedCountWords words
 };
 
-// LDS of one launch: cap_c candidate keys (a power of two), cap_t keys of
-// a first join's result, and per-thread staging.
+// Workgroups of the first phase of a fused iteration: each joins a slice of
+// every delta and tests its candidates; one workgroup then deduplicates
+// their survivors into the deltas.
+constexpr int kFusedGroups = 64;
+
+template <typename K>
+struct FusedScratch {
+  K* surv;      // [rel][group] runs of cap_c keys: new candidates
+  K* pres;      // [rel][group] runs of cap_c keys: candidates already held
+  u64* counts;  // [rel][group][4]: |surv|, |pres|, candidates, join outputs
+};
+
+// LDS of one phase-A workgroup: cap_c candidate keys (a power of two),
+// cap_t keys of a first join's result, and per-thread staging.
 template <typename K>
 u64 fused_lds_bytes(u32 cap_c, u32 cap_t);
-// Allows the launch's dynamic LDS size (call once before fused_iteration).
+// Device scratch of fused_iteration for nrels relations.
+template <typename K>
+u64 fused_scratch_bytes(u32 cap_c, int nrels);
+// Allows the launches' dynamic LDS sizes (call once before fused_iteration).
 template <typename K>
 hipError_t fused_prepare(u32 cap_c, u32 cap_t);
 template <typename K>
-hipError_t fused_iteration(const FusedIteration<K>& it, u32 cap_c, u32 cap_t, hipStream_t s);
+hipError_t fused_iteration(const FusedIteration<K>& it, u32 cap_c, u32 cap_t, void* scratch,
+                           hipStream_t s);
 // out = merge(tail, new delta) of relation r, sizes from counts[r][6] and
 // counts[r][2]; the grid covers max_out outputs, and `parts` holds
 // fused_merge_tiles(max_out) + 1 words.  Nothing runs after an overflow or
