@@ -131,6 +131,9 @@ def main():
     ap.add_argument("--batched-instances", type=int, default=4096,
                     help="independent Reach instances for the batched variant (0: skip)")
     ap.add_argument("--one-at-a-time-sample", type=int, default=256)
+    ap.add_argument("--variant", default="",
+                    help="run only this comparison (cspa, reach_er_2p22, nonlinear_er_2p22, "
+                         "batched, ebm_ablation, table6_microbench) and print its JSON")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once (a reference kernel of known "
                          "size for hardware byte counters)")
@@ -155,6 +158,22 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {args.copy_calibration_mb} MiB device to device")
         del src, dst
+    if args.variant:
+        steps = max(1, min(args.steps, 3))
+        verify = not args.no_verify
+        only = {"cspa": lambda: cspa_variant(stream, steps, verify=verify),
+                "reach_er_2p22": lambda: er_variant(stream, steps, verify=verify),
+                "nonlinear_er_2p22": lambda: nonlinear_variant(stream, steps, verify=verify),
+                "batched": lambda: batched_variant(stream, max(1, args.batched_instances),
+                                                   args.one_at_a_time_sample, steps,
+                                                   programs["reach"], verify=verify),
+                "ebm_ablation": lambda: ebm_ablation(stream, steps),
+                "table6_microbench": lambda: table6_microbench(stream)}
+        if args.variant not in only:
+            print(f"unknown variant {args.variant}; one of {sorted(only)}", file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({"variant": args.variant, "result": only[args.variant]()}), flush=True)
+        return
     log("generating inputs")
     reach_wl = workloads.reach_rmat16()
     sg_wl = workloads.sg_tree_50k()
@@ -562,7 +581,9 @@ def batched_variant(stream, n_inst, sample, steps, program, verify=True):
         e.batch_layout(nodes)
         e.load_batched("Edge", edges)
         e.program(program)
-        e.run()  # warm-up
+        for _ in range(4):  # warm-up until the buffers have settled
+            if e.run().allocations == 0:
+                break
         torch.cuda.synchronize()
         t = 0.0
         for _ in range(steps):
@@ -573,7 +594,10 @@ def batched_variant(stream, n_inst, sample, steps, program, verify=True):
             f"{st.fused_iterations} fused, {t * 1e3:.1f} ms")
         forms[form] = {"value": st.idb_tuples / t, "ms_per_fixpoint": t * 1e3,
                        "fused_iterations": st.fused_iterations,
+                       "fused_overflows": st.fused_overflows,
                        "graph_captures": st.graph_captures,
+                       "allocations_last_run": st.allocations, "peak_bytes": st.peak_bytes,
+                       "phase_ms": st.phase_ms,
                        "counts": e.iteration_counts("Reach", 0)}
     # e is the fused engine: its output is checked against one-at-a-time runs
     sample = min(sample, n_inst)

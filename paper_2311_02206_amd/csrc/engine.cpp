@@ -1339,9 +1339,9 @@ struct hl_engine {
     fz_key_bytes = int(sizeof(K));
   }
 
-  // A fused iteration's tail run holds at most this many keys (2 MB of
-  // 64-bit keys, so its membership searches stay in L2); a longer tail left
-  // by the multi-kernel path is folded into full first.
+  // A fused iteration's tail run next to a full below kTailMinFullBytes
+  // holds at most this many keys (2 MB of 64-bit keys, so its membership
+  // searches stay in L2); a longer one is folded into full first.
   static constexpr u64 kTailKeys = u64(1) << 18;
   // On the multi-kernel path a relation keeps a tail run once its full
   // holds this many bytes and the tail stays within an eighth of it.  The
@@ -1411,6 +1411,7 @@ struct hl_engine {
   // otherwise *total receives the total delta size.
   template <typename K>
   bool fused_iteration(u64* total) {
+    mark(HL_PHASE_FUSED);
     fused_setup<K>();
     std::vector<int> idbs, slot(rels.size(), -1);
     for (int k = 0; k < int(rels.size()); ++k)
@@ -1450,25 +1451,32 @@ struct hl_engine {
       }
       if (!empty_inner) it.plans[it.nplans++] = fp;  // an empty inner joins nothing
     }
-    // a tail that could outgrow its buffer this iteration is folded into
-    // full first
-    for (int r : idbs)
-      if (rels[r].n_tail + C > kTailKeys) {
-        flush_tails<K>();
-        break;
+    // The tail may grow by C keys this iteration.  Past kTailKeys it is
+    // folded into full first, unless full is so large that the multi-kernel
+    // path would keep the tail too (then it is folded once it reaches an
+    // eighth of full).
+    for (int r : idbs) {
+      Relation& R = rels[r];
+      const bool big = R.n_full * sizeof(K) >= kTailMinFullBytes;
+      if (R.n_tail + C > (big ? R.n_full / 8 : kTailKeys)) {
+        mark(HL_PHASE_MERGE);
+        flush_tail<K>(R);
+        mark(-1);
       }
+    }
     std::vector<u64> max_out(idbs.size());
     for (size_t r = 0; r < idbs.size(); ++r) {
       Relation& R = rels[idbs[r]];
       reserve(R.fz_next, C * sizeof(K), C * sizeof(K));
-      // the current tail keeps its contents; the other one is the merge target
-      reserve_keep(R.fz_tail[0], R.n_tail * sizeof(K), kTailKeys * sizeof(K));
-      reserve(R.fz_tail[1], kTailKeys * sizeof(K), kTailKeys * sizeof(K));
       // the merge grid covers 8 more full-capacity deltas, so a captured
       // graph serves several iterations
-      max_out[r] = std::min<u64>(kTailKeys, (R.n_tail + C + 8 * C - 1) / (8 * C) * (8 * C));
-      const u64 parts = (hl::fused_merge_tiles(kTailKeys) + 1) * sizeof(u64);
-      reserve(R.fz_parts, parts, parts);
+      max_out[r] = (R.n_tail + C + 8 * C - 1) / (8 * C) * (8 * C);
+      // the merge target holds the tail and one more delta (with room for
+      // the grid's span, so the pair of buffers settles after two rounds)
+      const u64 want = std::max<u64>(kTailKeys, max_out[r]);
+      reserve(R.fz_tail[1], (R.n_tail + C) * sizeof(K), want * sizeof(K));
+      const u64 parts = (hl::fused_merge_tiles(max_out[r]) + 1) * sizeof(u64);
+      reserve(R.fz_parts, parts, (hl::fused_merge_tiles(want) + 1) * sizeof(u64));
       it.delta_in[r] = kp<K>(R.delta);
       it.full[r] = kp<K>(R.full);
       it.tail[r] = kp<K>(R.fz_tail[0]);
