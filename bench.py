@@ -133,7 +133,8 @@ def main():
     ap.add_argument("--one-at-a-time-sample", type=int, default=256)
     ap.add_argument("--variant", default="",
                     help="run only this comparison (cspa, reach_er_2p22, nonlinear_er_2p22, "
-                         "batched, ebm_ablation, table6_microbench) and print its JSON")
+                         "batched, ebm_ablation, nested_join_ablation, table6_microbench) and "
+                         "print its JSON")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once (a reference kernel of known "
                          "size for hardware byte counters)")
@@ -168,6 +169,7 @@ def main():
                                                    args.one_at_a_time_sample, steps,
                                                    programs["reach"], verify=verify),
                 "ebm_ablation": lambda: ebm_ablation(stream, steps),
+                "nested_join_ablation": lambda: nested_ablation(stream, steps, verify=verify),
                 "table6_microbench": lambda: table6_microbench(stream)}
         if args.variant not in only:
             print(f"unknown variant {args.variant}; one of {sorted(only)}", file=sys.stderr)
@@ -265,6 +267,9 @@ def main():
                 line["variants"][name] = {"error": repr(exc)}
     if not args.no_variants:
         for name, fn in (("ebm_ablation", lambda: ebm_ablation(stream, max(1, min(args.steps, 3)))),
+                         ("nested_join_ablation",
+                          lambda: nested_ablation(stream, max(1, min(args.steps, 3)),
+                                                  verify=not args.no_verify)),
                          ("table6_microbench", lambda: table6_microbench(stream))):
             try:
                 line["variants"][name] = fn()
@@ -510,9 +515,9 @@ def plain_vs_learned(stream, workload, program, edb, idb, steps, verify, extra=N
                          "phase_ms": r.phase_ms}
             if verify and not well_formed(e, next(iter(idb))):
                 out[form]["well_formed"] = False
-        out["learned_vs_plain"] = out["learned_index"]["value"] / out["plain"]["value"]
-        for form, _ in forms[2:]:
-            out[form + "_vs_plain"] = out[form]["value"] / out["plain"]["value"]
+        for form, _ in forms[1:]:
+            key = "learned_vs_plain" if form == "learned_index" else form + "_vs_plain"
+            out[key] = out[form]["value"] / out["plain"]["value"]
         out["identical_output"] = all(identical(engines["plain"], engines[form],
                                                 [("x", n) for n in idb], verify)
                                       for form, _ in forms[1:])
@@ -534,6 +539,18 @@ def nonlinear_variant(stream, steps, verify=True):
     prog = "T(x, y) :- E(x, y).\nT(x, y) :- T(x, z), T(z, y)."
     return plain_vs_learned(stream, "nonlinear_closure_er_2p22_0.9x", prog,
                             {"E": wl["edb"]["Edge"]}, {"T": 2}, steps, verify)
+
+
+def nested_ablation(stream, steps, verify=True):
+    """Section 5.2 ablation on same-generation over the 50,000-node tree: the
+    three-atom rule as a materialised chain of load-balanced binary joins
+    (plain) against nested loops, one thread per outer tuple."""
+    import workloads
+    log("nested join ablation")
+    wl = workloads.sg_tree_50k()
+    prog = open(os.path.join(ROOT, "workloads", "programs", "sg.dl")).read()
+    return plain_vs_learned(stream, "sg_tree_50k", prog, wl["edb"], {"SG": 2}, steps, verify,
+                            forms=(("plain", {}), ("nested_joins", {"nested_joins": True})))
 
 
 def cspa_variant(stream, steps, verify=True):

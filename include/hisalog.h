@@ -89,6 +89,15 @@ extern "C" {
                                    to the host) captured once in a HIP graph
                                    and replayed while its buffers and grid
                                    stay the same */
+#define HL_FLAG_NESTED_JOINS 0x40u /* ablation of Section 5.2: evaluate a rule
+                                     body of two joins as nested loops, one
+                                     thread per outer tuple walking both
+                                     runs, instead of materialising the first
+                                     join's result and joining it again
+                                     (load-balanced).  Results are identical;
+                                     `join_outputs` then counts the kept
+                                     outputs.  Bodies whose outputs exceed one
+                                     sort chunk keep the materialised form */
 
 /* Kernels reported by hl_kernel_stats. */
 #define HL_KERNEL_RADIX_HIST 0    /* digit histogram of one radix pass */
@@ -261,8 +270,8 @@ typedef struct hl_tuning {
   float hash_load_factor;  /* load factor of the HISA hash tables */
   float ebm_k;             /* eager buffer growth factor */
   uint32_t flags;          /* the chosen HL_FLAG_LEARNED_INDEX,
-                              HL_FLAG_JOIN_DEDUP, HL_FLAG_FUSED and
-                              HL_FLAG_HIP_GRAPH bits */
+                              HL_FLAG_JOIN_DEDUP, HL_FLAG_NESTED_JOINS,
+                              HL_FLAG_FUSED and HL_FLAG_HIP_GRAPH bits */
   uint32_t trials;         /* settings timed (failed ones included) */
   double best_seconds;     /* fixpoint time under the chosen setting */
   double first_seconds;    /* fixpoint time under the engine's settings
@@ -273,9 +282,10 @@ typedef struct hl_tuning {
  * settings are searched one dimension at a time, starting from the
  * engine's own: how join inners are probed (HISA hash at load factor 0.5,
  * at 0.8, or the learned position index), the eager buffer growth factor
- * (1.5 or 8), in-tile dedup of join outputs (off or on) and, where the
- * recursive rules qualify, fused small iterations (off, on, or on and
- * replayed from HIP graphs).  Each setting
+ * (1.5 or 8), in-tile dedup of join outputs (off or on), nested
+ * evaluation of two-join bodies (off or on, where a rule has one) and,
+ * where the recursive rules qualify, fused small iterations (off, on, or
+ * on and replayed from HIP graphs).  Each setting
  * runs the fixpoint once to warm up and then `reps` times (at least 1),
  * and is scored by its fastest hl_run time; a setting that runs out of
  * device memory is skipped.  Every setting must give the same per-iteration

@@ -953,6 +953,7 @@ struct hl_engine {
       }
       return;
     }
+    if ((flags & HL_FLAG_NESTED_JOINS) && p.steps.size() == 2 && run_nested<K>(p, cur, n)) return;
     int ping = 0;
     for (size_t q = 0; q < p.steps.size(); ++q) {
       const Step& s = p.steps[q];
@@ -1085,6 +1086,59 @@ struct hl_engine {
         if (n == 0) return;
       }
     }
+  }
+
+  // A two-join body evaluated by nested loops (HL_FLAG_NESTED_JOINS, the
+  // paper's nested joins of Section 5.2, kept as an ablation of the
+  // materialised chain): one thread per outer tuple, a counting pass, a
+  // scan and a writing pass.  Returns false when the outputs exceed one
+  // sort chunk (the materialised chain then runs instead).
+  template <typename K>
+  bool run_nested(const Plan& p, const K* cur, u64 n) {
+    Relation& H = rels[p.head];
+    hl::NestedJoin<K> nj{};
+    for (int q = 0; q < 2; ++q) {
+      const Step& s = p.steps[q];
+      Relation& I = rels[s.inner_rel];
+      Index& ix = I.idx[s.inner_col];
+      if (ix.n == 0 || (learned() ? !ix.lm_ok : ix.cap == 0)) return true;  // nothing joins
+      nj.inner[q] = s.inner_col == 0 ? kp<K>(I.full) : kp<K>(ix.keys);
+      if (learned()) {
+        nj.lv[q] = ix.view<K>();
+      } else {
+        nj.table[q] = static_cast<const Slot*>(ix.table.p);
+        nj.cap[q] = ix.cap;
+      }
+      nj.js[q] = s.js;
+      nj.js[q].w = w;
+      nj.js[q].dd = 0;
+    }
+    if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "join outer side of 2^32 or more tuples");
+    reserve_grow(join_len, n * sizeof(u32));
+    reserve_grow(join_off, n * sizeof(u64));
+    reserve(ws, hl::scan_workspace_bytes(n), hl::scan_workspace_bytes(n) * 2);
+    u32* too_many = reinterpret_cast<u32*>(d_small + 2);
+    HIPCK(hl::fill_zero(d_small + 2, sizeof(u64), stream));
+    HIPCK(hl::join_nested<K>(cur, n, nj, static_cast<u32*>(join_len.p),
+                             static_cast<u64*>(join_off.p), d_small + 1, too_many, ws.p, nullptr,
+                             stream));
+    HIPCK(hipMemcpyAsync(h_small + 1, d_small + 1, 2 * sizeof(u64), hipMemcpyDeviceToHost,
+                         stream));
+    sync();
+    if (u32(h_small[2]) != 0)
+      fail(HL_E_UNSUPPORTED, "nested join: an outer tuple with 2^32 or more outputs");
+    const u64 total = h_small[1];
+    if (total > (u64(1) << sort_chunk_log2)) return false;
+    if (total == 0) return true;
+    // the nested form counts kept outputs only: they are its join outputs
+    H.raw_cand += total;
+    st.join_outputs += total;
+    reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + total) * sizeof(K));
+    HIPCK(hl::join_nested<K>(cur, n, nj, nullptr, static_cast<u64*>(join_off.p), nullptr, nullptr,
+                             nullptr, kp<K>(H.cand) + H.n_cand, stream));
+    H.n_cand += total;
+    st.candidates += total;
+    return true;
   }
 
   // Model of R's full relation for the set difference, if it has a current one.
@@ -1631,8 +1685,8 @@ struct hl_engine {
     float lf, k;
     u32 fl;  // kTunedFlags bits
   };
-  static constexpr u32 kTunedFlags =
-      HL_FLAG_LEARNED_INDEX | HL_FLAG_JOIN_DEDUP | HL_FLAG_FUSED | HL_FLAG_HIP_GRAPH;
+  static constexpr u32 kTunedFlags = HL_FLAG_LEARNED_INDEX | HL_FLAG_JOIN_DEDUP | HL_FLAG_FUSED |
+                                     HL_FLAG_HIP_GRAPH | HL_FLAG_NESTED_JOINS;
 
   void apply(const Setting& t) {
     load_factor = t.lf;
@@ -1703,7 +1757,18 @@ struct hl_engine {
       t.fl ^= HL_FLAG_JOIN_DEDUP;
       consider(t);
     }
-    // 4. fused small iterations, launched directly or from a HIP graph
+    // 4. nested evaluation of two-join bodies (only where there are some)
+    {
+      bool two = false;
+      for (auto* ps : {&plans0, &plansR})
+        for (const Plan& p : *ps) two |= p.steps.size() == 2;
+      if (two) {
+        Setting t = best;
+        t.fl ^= HL_FLAG_NESTED_JOINS;
+        consider(t);
+      }
+    }
+    // 5. fused small iterations, launched directly or from a HIP graph
     // (only where the recursive plans qualify)
     if (fz_plans && !(flags & HL_FLAG_NO_EBM)) {
       const Setting b = best;

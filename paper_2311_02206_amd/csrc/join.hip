@@ -368,6 +368,83 @@ __global__ __launch_bounds__(kNT) void project_kernel(const K* in, u64 n, JoinSp
   if (filtered) cmp.flush(out, cursor, &s_base);
 }
 
+// ------------------------------------------------------ nested joins
+// The paper's nested evaluation of a two-join body (Section 5.2), kept as
+// an ablation of the materialised form above: one thread per outer tuple
+// walks the run of its first join and, for every tuple of it, the run of
+// the second join.  A first pass counts each thread's kept outputs, a scan
+// turns the counts into offsets, and a second pass writes them.
+struct NestedSide {
+  const void* inner;
+  const Slot* table;  // hash index, or null: probe through the learned view
+  u64 cap;
+  JoinSpec js;
+};
+
+template <typename K>
+__device__ __forceinline__ void nested_run(const NestedSide& s, const LearnedView<K>& lv, u32 jc,
+                                           int w, u64& start, u64& len) {
+  start = 0;
+  len = 0;
+  if (s.table) {
+    u32 st = 0, ln = 0;
+    if (hisa_find(s.table, s.cap, jc, st, ln)) {
+      start = st;
+      len = ln;
+    }
+    return;
+  }
+  const u32 st = lm_lower_bound(lv, K(jc) << w);
+  if (st >= lv.n || K(lv.keys[st] >> w) != K(jc)) return;
+  const K next = (K(jc) + 1) << w;
+  const u32 en = next == 0 ? u32(lv.n) : lm_lower_bound(lv, next);
+  start = st;
+  len = en - st;
+}
+
+template <typename K, bool kWrite>
+__global__ __launch_bounds__(kNT) void nested_kernel(const K* outer, u64 n, NestedSide a,
+                                                     LearnedView<K> la, NestedSide b,
+                                                     LearnedView<K> lb, u32* count,
+                                                     const u64* off, K* out, u32* too_many) {
+  const u64 i = u64(blockIdx.x) * kNT + threadIdx.x;
+  if (i >= n) return;
+  const int w = a.js.w;
+  const K mask = (K(1) << w) - 1;
+  const K* ia = static_cast<const K*>(a.inner);
+  const K* ib = static_cast<const K*>(b.inner);
+  const K k = outer[i];
+  const K c0 = k >> w, c1 = k & mask;
+  u64 sa, na;
+  nested_run(a, la, u32(a.js.outer_col == 0 ? c0 : c1), w, sa, na);
+  u64 pos = kWrite ? off[i] : 0;
+  u64 kept = 0;
+  for (u64 x = 0; x < na; ++x) {
+    const K oa = ia[sa + x] & mask;
+    if (!((a.js.fa < 0 || pick(a.js.fa, c0, c1, oa) != pick(a.js.fb, c0, c1, oa)) &&
+          (a.js.ea < 0 || pick(a.js.ea, c0, c1, oa) == pick(a.js.eb, c0, c1, oa))))
+      continue;
+    const K d0 = pick(a.js.src0, c0, c1, oa), d1 = pick(a.js.src1, c0, c1, oa);
+    u64 sb, nb;
+    nested_run(b, lb, u32(b.js.outer_col == 0 ? d0 : d1), w, sb, nb);
+    for (u64 y = 0; y < nb; ++y) {
+      const K ob = ib[sb + y] & mask;
+      if (!((b.js.fa < 0 || pick(b.js.fa, d0, d1, ob) != pick(b.js.fb, d0, d1, ob)) &&
+            (b.js.ea < 0 || pick(b.js.ea, d0, d1, ob) == pick(b.js.eb, d0, d1, ob))))
+        continue;
+      if (kWrite) out[pos++] = (pick(b.js.src0, d0, d1, ob) << w) | pick(b.js.src1, d0, d1, ob);
+      else ++kept;
+    }
+  }
+  if (!kWrite) {
+    if (kept > 0xFFFFFFFFull) {
+      atomicOr(too_many, 1u);  // the counts are 32-bit: the caller fails
+      kept = 0;
+    }
+    count[i] = u32(kept);
+  }
+}
+
 u64 tiles_of(u64 n) { return (n + kTile - 1) / kTile; }
 
 }  // namespace
@@ -463,7 +540,35 @@ hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, 
   return hipGetLastError();
 }
 
+template <typename K>
+hipError_t join_nested(const K* outer, u64 n, const NestedJoin<K>& nj, u32* count, u64* off,
+                       u64* d_total, u32* too_many, void* scan_ws, K* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const u64 blocks = (n + kNT - 1) / kNT;
+  if (blocks >= (u64(1) << 31) || n >= (u64(1) << 32)) return hipErrorInvalidValue;
+  for (int q = 0; q < 2; ++q) {
+    const JoinSpec& js = nj.js[q];
+    if (!nj.inner[q] || (!nj.table[q] && !nj.lv[q].keys) || js.outer_col < 0 ||
+        js.outer_col > 1)
+      return hipErrorInvalidValue;
+  }
+  NestedSide a{nj.inner[0], nj.table[0], nj.cap[0], nj.js[0]};
+  NestedSide b{nj.inner[1], nj.table[1], nj.cap[1], nj.js[1]};
+  if (!out) {
+    nested_kernel<K, false><<<dim3(u32(blocks)), kNT, 0, s>>>(outer, n, a, nj.lv[0], b, nj.lv[1],
+                                                              count, nullptr, nullptr, too_many);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return scan_u32_u64(count, n, off, d_total, scan_ws, s);
+  }
+  nested_kernel<K, true><<<dim3(u32(blocks)), kNT, 0, s>>>(outer, n, a, nj.lv[0], b, nj.lv[1],
+                                                           nullptr, off, out, nullptr);
+  return hipGetLastError();
+}
+
 #define HL_INSTANTIATE(K)                                                                     \
+  template hipError_t join_nested<K>(const K*, u64, const NestedJoin<K>&, u32*, u64*, u64*,  \
+                                     u32*, void*, K*, hipStream_t);                           \
   template hipError_t join_probe<K>(const K*, u64, const JoinSpec&, const Slot*, u64, u32*,  \
                                     u32*, hipStream_t, LaunchTimer*);                         \
   template hipError_t join_expand_tiles<K>(const K*, u64, const u64*, const u32*, const K*,  \

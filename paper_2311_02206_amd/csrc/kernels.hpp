@@ -183,6 +183,26 @@ hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* s
 template <typename K>
 hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, hipStream_t s);
 
+// Nested evaluation of a two-join body (the paper's nested joins, kept as an
+// ablation): join q probes inner[q] through table[q] (hash) or lv[q].
+template <typename K>
+struct NestedJoin {
+  const K* inner[2];
+  const Slot* table[2];
+  u64 cap[2];
+  LearnedView<K> lv[2];
+  JoinSpec js[2];
+};
+// With out == null: counts each outer tuple's kept outputs into count[],
+// their exclusive prefix into off[] and the total into *d_total (device),
+// using scan_ws (scan_workspace_bytes(n)); an outer tuple with 2^32 or more
+// outputs sets *too_many (device, zeroed by the caller) and the results
+// are void.  With out: writes the outputs of outer tuple i at
+// out[off[i]...].
+template <typename K>
+hipError_t join_nested(const K* outer, u64 n, const NestedJoin<K>& nj, u32* count, u64* off,
+                       u64* d_total, u32* too_many, void* scan_ws, K* out, hipStream_t s);
+
 // --------------------------------------------------- fused iteration
 // One workgroup runs every rule of the stratum for a small iteration (see
 // fused.hip).  Relations are numbered 0 .. nrels-1 (the IDB relations);

@@ -30,6 +30,7 @@ HL_FLAG_LEARNED_INDEX = 0x4
 HL_FLAG_JOIN_DEDUP = 0x8
 HL_FLAG_FUSED = 0x10
 HL_FLAG_HIP_GRAPH = 0x20
+HL_FLAG_NESTED_JOINS = 0x40
 KERNELS = ("radix_hist", "radix_scatter", "unique_diff", "merge", "join_probe", "join_expand",
            "hisa_build", "learned_fit")
 PHASES = ("index_edb", "join", "sort", "diff", "merge", "index", "fused")
@@ -178,7 +179,7 @@ class Engine:
                  ebm_k: float = 8.0, load_factor: float = 0.5, budget_bytes: int = 0,
                  kernel_timing: bool = False, learned: bool = False, sort_chunk_log2: int = 0,
                  join_dedup: bool = False, fused: bool = False, hip_graph: bool = False,
-                 fused_capacity: int = 0):
+                 fused_capacity: int = 0, nested_joins: bool = False):
         L = lib()
         opt = Options()
         L.hl_options_init(ctypes.byref(opt))
@@ -188,7 +189,8 @@ class Engine:
                      (HL_FLAG_LEARNED_INDEX if learned else 0) |
                      (HL_FLAG_JOIN_DEDUP if join_dedup else 0) |
                      (HL_FLAG_FUSED if fused else 0) |
-                     (HL_FLAG_HIP_GRAPH if hip_graph else 0))
+                     (HL_FLAG_HIP_GRAPH if hip_graph else 0) |
+                     (HL_FLAG_NESTED_JOINS if nested_joins else 0))
         opt.ebm_k = ebm_k
         opt.hash_load_factor = load_factor
         opt.hbm_budget_bytes = budget_bytes
@@ -307,6 +309,7 @@ class Engine:
         return {"hash_load_factor": round(t.hash_load_factor, 3), "ebm_k": round(t.ebm_k, 3),
                 "learned": bool(t.flags & HL_FLAG_LEARNED_INDEX),
                 "join_dedup": bool(t.flags & HL_FLAG_JOIN_DEDUP),
+                "nested_joins": bool(t.flags & HL_FLAG_NESTED_JOINS),
                 "fused": bool(t.flags & (HL_FLAG_FUSED | HL_FLAG_HIP_GRAPH)),
                 "hip_graph": bool(t.flags & HL_FLAG_HIP_GRAPH), "trials": t.trials,
                 "best_seconds": t.best_seconds, "first_seconds": t.first_seconds}

@@ -406,3 +406,33 @@ def test_error_paths():
     with pytest.raises(pkg.HlError) as ei:
         gpu_eval(PROG["reach"], wl["edb"], {"Reach": 2}, budget_bytes=1 << 16)
     assert ei.value.code == pkg.hisalog.HL_E_NOMEM
+
+
+@pytest.mark.parametrize("case", ["sg_paper", "sg_tree", "sg_tree_learned", "cspa", "random"])
+def test_nested_joins_match_oracle(case):
+    """The nested evaluation of two-join bodies (the Section 5.2 ablation)
+    gives the oracle's result: same-generation (a filter on the second
+    join), the CSPA-shaped program (a three-atom rule among two-atom ones)
+    and random two- and three-atom programs."""
+    say(f"nested joins, {case}")
+    if case == "sg_paper":
+        E = np.array([[9, 0], [9, 2], [0, 3], [1, 3], [1, 4], [1, 5], [2, 5], [3, 6], [4, 7],
+                      [4, 8], [5, 8], [6, 10], [8, 11], [12, 10], [12, 11]], dtype=np.uint32)
+        check_same(PROG["sg"], {"Edge": E}, {"SG": 2}, nested_joins=True)
+    elif case.startswith("sg_tree"):
+        wl = workloads.scaled_tree(3000, seed=23)
+        check_same(PROG["sg"], wl["edb"], {"SG": 2}, nested_joins=True,
+                   learned=case.endswith("learned"))
+    elif case == "cspa":
+        cs = workloads.cspa(11)["edb"]
+        check_same(PROG["cspa_shaped"], cs, {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2},
+                   nested_joins=True)
+    else:
+        rng = np.random.default_rng(29)
+        progs = ["P(x, y) :- E(x, y).\nP(x, y) :- E(x, a), P(a, b), F(b, y), x != y.\n",
+                 "P(x, y) :- F(y, x).\nP(x, y) :- P(x, a), E(a, b), E(b, y).\n",
+                 "P(x, y) :- E(x, y).\nP(x, y) :- E(a, x), P(a, b), E(y, b).\n"]
+        for prog in progs:
+            E = rng.integers(0, 40, size=(120, 2)).astype(np.uint32)
+            F = rng.integers(0, 40, size=(60, 2)).astype(np.uint32)
+            check_same(prog, {"E": E, "F": F}, {"P": 2}, nested_joins=True)
