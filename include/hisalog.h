@@ -80,9 +80,8 @@ extern "C" {
                                variants, 2 joins per rule), eager buffer
                                management is on, and the last iteration's
                                output rate predicts that the candidates fit
-                               in LDS (8,192 64-bit or 16,384 32-bit keys
-                               on a 160 KB-LDS device); an iteration whose
-                               candidates do not fit is rerun on the
+                               in LDS (see fused_capacity); an iteration
+                               whose candidates do not fit is rerun on the
                                multi-kernel path.  Results are identical */
 #define HL_FLAG_HIP_GRAPH 0x20u /* HL_FLAG_FUSED, with each fused iteration
                                    (its launches and the copy of its counts
@@ -147,11 +146,14 @@ typedef struct hl_options {
   uint32_t sort_chunk_log2;  /* an iteration's new tuples are sorted in chunks
                                 of at most 2^sort_chunk_log2 keys (12..31;
                                 0: 31) */
-  uint32_t fused_capacity;   /* candidate keys a fused iteration holds in LDS
-                                (HL_FLAG_FUSED): a power of two from 1,024 up
-                                to what the device's LDS allows; 0: the
-                                largest that fits.  Larger is not faster
-                                per iteration; it lets more iterations fuse */
+  uint32_t fused_capacity;   /* new tuples (distinct candidates, new or
+                                already held) a fused iteration gathers per
+                                relation in LDS (HL_FLAG_FUSED): a power of
+                                two from 1,024 up to what one workgroup's
+                                LDS holds; 0: the largest that fits (16,384
+                                64-bit or 32,768 32-bit keys on a 160 KB-LDS
+                                device).  Larger is not faster per
+                                iteration; it lets more iterations fuse */
   uint32_t reserved[6];      /* must be zero */
 } hl_options;
 

@@ -447,7 +447,8 @@ struct hl_engine {
   bool fz_plans = false;           // the recursive plans qualify
   bool fz_live = false;            // device counts carry over from the last iteration
   int fz_key_bytes = 0;            // key width the LDS capacities were set for
-  u32 fz_cap_c = 0, fz_cap_t = 0;  // LDS capacities in keys
+  u32 fz_cap_c = 0, fz_cap_t = 0;  // LDS capacities in keys: a joining workgroup
+  u32 fz_cap_b = 0;                // the finishing workgroup: new tuples per iteration
   u64 fz_fail_at = ~u64(0);        // smallest total delta that overflowed in this run
   u64 last_in = 0, last_out = 0;   // last iteration: outer delta tuples, join outputs
   struct FzGraph {
@@ -1369,9 +1370,10 @@ struct hl_engine {
     return (flags & (HL_FLAG_FUSED | HL_FLAG_HIP_GRAPH)) && !(flags & HL_FLAG_NO_EBM) && fz_plans;
   }
 
-  // LDS capacities for key type K: the largest power-of-two candidate
-  // buffer (and half of it for a first join's result) that fits the
-  // device's LDS per workgroup.
+  // LDS capacities for key type K: for a joining workgroup the largest
+  // power-of-two candidate buffer (and half of it for a first join's
+  // result) that fits the device's LDS per workgroup; for the finishing
+  // workgroup, which holds only keys, the largest power of two that fits.
   template <typename K>
   void fused_setup() {
     if (fz_key_bytes == int(sizeof(K))) return;
@@ -1382,14 +1384,18 @@ struct hl_engine {
     for (u32 t = 2; t <= 16384; t <<= 1)
       if (hl::fused_lds_bytes<K>(t, t / 2) <= avail) c = t;
     if (c < 1024) fail(HL_E_UNSUPPORTED, "fused iterations need more LDS per workgroup");
+    u32 b = c;
+    while (b < 32768 && u64(2 * b) * sizeof(K) <= avail) b *= 2;
     if (fused_capacity) {
-      if (fused_capacity > c)
+      if (fused_capacity > b)
         fail(HL_E_UNSUPPORTED, "fused_capacity exceeds the LDS of one workgroup");
-      c = fused_capacity;
+      b = fused_capacity;
+      c = std::min(c, b);
     }
-    HIPCK(hl::fused_prepare<K>(c, c / 2));
+    HIPCK(hl::fused_prepare<K>(c, c / 2, b));
     fz_cap_c = c;
     fz_cap_t = c / 2;
+    fz_cap_b = b;
     fz_key_bytes = int(sizeof(K));
   }
 
@@ -1456,7 +1462,7 @@ struct hl_engine {
   bool fused_next(u64 sum_delta) const {
     if (!fused_on() || sum_delta == 0 || sum_delta >= fz_fail_at) return false;
     const double rate = last_in ? double(last_out) / double(last_in) : 1.0;
-    return double(sum_delta) * std::max(rate, 1.0) <= 0.75 * double(fz_cap_c);
+    return double(sum_delta) * std::max(rate, 1.0) <= 0.75 * double(fz_cap_b);
   }
 
   // One iteration of the recursive stratum as a fused launch plus
@@ -1473,7 +1479,7 @@ struct hl_engine {
         slot[k] = int(idbs.size());
         idbs.push_back(k);
       }
-    const u64 C = fz_cap_c;
+    const u64 C = fz_cap_b;  // most new tuples one relation gets per iteration
     hl::FusedIteration<K> it{};
     it.nrels = int(idbs.size());
     it.w = w;
@@ -1550,7 +1556,7 @@ struct hl_engine {
                            stream));
     }
     auto enqueue = [&] {
-      HIPCK(hl::fused_iteration<K>(it, fz_cap_c, fz_cap_t, fz_scratch.p, stream));
+      HIPCK(hl::fused_iteration<K>(it, fz_cap_c, fz_cap_t, fz_cap_b, fz_scratch.p, stream));
       for (size_t r = 0; r < idbs.size(); ++r) {
         Relation& R = rels[idbs[r]];
         HIPCK(hl::fused_merge<K>(kp<K>(R.fz_tail[0]), kp<K>(R.fz_next), d_fz, int(r), max_out[r],
@@ -1576,6 +1582,7 @@ struct hl_engine {
         add(&max_out[r], sizeof(u64));
       }
       add(&fz_cap_c, sizeof(fz_cap_c));
+      add(&fz_cap_b, sizeof(fz_cap_b));
       add(&fz_scratch.p, sizeof(fz_scratch.p));
       FzGraph* g = nullptr;
       for (auto& c : fz_graphs)

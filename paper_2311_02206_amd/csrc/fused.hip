@@ -354,9 +354,9 @@ __device__ u32 fz_count_distinct(const K* a, u32 n, u32* wsum) {
 // relation gets a delta.
 template <typename K>
 __global__ __launch_bounds__(kFNT) void fused_finish_kernel(FusedIteration<K> it, u32 cap_c,
-                                                            u32 G, FusedScratch<K> sc) {
+                                                            u32 cap_b, u32 G, FusedScratch<K> sc) {
   extern __shared__ __align__(16) unsigned char s_dyn[];
-  K* buf = reinterpret_cast<K*>(s_dyn);  // cap_c keys
+  K* buf = reinterpret_cast<K*>(s_dyn);  // cap_b keys (runs are cap_c apart)
   __shared__ u32 s_wsum[kFWaves];
   __shared__ u32 s_off[kFusedGroups + 1];
   __shared__ u64 s_sum[2][kFWaves];
@@ -373,7 +373,7 @@ __global__ __launch_bounds__(kFNT) void fused_finish_kernel(FusedIteration<K> it
       raw = block_sum<kFNT>(rg, s_sum[1]);
     }
     u32 n = fz_offsets(sc.counts, h, G, 0, s_off, s_wsum);
-    if (n > cap_c) goto overflow;
+    if (n > cap_b) goto overflow;
     fz_gather(sc.surv, h, G, cap_c, s_off, buf);
     u32 p2 = 2;
     while (p2 < n) p2 <<= 1;
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(kFNT) void fused_finish_kernel(FusedIteration<K> it
     }
     __syncthreads();
     n = fz_offsets(sc.counts, h, G, 1, s_off, s_wsum);
-    if (n > cap_c) goto overflow;
+    if (n > cap_b) goto overflow;
     fz_gather(sc.pres, h, G, cap_c, s_off, buf);
     p2 = 2;
     while (p2 < n) p2 <<= 1;
@@ -519,23 +519,24 @@ u64 fused_scratch_bytes(u32 cap_c, int nrels) {
 }
 
 template <typename K>
-hipError_t fused_prepare(u32 cap_c, u32 cap_t) {
+hipError_t fused_prepare(u32 cap_c, u32 cap_t, u32 cap_b) {
   hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_join_kernel<K>),
                                      hipFuncAttributeMaxDynamicSharedMemorySize,
                                      int(fused_lds_bytes<K>(cap_c, cap_t)));
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute(reinterpret_cast<const void*>(&fused_finish_kernel<K>),
                              hipFuncAttributeMaxDynamicSharedMemorySize,
-                             int(u64(cap_c) * sizeof(K)));
+                             int(u64(cap_b) * sizeof(K)));
 }
 
 u64 fused_merge_tiles(u64 n) { return (n + kFMTile - 1) / kFMTile; }
 
 template <typename K>
-hipError_t fused_iteration(const FusedIteration<K>& it, u32 cap_c, u32 cap_t, void* scratch,
-                           hipStream_t s) {
+hipError_t fused_iteration(const FusedIteration<K>& it, u32 cap_c, u32 cap_t, u32 cap_b,
+                           void* scratch, hipStream_t s) {
   if (it.nrels < 1 || it.nrels > kFusedMaxRels || it.nplans < 0 || it.nplans > kFusedMaxPlans ||
-      cap_c < 2 || (cap_c & (cap_c - 1)) != 0 || !it.counts || !scratch)
+      cap_c < 2 || (cap_c & (cap_c - 1)) != 0 || cap_b < 2 || (cap_b & (cap_b - 1)) != 0 ||
+      !it.counts || !scratch)
     return hipErrorInvalidValue;
   for (int p = 0; p < it.nplans; ++p) {
     const FusedPlan<K>& pl = it.plans[p];
@@ -555,7 +556,8 @@ hipError_t fused_iteration(const FusedIteration<K>& it, u32 cap_c, u32 cap_t, vo
                                                                                    cap_t, sc);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  fused_finish_kernel<K><<<1, kFNT, u64(cap_c) * sizeof(K), s>>>(it, cap_c, kFusedGroups, sc);
+  fused_finish_kernel<K><<<1, kFNT, u64(cap_b) * sizeof(K), s>>>(it, cap_c, cap_b, kFusedGroups,
+                                                                   sc);
   return hipGetLastError();
 }
 
@@ -582,8 +584,8 @@ hipError_t fused_advance(u64* counts, int nrels, hipStream_t s) {
 #define HL_INSTANTIATE(K)                                                                      \
   template u64 fused_lds_bytes<K>(u32, u32);                                                   \
   template u64 fused_scratch_bytes<K>(u32, int);                                               \
-  template hipError_t fused_prepare<K>(u32, u32);                                              \
-  template hipError_t fused_iteration<K>(const FusedIteration<K>&, u32, u32, void*,            \
+  template hipError_t fused_prepare<K>(u32, u32, u32);                                         \
+  template hipError_t fused_iteration<K>(const FusedIteration<K>&, u32, u32, u32, void*,       \
                                          hipStream_t);                                         \
   template hipError_t fused_merge<K>(const K*, const K*, const u64*, int, u64, u64*, K*,       \
                                      hipStream_t);

@@ -247,7 +247,7 @@ struct FusedIteration {
   const K* delta_in[kFusedMaxRels];
   const K* full[kFusedMaxRels];
   const K* tail[kFusedMaxRels];
-  K* delta_out[kFusedMaxRels];  // room for cap_c keys each
+  K* delta_out[kFusedMaxRels];  // room for cap_b keys each
   u64* counts;                  // kFusedCountWords words
 };
 
@@ -264,7 +264,9 @@ struct FusedScratch {
 };
 
 // LDS of one phase-A workgroup: cap_c candidate keys (a power of two),
-// cap_t keys of a first join's result, and per-thread staging.
+// cap_t keys of a first join's result, and per-thread staging.  The
+// finishing workgroup holds cap_b keys (a power of two): the new tuples of
+// one relation in one iteration.
 template <typename K>
 u64 fused_lds_bytes(u32 cap_c, u32 cap_t);
 // Device scratch of fused_iteration for nrels relations.
@@ -272,10 +274,10 @@ template <typename K>
 u64 fused_scratch_bytes(u32 cap_c, int nrels);
 // Allows the launches' dynamic LDS sizes (call once before fused_iteration).
 template <typename K>
-hipError_t fused_prepare(u32 cap_c, u32 cap_t);
+hipError_t fused_prepare(u32 cap_c, u32 cap_t, u32 cap_b);
 template <typename K>
-hipError_t fused_iteration(const FusedIteration<K>& it, u32 cap_c, u32 cap_t, void* scratch,
-                           hipStream_t s);
+hipError_t fused_iteration(const FusedIteration<K>& it, u32 cap_c, u32 cap_t, u32 cap_b,
+                           void* scratch, hipStream_t s);
 // out = merge(tail, new delta) of relation r, sizes from counts[r][6] and
 // counts[r][2]; the grid covers max_out outputs, and `parts` holds
 // fused_merge_tiles(max_out) + 1 words.  Nothing runs after an overflow or
