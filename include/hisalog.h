@@ -154,7 +154,11 @@ typedef struct hl_options {
                                 64-bit or 32,768 32-bit keys on a 160 KB-LDS
                                 device).  Larger is not faster per
                                 iteration; it lets more iterations fuse */
-  uint32_t reserved[6];      /* must be zero */
+  uint32_t expand_tile;      /* join outputs (and merged outer tuples) one
+                                expand workgroup handles: 1024, 2048 or
+                                4096 (0: 2048); hl_autotune measures all
+                                three */
+  uint32_t reserved[5];      /* must be zero */
 } hl_options;
 
 typedef struct hl_stats {
@@ -278,12 +282,15 @@ typedef struct hl_tuning {
   double best_seconds;     /* fixpoint time under the chosen setting */
   double first_seconds;    /* fixpoint time under the engine's settings
                               before tuning */
+  uint32_t expand_tile;    /* the chosen hl_options.expand_tile */
+  uint32_t reserved;
 } hl_tuning;
 
 /* Tunes the engine for the loaded program and data by measurement.  The
  * settings are searched one dimension at a time, starting from the
  * engine's own: how join inners are probed (HISA hash at load factor 0.5,
- * at 0.8, or the learned position index), the eager buffer growth factor
+ * at 0.8, or the learned position index), the join expand tile (1024,
+ * 2048 or 4096 outputs per workgroup), the eager buffer growth factor
  * (1.5 or 8), in-tile dedup of join outputs (off or on), nested
  * evaluation of two-join bodies (off or on, where a rule has one) and,
  * where the recursive rules qualify, fused small iterations (off, on, or

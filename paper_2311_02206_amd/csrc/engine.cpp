@@ -416,6 +416,7 @@ struct hl_engine {
   float load_factor = 0.5f;
   int sort_chunk_log2 = 31;
   u32 fused_capacity = 0;  // 0: the largest that fits
+  int join_items = 8;      // join expand outputs per thread (4, 8, 16)
   Memory mem;
   std::string err;
 
@@ -1012,11 +1013,12 @@ struct hl_engine {
         // One join's outputs exceed one sort: expand a range of tiles at a
         // time (at most `cap` outputs) and absorb each range into the head
         // relation's pending delta, so memory stays bounded by the range.
-        const u64 nt = hl::join_tiles(n, total);
-        reserve_grow(join_parts, hl::join_parts(n, total) * sizeof(u64));
+        const u64 nt = hl::join_tiles(n, total, join_items);
+        reserve_grow(join_parts, hl::join_parts(n, total, join_items) * sizeof(u64));
         u64* parts = static_cast<u64*>(join_parts.p);
-        HIPCK(hl::join_partition(static_cast<u64*>(join_off.p), n, total, parts, stream));
-        const u64 tile_out = hl::join_tile_outputs();
+        HIPCK(hl::join_partition(static_cast<u64*>(join_off.p), n, total, parts, stream,
+                                 join_items));
+        const u64 tile_out = hl::join_tile_outputs(join_items);
         const u64 per = std::max<u64>(1, cap / tile_out);
         reserve_grow(jchunk, per * tile_out * sizeof(K));
         const bool filt = js.fa >= 0 || js.ea >= 0 || js.dd;
@@ -1028,7 +1030,8 @@ struct hl_engine {
           }
           HIPCK(hl::join_expand_tiles<K>(cur, n, static_cast<u64*>(join_off.p),
                                          static_cast<u32*>(join_start.p), inner, total, js, parts,
-                                         t0, tiles, kp<K>(jchunk), d_cursor, stream, kt()));
+                                         t0, tiles, kp<K>(jchunk), d_cursor, stream, kt(),
+                                         join_items));
           u64 m;
           if (filt) {
             HIPCK(hipMemcpyAsync(h_small, d_cursor, sizeof(u64), hipMemcpyDeviceToHost, stream));
@@ -1066,11 +1069,11 @@ struct hl_engine {
         h_small[0] = base;
         HIPCK(hipMemcpyAsync(d_cursor, h_small, sizeof(u64), hipMemcpyHostToDevice, stream));
       }
-      reserve_grow(join_parts, hl::join_parts(n, total) * sizeof(u64));
+      reserve_grow(join_parts, hl::join_parts(n, total, join_items) * sizeof(u64));
       HIPCK(hl::join_expand<K>(cur, n, static_cast<u64*>(join_off.p),
                                static_cast<u32*>(join_start.p), inner, total, js,
                                static_cast<u64*>(join_parts.p), filtered ? out : out + base,
-                               d_cursor, stream, kt()));
+                               d_cursor, stream, kt(), join_items));
       u64 produced = total;
       if (filtered) {
         HIPCK(hipMemcpyAsync(h_small, d_cursor, sizeof(u64), hipMemcpyDeviceToHost, stream));
@@ -1691,6 +1694,7 @@ struct hl_engine {
   struct Setting {
     float lf, k;
     u32 fl;  // kTunedFlags bits
+    int items;  // join expand outputs per thread
   };
   static constexpr u32 kTunedFlags = HL_FLAG_LEARNED_INDEX | HL_FLAG_JOIN_DEDUP | HL_FLAG_FUSED |
                                      HL_FLAG_HIP_GRAPH | HL_FLAG_NESTED_JOINS;
@@ -1699,6 +1703,7 @@ struct hl_engine {
     load_factor = t.lf;
     ebm_k = t.k;
     flags = (flags & ~kTunedFlags) | t.fl;
+    join_items = t.items;
   }
 
   // Fastest of `reps` timed runs after a warm-up; +inf if the device ran
@@ -1725,7 +1730,7 @@ struct hl_engine {
 
   void autotune(u32 reps, hl_tuning* out) {
     if (rules.empty()) fail(HL_E_STATE, "no program");
-    Setting best{load_factor, ebm_k, flags & kTunedFlags};
+    Setting best{load_factor, ebm_k, flags & kTunedFlags, join_items};
     std::vector<std::vector<u64>> ref, got;
     u32 trials = 1;
     double best_t = trial(best, reps, &ref);
@@ -1748,10 +1753,20 @@ struct hl_engine {
     };
     // 1. how join inners are probed
     const Setting base = best;
-    for (const Setting& t : {Setting{0.5f, base.k, base.fl & ~u32(HL_FLAG_LEARNED_INDEX)},
-                             Setting{0.8f, base.k, base.fl & ~u32(HL_FLAG_LEARNED_INDEX)},
-                             Setting{base.lf, base.k, base.fl | HL_FLAG_LEARNED_INDEX}})
+    for (const Setting& t :
+         {Setting{0.5f, base.k, base.fl & ~u32(HL_FLAG_LEARNED_INDEX), base.items},
+          Setting{0.8f, base.k, base.fl & ~u32(HL_FLAG_LEARNED_INDEX), base.items},
+          Setting{base.lf, base.k, base.fl | HL_FLAG_LEARNED_INDEX, base.items}})
       if (t.lf != base.lf || t.fl != base.fl) consider(t);
+    // join expand tile: outputs per thread
+    {
+      const Setting b = best;
+      for (int it : {4, 8, 16}) {
+        Setting t = b;
+        t.items = it;
+        if (it != b.items) consider(t);
+      }
+    }
     // 2. eager buffer growth factor
     {
       Setting t = best;
@@ -1795,6 +1810,7 @@ struct hl_engine {
       out->ebm_k = best.k;
       out->flags = best.fl;
       out->trials = trials;
+      out->expand_tile = u32(256 * best.items);
       out->best_seconds = best_t;
       out->first_seconds = first_t;
     }
@@ -1983,6 +1999,9 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   if (o.fused_capacity != 0 &&
       (o.fused_capacity < 1024 || (o.fused_capacity & (o.fused_capacity - 1)) != 0))
     return HL_E_INVALID;
+  if (o.expand_tile != 0 && o.expand_tile != 1024 && o.expand_tile != 2048 &&
+      o.expand_tile != 4096)
+    return HL_E_INVALID;
   if (o.device == -1) {
     // planning-only engine: declarations and programs, no device work
     hl_engine* e = new (std::nothrow) hl_engine();
@@ -2004,6 +2023,7 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   e->load_factor = o.hash_load_factor;
   e->sort_chunk_log2 = o.sort_chunk_log2 ? int(o.sort_chunk_log2) : 31;
   e->fused_capacity = o.fused_capacity;
+  e->join_items = o.expand_tile ? int(o.expand_tile / 256) : 8;
   int rc = guard(e, [&] {
     if (o.stream) {
       e->stream = static_cast<hipStream_t>(o.stream);

@@ -152,10 +152,11 @@ __device__ __forceinline__ u64 lbs_path(const u64* off, u64 na, u64 nb, u64 diag
   return lo;
 }
 
-__global__ void lbs_partition_kernel(const u64* off, u64 na, u64 nb, u64* parts, u64 nparts) {
+__global__ void lbs_partition_kernel(const u64* off, u64 na, u64 nb, u64* parts, u64 nparts,
+                                     u64 tile) {
   const u64 t = u64(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= nparts) return;
-  u64 diag = t * kTile;
+  u64 diag = t * tile;
   if (diag > na + nb) diag = na + nb;
   parts[t] = lbs_path(off, na, nb, diag);
 }
@@ -190,19 +191,18 @@ struct Compactor {
   }
 };
 
-// Outputs of one expand tile, deduplicated in an LDS hash set of
-// kDedupSlots keys with linear probing.  A tile emits at most kTile keys, so
-// the set is at most half full and every insertion finds its key or an
-// empty slot.  The all-ones key marks an empty slot; that one key value is
-// never dropped here (the sort and unique that follow remove its repeats).
-constexpr u32 kDedupSlots = 2 * u32(kTile);
-
-template <typename K>
+// Outputs of one expand tile, deduplicated in an LDS hash set of SLOTS
+// keys (twice the tile) with linear probing.  A tile emits at most half
+// that many keys, so the set is at most half full and every insertion finds
+// its key or an empty slot.  The all-ones key marks an empty slot; that one
+// key value is never dropped here (the sort and unique that follow remove
+// its repeats).
+template <u32 SLOTS, typename K>
 __device__ __forceinline__ bool first_in_tile(K* set, K v) {
   const K empty = ~K(0);
   if (v == empty) return true;
-  u32 h = mix32(u32(v) ^ u32(u64(v) >> 32)) & (kDedupSlots - 1);
-  for (u32 probe = 0; probe < kDedupSlots; ++probe) {
+  u32 h = mix32(u32(v) ^ u32(u64(v) >> 32)) & (SLOTS - 1);
+  for (u32 probe = 0; probe < SLOTS; ++probe) {
     K prev;
     if constexpr (sizeof(K) == 8)
       prev = K(atomicCAS(reinterpret_cast<unsigned long long*>(set + h),
@@ -212,16 +212,20 @@ __device__ __forceinline__ bool first_in_tile(K* set, K v) {
                          (unsigned int)v));
     if (prev == empty) return true;
     if (prev == v) return false;
-    h = (h + 1) & (kDedupSlots - 1);
+    h = (h + 1) & (SLOTS - 1);
   }
   return true;
 }
 
-template <typename K>
+// ITEMS outputs per thread: a tile of kNT * ITEMS outputs and outer tuples.
+template <typename K, int ITEMS>
 __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer, const u64* off,
                                                      const u32* start, const K* inner,
                                                      u64 total, JoinSpec js, const u64* parts,
                                                      u64 tile0, K* out, u64* cursor) {
+  constexpr u64 kTile = u64(kNT) * ITEMS;
+  constexpr int kItems = ITEMS;
+  constexpr u32 kDedupSlots = 2 * u32(kTile);
   // Offsets of the tile's outer tuples relative to its first output b0: the
   // merge path puts every one of them in [b0, b1], so 32 bits hold them.
   // s_pool holds them and the run starts; after the block scan below (once
@@ -319,7 +323,7 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
 #pragma unroll
     for (int r = 0; r < kItems; ++r)
       if ((keep >> r) & 1u)
-        if (!first_in_tile(dset, v[r])) keep &= ~(1u << r);
+        if (!first_in_tile<kDedupSlots>(dset, v[r])) keep &= ~(1u << r);
   }
   // one block scan places every survivor of the tile in LDS, then one
   // atomic claims the tile's output range
@@ -479,36 +483,52 @@ hipError_t join_probe_learned(const K* outer, u64 n, const JoinSpec& js,
   return hipGetLastError();
 }
 
-u64 join_parts(u64 n_outer, u64 total) { return tiles_of(n_outer + total) + 1; }
+bool join_items_ok(int items) { return items == 4 || items == 8 || items == 16; }
 
-hipError_t join_partition(const u64* off, u64 n_outer, u64 total, u64* parts, hipStream_t s) {
-  if (total == 0) return hipSuccess;
-  if (n_outer >= (u64(1) << 32)) return hipErrorInvalidValue;
-  const u64 nt = tiles_of(n_outer + total);
-  if (nt >= (u64(1) << 31)) return hipErrorInvalidValue;
-  const u64 nparts = nt + 1;
-  lbs_partition_kernel<<<dim3(u32((nparts + 255) / 256)), 256, 0, s>>>(off, n_outer, total,
-                                                                       parts, nparts);
-  return hipGetLastError();
+u64 join_tile_outputs(int items) { return u64(kNT) * u64(items); }
+
+u64 join_tiles(u64 n_outer, u64 total, int items) {
+  const u64 t = join_tile_outputs(items);
+  return (n_outer + total + t - 1) / t;
 }
 
-u64 join_tiles(u64 n_outer, u64 total) { return tiles_of(n_outer + total); }
+u64 join_parts(u64 n_outer, u64 total, int items) { return join_tiles(n_outer, total, items) + 1; }
 
-u64 join_tile_outputs() { return kTile; }
+hipError_t join_partition(const u64* off, u64 n_outer, u64 total, u64* parts, hipStream_t s,
+                          int items) {
+  if (total == 0) return hipSuccess;
+  if (n_outer >= (u64(1) << 32) || !join_items_ok(items)) return hipErrorInvalidValue;
+  const u64 nt = join_tiles(n_outer, total, items);
+  if (nt >= (u64(1) << 31)) return hipErrorInvalidValue;
+  const u64 nparts = nt + 1;
+  lbs_partition_kernel<<<dim3(u32((nparts + 255) / 256)), 256, 0, s>>>(
+      off, n_outer, total, parts, nparts, join_tile_outputs(items));
+  return hipGetLastError();
+}
 
 template <typename K>
 hipError_t join_expand_tiles(const K* outer, u64 n_outer, const u64* off, const u32* start,
                              const K* inner, u64 total, const JoinSpec& js, const u64* parts,
                              u64 tile0, u64 tiles, K* out, u64* cursor, hipStream_t s,
-                             LaunchTimer* timer) {
+                             LaunchTimer* timer, int items) {
   if (total == 0 || tiles == 0) return hipSuccess;
-  const u64 nt = tiles_of(n_outer + total);
+  if (!join_items_ok(items)) return hipErrorInvalidValue;
+  const u64 nt = join_tiles(n_outer, total, items);
   if (n_outer >= (u64(1) << 32) || tile0 + tiles > nt || tiles >= (u64(1) << 31))
     return hipErrorInvalidValue;
   if (timer) timer->begin(K_JOIN_EXPAND, s);
-  const size_t dyn = js.dd ? kDedupSlots * sizeof(K) : 0;
-  expand_kernel<K><<<dim3(u32(tiles)), kNT, dyn, s>>>(outer, n_outer, off, start, inner, total,
-                                                      js, parts, tile0, out, cursor);
+  // the dedup set (2 slots per tile output) lives in dynamic LDS
+  const size_t dyn = js.dd ? 2 * join_tile_outputs(items) * sizeof(K) : 0;
+  const dim3 grid = dim3(u32(tiles));
+  if (items == 4)
+    expand_kernel<K, 4><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, js,
+                                               parts, tile0, out, cursor);
+  else if (items == 16)
+    expand_kernel<K, 16><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, js,
+                                                parts, tile0, out, cursor);
+  else
+    expand_kernel<K, 8><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, js,
+                                               parts, tile0, out, cursor);
   // by definition: each inner tuple of a matched run read once, each output
   // written once, each outer tuple with its offset and run start read once
   // (apportioned to the launch's share of the tiles)
@@ -524,11 +544,11 @@ hipError_t join_expand_tiles(const K* outer, u64 n_outer, const u64* off, const 
 template <typename K>
 hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* start,
                        const K* inner, u64 total, const JoinSpec& js, u64* parts, K* out,
-                       u64* cursor, hipStream_t s, LaunchTimer* timer) {
-  hipError_t e = join_partition(off, n_outer, total, parts, s);
+                       u64* cursor, hipStream_t s, LaunchTimer* timer, int items) {
+  hipError_t e = join_partition(off, n_outer, total, parts, s, items);
   if (e != hipSuccess || total == 0) return e;
   return join_expand_tiles<K>(outer, n_outer, off, start, inner, total, js, parts, 0,
-                              tiles_of(n_outer + total), out, cursor, s, timer);
+                              join_tiles(n_outer, total, items), out, cursor, s, timer, items);
 }
 
 template <typename K>
@@ -573,10 +593,10 @@ hipError_t join_nested(const K* outer, u64 n, const NestedJoin<K>& nj, u32* coun
                                     u32*, hipStream_t, LaunchTimer*);                         \
   template hipError_t join_expand_tiles<K>(const K*, u64, const u64*, const u32*, const K*,  \
                                            u64, const JoinSpec&, const u64*, u64, u64, K*,   \
-                                           u64*, hipStream_t, LaunchTimer*);                 \
+                                           u64*, hipStream_t, LaunchTimer*, int);            \
   template hipError_t join_expand<K>(const K*, u64, const u64*, const u32*, const K*, u64,  \
                                      const JoinSpec&, u64*, K*, u64*, hipStream_t,            \
-                                     LaunchTimer*);                                           \
+                                     LaunchTimer*, int);                                      \
   template hipError_t project<K>(const K*, u64, const JoinSpec&, K*, u64*, hipStream_t);   \
   template hipError_t join_probe_learned<K>(const K*, u64, const JoinSpec&,                  \
                                             const LearnedView<K>&, u32*, u32*, hipStream_t,  \

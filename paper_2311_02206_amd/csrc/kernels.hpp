@@ -157,11 +157,16 @@ template <typename K>
 hipError_t join_probe_learned(const K* outer, u64 n, const JoinSpec& js,
                               const LearnedView<K>& lv, u32* start, u32* len, hipStream_t s,
                               LaunchTimer* timer = nullptr);
-u64 join_parts(u64 n_outer, u64 total);  // entries of the partition array
-u64 join_tiles(u64 n_outer, u64 total);  // expand tiles (join_parts - 1)
-u64 join_tile_outputs();                 // most outputs one expand tile emits
+// The expand gives each thread `items` outputs (4, 8 or 16): tiles of
+// 256 * items merged outer tuples and outputs per workgroup.  Every call of
+// one join must use the same items.
+bool join_items_ok(int items);
+u64 join_parts(u64 n_outer, u64 total, int items = 8);  // entries of the partition array
+u64 join_tiles(u64 n_outer, u64 total, int items = 8);  // expand tiles (join_parts - 1)
+u64 join_tile_outputs(int items = 8);                   // most outputs one tile emits
 // Merge-path partition of the expand's tiles (parts: join_parts entries).
-hipError_t join_partition(const u64* off, u64 n_outer, u64 total, u64* parts, hipStream_t s);
+hipError_t join_partition(const u64* off, u64 n_outer, u64 total, u64* parts, hipStream_t s,
+                          int items = 8);
 // Expands tiles tile0 .. tile0 + tiles - 1 only (parts from join_partition).
 // Unfiltered outputs go to out[j - j0], j0 the first output index of tile0;
 // filtered ones (or with js.dd) are appended at *cursor.
@@ -169,16 +174,16 @@ template <typename K>
 hipError_t join_expand_tiles(const K* outer, u64 n_outer, const u64* off, const u32* start,
                              const K* inner, u64 total, const JoinSpec& js, const u64* parts,
                              u64 tile0, u64 tiles, K* out, u64* cursor, hipStream_t s,
-                             LaunchTimer* timer = nullptr);
+                             LaunchTimer* timer = nullptr, int items = 8);
 // Expands every (outer, inner run) pair.  Without a filter, output j goes
 // to out[j]; with one, survivors are appended at *cursor (device, u64).
-// With js.dd, an output equal to an earlier output of the same tile (2,048
+// With js.dd, an output equal to an earlier output of the same tile (its
 // merged outer and output slots) is dropped as well, and the rest are
 // appended at *cursor: the result is the same set with fewer duplicates.
 template <typename K>
 hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* start,
                        const K* inner, u64 total, const JoinSpec& js, u64* parts, K* out,
-                       u64* cursor, hipStream_t s, LaunchTimer* timer = nullptr);
+                       u64* cursor, hipStream_t s, LaunchTimer* timer = nullptr, int items = 8);
 // A rule body of one atom: projects (and filters) every outer pair.
 template <typename K>
 hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, hipStream_t s);

@@ -57,7 +57,8 @@ class Options(ctypes.Structure):
         ("arena_bytes", ctypes.c_uint64), ("hbm_budget_bytes", ctypes.c_uint64),
         ("stream", ctypes.c_void_p), ("ebm_k", ctypes.c_float),
         ("hash_load_factor", ctypes.c_float), ("sort_chunk_log2", ctypes.c_uint32),
-        ("fused_capacity", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 6),
+        ("fused_capacity", ctypes.c_uint32), ("expand_tile", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32 * 5),
     ]
 
 
@@ -84,6 +85,7 @@ class Tuning(ctypes.Structure):
         ("hash_load_factor", ctypes.c_float), ("ebm_k", ctypes.c_float),
         ("flags", ctypes.c_uint32), ("trials", ctypes.c_uint32),
         ("best_seconds", ctypes.c_double), ("first_seconds", ctypes.c_double),
+        ("expand_tile", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -179,7 +181,7 @@ class Engine:
                  ebm_k: float = 8.0, load_factor: float = 0.5, budget_bytes: int = 0,
                  kernel_timing: bool = False, learned: bool = False, sort_chunk_log2: int = 0,
                  join_dedup: bool = False, fused: bool = False, hip_graph: bool = False,
-                 fused_capacity: int = 0, nested_joins: bool = False):
+                 fused_capacity: int = 0, nested_joins: bool = False, expand_tile: int = 0):
         L = lib()
         opt = Options()
         L.hl_options_init(ctypes.byref(opt))
@@ -196,6 +198,7 @@ class Engine:
         opt.hbm_budget_bytes = budget_bytes
         opt.sort_chunk_log2 = sort_chunk_log2
         opt.fused_capacity = fused_capacity
+        opt.expand_tile = expand_tile
         self._arena = arena  # keep the caller's tensor alive
         if arena is not None:
             opt.arena = _ptr(arena)
@@ -311,7 +314,8 @@ class Engine:
                 "join_dedup": bool(t.flags & HL_FLAG_JOIN_DEDUP),
                 "nested_joins": bool(t.flags & HL_FLAG_NESTED_JOINS),
                 "fused": bool(t.flags & (HL_FLAG_FUSED | HL_FLAG_HIP_GRAPH)),
-                "hip_graph": bool(t.flags & HL_FLAG_HIP_GRAPH), "trials": t.trials,
+                "hip_graph": bool(t.flags & HL_FLAG_HIP_GRAPH), "expand_tile": t.expand_tile,
+                "trials": t.trials,
                 "best_seconds": t.best_seconds, "first_seconds": t.first_seconds}
 
     def count(self, name: str) -> int:

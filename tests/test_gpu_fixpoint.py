@@ -436,3 +436,19 @@ def test_nested_joins_match_oracle(case):
             E = rng.integers(0, 40, size=(120, 2)).astype(np.uint32)
             F = rng.integers(0, 40, size=(60, 2)).astype(np.uint32)
             check_same(prog, {"E": E, "F": F}, {"P": 2}, nested_joins=True)
+
+
+@pytest.mark.parametrize("tile", [1024, 4096])
+def test_expand_tiles_match_oracle(tile):
+    """Join expand tiles of 1,024 and 4,096 outputs (2,048 is the default
+    everywhere else): plain, with in-tile dedup (its LDS set scales with the
+    tile), and with joins expanded a range of tiles at a time."""
+    say(f"expand tile {tile}")
+    wl = workloads.scaled_rmat(12, 12_000, seed=0xC2A)
+    check_same(PROG["reach"], wl["edb"], {"Reach": 2}, expand_tile=tile)
+    check_same(PROG["reach"], wl["edb"], {"Reach": 2}, expand_tile=tile, join_dedup=True)
+    tr = workloads.scaled_tree(2000, seed=31)
+    check_same(PROG["sg"], tr["edb"], {"SG": 2}, expand_tile=tile, sort_chunk_log2=12)
+    cs = workloads.cspa(11)["edb"]
+    check_same(PROG["cspa_shaped"], cs, {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2},
+               expand_tile=tile, join_dedup=True)
