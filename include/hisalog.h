@@ -17,8 +17,9 @@
  *   - Return value: HL_OK (0) or a negative HL_E_* code; no call aborts or
  *     throws.  hl_last_error(engine) describes the most recent failure.
  *   - Relation tuples are uint32 columns; host and device row buffers are
- *     row-major n x arity.  This build supports arity 2 (binary relations);
- *     other arities are rejected with HL_E_UNSUPPORTED.
+ *     row-major n x arity.  Arity 1 and 2 are supported (a unary tuple is
+ *     stored as the pair (x, 0)); other arities are rejected with
+ *     HL_E_UNSUPPORTED.
  *   - One engine is used by one host thread at a time.  Device work is
  *     enqueued on the engine's stream; calls that return host-visible
  *     results synchronise that stream before returning.
@@ -206,9 +207,10 @@ int hl_create(const hl_options* opt, hl_engine** out);
  * arena or stream).  NULL is ignored. */
 void hl_destroy(hl_engine* e);
 
-/* Declares relation `name` (identifier, at most 63 bytes) of `arity` columns,
- * extensional (is_edb != 0: loaded with hl_load*) or intensional (derived by
- * rules).  Before hl_program.  Duplicate names: HL_E_INVALID. */
+/* Declares relation `name` (identifier, at most 63 bytes) of `arity` columns
+ * (1 or 2; others HL_E_UNSUPPORTED), extensional (is_edb != 0: loaded with
+ * hl_load*) or intensional (derived by rules).  Before hl_program.
+ * Duplicate names: HL_E_INVALID. */
 int hl_declare(hl_engine* e, const char* name, uint32_t arity, int32_t is_edb);
 
 /* Appends n_rows host rows (row-major n x arity uint32) to EDB relation

@@ -273,6 +273,10 @@ class EventTimer : public hl::LaunchTimer {
 
 // ------------------------------------------------------------------ program
 
+// The second column of a unary relation holds the constant 0: its atoms
+// take this id there, which no variable has.
+constexpr int kZeroVar = -2;
+
 struct Atom {
   int rel = -1;
   int arg[2] = {-1, -1};  // variable ids; wildcards get fresh ids
@@ -580,6 +584,7 @@ struct hl_engine {
       break;
     }
     if (k != rels[a.rel].arity) fail(HL_E_INVALID, "arity mismatch for " + name);
+    if (k == 1) a.arg[1] = kZeroVar;
     return a;
   }
 
@@ -610,7 +615,8 @@ struct hl_engine {
       std::set<int> bodyvars;
       for (auto& a : r.body) bodyvars.insert({a.arg[0], a.arg[1]});
       for (int v : r.head.arg)
-        if (!bodyvars.count(v)) fail(HL_E_INVALID, "head variable not bound in the body");
+        if (v != kZeroVar && !bodyvars.count(v))
+          fail(HL_E_INVALID, "head variable not bound in the body");
       for (auto& f : filters) {
         auto a = vars.find(f.first), b = vars.find(f.second);
         if (a == vars.end() || b == vars.end() || !bodyvars.count(a->second) ||
@@ -648,6 +654,7 @@ struct hl_engine {
       if (j != first) remaining.push_back(j);
     std::vector<bool> applied(r.neq.size(), false);
     auto src_of = [&](int v, const int* avail, int navail) {
+      if (v == kZeroVar) return 3;  // a unary head's constant column
       for (int k = 0; k < navail; ++k)
         if (avail[k] == v) return k;
       return -1;
@@ -664,7 +671,8 @@ struct hl_engine {
         applied[f] = true;
       }
     };
-    auto in_cur = [&](int v) { return v == cur[0] || v == cur[1]; };
+    // joins and equality tests never use the constant column
+    auto in_cur = [&](int v) { return v != kZeroVar && (v == cur[0] || v == cur[1]); };
     if (remaining.empty()) {
       p.proj.outer_col = 0;
       take_filter(p.proj, cur, 2);
@@ -711,6 +719,7 @@ struct hl_engine {
         need.insert({r.head.arg[0], r.head.arg[1]});
         for (size_t f = 0; f < r.neq.size(); ++f)
           if (!applied[f]) need.insert({r.neq[f].first, r.neq[f].second});
+        need.erase(kZeroVar);
         std::vector<int> keep;
         for (int k = 0; k < 3; ++k)
           if (need.count(avail[k]) && std::find(keep.begin(), keep.end(), avail[k]) == keep.end())
@@ -2073,7 +2082,7 @@ int hl_declare(hl_engine* e, const char* name, uint32_t arity, int32_t is_edb) {
         fail(HL_E_INVALID, "bad relation name");
     if (!e->rules.empty()) fail(HL_E_STATE, "declare before hl_program");
     if (e->find(name) >= 0) fail(HL_E_INVALID, std::string("relation declared twice: ") + name);
-    if (arity != 2) fail(HL_E_UNSUPPORTED, "only binary relations are supported");
+    if (arity != 1 && arity != 2) fail(HL_E_UNSUPPORTED, "only unary and binary relations");
     Relation R;
     R.name = name;
     R.arity = int(arity);

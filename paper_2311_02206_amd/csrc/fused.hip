@@ -34,9 +34,10 @@ constexpr int kFWaves = kFNT / kWave;
 constexpr int kLock = 4;  // membership searches in flight per thread
 static_assert(kFusedGroups < kFNT, "one finishing thread per phase-A workgroup");
 
+// Value number src of (c0, c1, inner's other column); 3 is the constant 0.
 template <typename K>
 __device__ __forceinline__ K fz_pick(int src, K c0, K c1, K o) {
-  return src == 0 ? c0 : (src == 1 ? c1 : o);
+  return src == 0 ? c0 : (src == 1 ? c1 : (src == 2 ? o : K(0)));
 }
 
 __device__ __forceinline__ bool fz_hash_find(const Slot* table, u64 cap, u32 key, u32& start,

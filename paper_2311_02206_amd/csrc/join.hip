@@ -48,9 +48,11 @@ __device__ __forceinline__ bool hisa_find(const Slot* table, u64 cap, u32 key, u
   return false;
 }
 
+// Value number src of (c0, c1, inner's other column); 3 is the constant 0
+// (the second column of a unary relation).
 template <typename K>
 __device__ __forceinline__ K pick(int src, K c0, K c1, K o) {
-  return src == 0 ? c0 : (src == 1 ? c1 : o);
+  return src == 0 ? c0 : (src == 1 ? c1 : (src == 2 ? o : K(0)));
 }
 
 // One lane per outer tuple.  Outer arrays are sorted on (or grouped by)

@@ -135,7 +135,8 @@ hipError_t key_range(const K* keys, u64 n, K lo, K hi, u64* out, hipStream_t s);
 
 // ---------------------------------------------------------------- join
 // Values of the current pair (c0, c1) and of the inner tuple's non-join
-// column are numbered 0, 1, 2.  The output pair is (v[src0], v[src1]); a
+// column are numbered 0, 1, 2, and 3 is the constant 0 (the second column
+// of a unary relation).  The output pair is (v[src0], v[src1]); a
 // filter fa >= 0 keeps it only when v[fa] != v[fb], a filter ea >= 0 only
 // when v[ea] == v[eb] (a variable repeated in an atom, or an atom whose two
 // variables are both already bound).

@@ -418,7 +418,7 @@ def evaluate(program: str, edb: dict, idb: dict, **engine_kw):
     relation, per-iteration delta sizes, and the run's statistics."""
     with Engine(**engine_kw) as e:
         for name, rows in edb.items():
-            e.declare(name, 2, True)
+            e.declare(name, int(rows.shape[1]) if len(rows.shape) == 2 else 1, True)
         for name, ar in idb.items():
             e.declare(name, ar, False)
         for name, rows in edb.items():

@@ -452,3 +452,35 @@ def test_expand_tiles_match_oracle(tile):
     cs = workloads.cspa(11)["edb"]
     check_same(PROG["cspa_shaped"], cs, {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2},
                expand_tile=tile, join_dedup=True)
+
+
+UNARY = ("R(x) :- S(x).\nR(y) :- R(x), E(x, y).\nN(x) :- E(x, _).\nN(y) :- E(_, y).\n"
+         "B(x, y) :- R(x), E(y, x), x != y.\nL(x) :- E(x, x).\nC(x, x) :- R(x), L(x).\n")
+UNARY_IDB = {"R": 1, "N": 1, "B": 2, "L": 1, "C": 2}
+# the part that fused iterations take (every join inner an EDB relation)
+UNARY_FUSED = "R(x) :- S(x).\nR(y) :- R(x), E(x, y).\nB(x, y) :- R(x), E(y, x), x != y.\n"
+
+
+@pytest.mark.parametrize("mode", ["plain", "learned", "fused_graph"])
+def test_unary_relations(mode):
+    """Unary EDB and IDB relations against the oracle: single-source
+    reachability (pinned to BFS), projections, a unary atom as a join's
+    outer and inner, a self-loop test and a binary head over a unary body."""
+    say(f"unary relations, {mode}")
+    kw = {"plain": {}, "learned": {"learned": True},
+          "fused_graph": {"fused": True, "hip_graph": True}}[mode]
+    wl = workloads.reach_er_1000()
+    E = np.concatenate([wl["edb"]["Edge"], np.array([[7, 7], [500, 500]], dtype=np.uint32)])
+    S = np.array([[0], [17], [999]], dtype=np.uint32)
+    edb = {"E": E, "S": S}
+    if mode == "fused_graph":
+        rels, deltas, st, want = check_same(UNARY_FUSED, edb, {"R": 1, "B": 2}, **kw)
+    else:
+        rels, deltas, st, want = check_same(UNARY, edb, UNARY_IDB, **kw)
+    reach = set()
+    for s in (0, 17, 999):
+        reach |= {s} | set(oracle.reach_from(wl["n_nodes"], E, s).tolist())
+    assert sorted(reach) == rels["R"][:, 0].tolist()
+    assert rels["R"].shape[1] == 1 and rels["B"].shape[1] == 2
+    if mode == "fused_graph":
+        assert st.fused_iterations > 0

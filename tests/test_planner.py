@@ -80,3 +80,23 @@ def test_random_programs_mostly_plan():
             unsupported += c == H.HL_E_UNSUPPORTED
     print("planned", ok, "unsupported", unsupported)
     assert ok >= 100
+
+
+def test_unary_relations_plan():
+    """Unary relations: declared with arity 1, used in heads and bodies; a
+    unary atom joins on its one column, never on its constant one."""
+    e = pkg.Engine(device=-1)
+    for name, ar, edb in (("E", 2, True), ("S", 1, True), ("R", 1, False), ("B", 2, False),
+                          ("N", 1, False)):
+        e.declare(name, ar, edb)
+    e.program("R(x) :- S(x).\nR(y) :- R(x), E(x, y).\nN(x) :- E(x, _).\n"
+              "B(x, y) :- R(x), E(y, x).\nN(x) :- E(x, x).\nB(x, x) :- R(x), S(x).\n")
+    assert code_of(lambda: e.program("R(x, y) :- E(x, y).")) == H.HL_E_INVALID
+    assert code_of(lambda: e.program("B(x) :- E(x, y).")) == H.HL_E_INVALID
+    # two unary atoms with no shared variable: a cross product
+    assert code_of(lambda: e.program("B(x, y) :- R(x), S(y).")) == H.HL_E_UNSUPPORTED
+    e.close()
+    e = pkg.Engine(device=-1)
+    assert code_of(lambda: e.declare("Z", 0, False)) == H.HL_E_UNSUPPORTED
+    e.declare("U", 1, False)
+    e.close()
