@@ -104,3 +104,21 @@ def test_fused_flags_and_capacity_are_checked_on_a_planning_engine():
     assert create(h.HL_FLAG_FUSED, 4096) == 0
     assert create(h.HL_FLAG_FUSED, 1000) == h.HL_E_INVALID
     assert create(h.HL_FLAG_FUSED, 512) == h.HL_E_INVALID
+
+
+def test_expand_tile_option_is_checked():
+    """hl_options.expand_tile takes 0 (default), 1024, 2048 or 4096."""
+    import ctypes
+    h = pkg.hisalog
+    L = pkg.lib()
+    for tile, want in ((0, 0), (1024, 0), (2048, 0), (4096, 0), (512, h.HL_E_INVALID),
+                       (3000, h.HL_E_INVALID), (8192, h.HL_E_INVALID)):
+        opt = h.Options()
+        L.hl_options_init(ctypes.byref(opt))
+        opt.device = -1
+        opt.expand_tile = tile
+        e = ctypes.c_void_p()
+        rc = L.hl_create(ctypes.byref(opt), ctypes.byref(e))
+        if rc == 0:
+            L.hl_destroy(e)
+        assert rc == want, tile
