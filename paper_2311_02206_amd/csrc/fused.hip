@@ -337,6 +337,79 @@ __device__ __forceinline__ u32 fz_offsets(const u64* counts, int h, u32 G, int w
   return total;
 }
 
+// Sorts buf[0, n), the concatenation of R sorted runs with offsets
+// ro[0, R] (LDS; rewritten), and returns where the sorted keys are.  With
+// n <= cap / 2 the runs are merged pairwise, ping-ponging with the upper
+// half of the buffer: each thread takes 8 consecutive outputs, finds its
+// pair of runs (the first whose end is past its first output), splits the
+// pair by a merge-path search and merges serially (ties: the earlier run
+// first).  log2(R) rounds cost far fewer LDS accesses than a bitonic
+// network over the same keys.  Larger inputs take the bitonic sort.
+// Every thread must call it.
+template <typename K>
+__device__ K* fz_sort_runs(K* buf, u32 n, u32 cap, u32* ro, u32 R) {
+  if (n <= 1) return buf;
+  if (n > cap / 2) {
+    u32 p2 = 2;
+    while (p2 < n) p2 <<= 1;
+    for (u32 k = n + threadIdx.x; k < p2; k += kFNT) buf[k] = ~K(0);
+    __syncthreads();
+    fz_bitonic(buf, p2);
+    return buf;
+  }
+  constexpr u32 kSpan = 8;
+  K* src = buf;
+  K* dst = buf + cap / 2;
+  while (R > 1) {
+    const u32 R2 = (R + 1) / 2;
+    for (u32 c0 = threadIdx.x * kSpan; c0 < n; c0 += kFNT * kSpan) {
+      const u32 c1 = (c0 + kSpan) < n ? (c0 + kSpan) : n;
+      u32 k = c0;
+      while (k < c1) {
+        // pair i covers runs 2i and 2i + 1: [ro[2i], ro[min(2i + 2, R)])
+        u32 lo = 0, hi = R2 - 1;
+        while (lo < hi) {
+          const u32 mid = (lo + hi) >> 1;
+          const u32 e = 2 * mid + 2 < R ? 2 * mid + 2 : R;
+          if (ro[e] > k) hi = mid;
+          else lo = mid + 1;
+        }
+        const u32 a0 = ro[2 * lo];
+        const u32 a1 = ro[2 * lo + 1 < R ? 2 * lo + 1 : R];
+        const u32 b1 = ro[2 * lo + 2 < R ? 2 * lo + 2 : R];
+        if (b1 <= k) break;  // cannot happen (ro[R] == n > k); never loops
+        const u32 la = a1 - a0, lb = b1 - a1, diag = k - a0;
+        u32 alo = diag > lb ? diag - lb : 0, ahi = diag < la ? diag : la;
+        while (alo < ahi) {
+          const u32 mid = (alo + ahi) >> 1;
+          if (!(src[a1 + (diag - 1 - mid)] < src[a0 + mid])) alo = mid + 1;
+          else ahi = mid;
+        }
+        u32 ai = alo, bi = diag - alo;
+        const u32 end = c1 < b1 ? c1 : b1;
+        for (; k < end; ++k) {
+          const bool take_a = bi >= lb || (ai < la && !(src[a1 + bi] < src[a0 + ai]));
+          dst[k] = take_a ? src[a0 + ai++] : src[a1 + bi++];
+        }
+      }
+    }
+    __syncthreads();
+    // the merged runs start where the even runs started
+    const u32 j = threadIdx.x;
+    u32 v = 0;
+    if (j < R2) v = ro[2 * j];
+    __syncthreads();
+    if (j < R2) ro[j] = v;
+    if (j == R2) ro[j] = n;
+    __syncthreads();
+    R = R2;
+    K* t = src;
+    src = dst;
+    dst = t;
+  }
+  return src;
+}
+
 // Number of distinct keys in the sorted a[0, n); every thread must call it.
 template <typename K>
 __device__ u32 fz_count_distinct(const K* a, u32 n, u32* wsum) {
@@ -376,31 +449,23 @@ __global__ __launch_bounds__(kFNT) void fused_finish_kernel(FusedIteration<K> it
     u32 n = fz_offsets(sc.counts, h, G, 0, s_off, s_wsum);
     if (n > cap_b) goto overflow;
     fz_gather(sc.surv, h, G, cap_c, s_off, buf);
-    u32 p2 = 2;
-    while (p2 < n) p2 <<= 1;
-    for (u32 k = n + threadIdx.x; k < p2; k += kFNT) buf[k] = ~K(0);
-    __syncthreads();
-    if (n > 1) fz_bitonic(buf, p2);
+    const K* srt = fz_sort_runs(buf, n, cap_b, s_off, G);
     K* out = it.delta_out[h];
     u32 d = 0;
     for (u32 b = 0; b < n; b += kFNT) {
       const u32 i = b + threadIdx.x;
-      const bool first = i < n && (i == 0 || buf[i - 1] != buf[i]);
+      const bool first = i < n && (i == 0 || srt[i - 1] != srt[i]);
       u32 tot;
       const u32 pos = block_exclusive_scan<kFNT>(first ? 1u : 0u, s_wsum, tot);
-      if (first) out[d + pos] = buf[i];
+      if (first) out[d + pos] = srt[i];
       d += tot;
     }
     __syncthreads();
     n = fz_offsets(sc.counts, h, G, 1, s_off, s_wsum);
     if (n > cap_b) goto overflow;
     fz_gather(sc.pres, h, G, cap_c, s_off, buf);
-    p2 = 2;
-    while (p2 < n) p2 <<= 1;
-    for (u32 k = n + threadIdx.x; k < p2; k += kFNT) buf[k] = ~K(0);
-    __syncthreads();
-    if (n > 1) fz_bitonic(buf, p2);
-    const u32 dp = fz_count_distinct(buf, n, s_wsum);
+    srt = fz_sort_runs(buf, n, cap_b, s_off, G);
+    const u32 dp = fz_count_distinct(srt, n, s_wsum);
     if (threadIdx.x == 0) {
       cnt[h * kFusedSlots + 2] = d;
       cnt[h * kFusedSlots + 3] = u64(d) + dp;
