@@ -133,8 +133,8 @@ def main():
     ap.add_argument("--one-at-a-time-sample", type=int, default=256)
     ap.add_argument("--variant", default="",
                     help="run only this comparison (cspa, reach_er_2p22, nonlinear_er_2p22, "
-                         "batched, ebm_ablation, nested_join_ablation, table6_microbench) and "
-                         "print its JSON")
+                         "batched, batched_autotuned, ebm_ablation, nested_join_ablation, "
+                         "table6_microbench) and print its JSON")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once (a reference kernel of known "
                          "size for hardware byte counters)")
@@ -168,6 +168,8 @@ def main():
                 "batched": lambda: batched_variant(stream, max(1, args.batched_instances),
                                                    args.one_at_a_time_sample, steps,
                                                    programs["reach"], verify=verify),
+                "batched_autotuned": lambda: batched_autotuned(
+                    stream, max(1, args.batched_instances), steps, programs["reach"]),
                 "ebm_ablation": lambda: ebm_ablation(stream, steps),
                 "nested_join_ablation": lambda: nested_ablation(stream, steps, verify=verify),
                 "table6_microbench": lambda: table6_microbench(stream)}
@@ -575,6 +577,40 @@ def er_variant(stream, steps, verify=True):
     prog = open(os.path.join(ROOT, "workloads", "programs", "reach.dl")).read()
     return plain_vs_learned(stream, "reach_er_2p22_0.9x", prog, wl["edb"], {"Reach": 2},
                             steps, verify, forms=ALL_FORMS)
+
+
+def batched_autotuned(stream, n_inst, steps, program):
+    """The batch after hl_autotune chose its settings (probe method and load
+    factor, expand tile, EBM growth, in-tile dedup, fused iterations), timed
+    against the engine's defaults with fused iterations from HIP graphs.
+    Not part of the default run: the search takes a few minutes."""
+    import workloads
+    from paper_2311_02206_amd import Engine
+    log(f"batched autotune: generating {n_inst} instances")
+    nodes, edges = workloads.batched_reach_instances(n_inst, seed=0xC4)
+    e = Engine(device=0, stream=stream, ebm_k=1.5, fused=True, hip_graph=True)
+    try:
+        e.declare("Edge", 2, True)
+        e.declare("Reach", 2, False)
+        e.batch_layout(nodes)
+        e.load_batched("Edge", edges)
+        e.program(program)
+        for _ in range(4):
+            if e.run().allocations == 0:
+                break
+        before = sorted(e.run().seconds for _ in range(steps))[steps // 2]
+        counts = e.iteration_counts("Reach", 0)
+        chosen = e.autotune(reps=1)
+        for _ in range(4):
+            if e.run().allocations == 0:
+                break
+        runs = [e.run() for _ in range(steps)]
+        after = sorted(r.seconds for r in runs)[steps // 2]
+        return {"workload": f"batched_reach_{n_inst}_instances", "tuples": runs[-1].idb_tuples,
+                "ms_before": before * 1e3, "ms_after": after * 1e3, "speedup": before / after,
+                "same_deltas": e.iteration_counts("Reach", 0) == counts, "settings": chosen}
+    finally:
+        e.close()
 
 
 def batched_variant(stream, n_inst, sample, steps, program, verify=True):
