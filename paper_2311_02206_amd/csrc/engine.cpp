@@ -1264,9 +1264,11 @@ struct hl_engine {
       const bool use_model = learned() && R.n_full > 0 && R.idx[0].lm_ok &&
                              R.idx[0].lm_keys == R.full.p && R.idx[0].lm_n == R.n_full;
       if (use_model) mv = R.idx[0].view<K>();
+      // a tail run beside full is tested in the same pass
       HIPCK(hl::unique_diff<K>(kp<K>(sbuf), R.n_cand, kp<K>(R.full), R.n_full, kp<K>(obuf),
                                kp<K>(sbuf), d_small + 2 * q, ws.p, stream, kt(),
-                               use_model ? &mv : nullptr));
+                               use_model ? &mv : nullptr,
+                               R.n_tail ? kp<K>(R.fz_tail[0]) : nullptr, R.n_tail));
       std::swap(R.delta, sbuf);
     }
     HIPCK(hipMemcpyAsync(h_small, d_small, 2 * idbs.size() * sizeof(u64), hipMemcpyDeviceToHost,
@@ -1277,37 +1279,6 @@ struct hl_engine {
     for (auto& c : chunked) {
       h_small[2 * c.first] = c.second.first;
       h_small[2 * c.first + 1] = c.second.second;
-    }
-    // relations with a tail run: drop the new tuples the tail already holds
-    // (a second membership pass over the delta, one more synchronisation)
-    {
-      bool any = false;
-      for (size_t q = 0; q < idbs.size(); ++q) {
-        Relation& R = rels[idbs[q]];
-        const u64 D = h_small[2 * q];
-        bool was_chunked = false;
-        for (auto& c : chunked) was_chunked |= c.first == q;
-        if (R.n_tail == 0 || D == 0 || was_chunked) continue;
-        if (!any) mark(HL_PHASE_DIFF);
-        any = true;
-        reserve_grow(tmp[0], D * sizeof(K));
-        reserve(ws, hl::unique_diff_workspace_bytes(D), hl::unique_diff_workspace_bytes(D) * 2);
-        HIPCK(hl::unique_diff<K>(kp<K>(R.delta), D, kp<K>(R.fz_tail[0]), R.n_tail, kp<K>(tmp[0]),
-                                 kp<K>(R.delta), d_small + 2 * q, ws.p, stream, kt()));
-      }
-      if (any) {
-        // relations without a second pass keep their counts on the device,
-        // except the chunked ones (zeroed there); distinct counts stay the
-        // first pass's
-        const std::vector<u64> first(h_small, h_small + 2 * idbs.size());
-        HIPCK(hipMemcpyAsync(h_small, d_small, 2 * idbs.size() * sizeof(u64),
-                             hipMemcpyDeviceToHost, stream));
-        mark(-1);
-        sync();
-        collect();
-        for (size_t q = 0; q < idbs.size(); ++q) h_small[2 * q + 1] = first[2 * q + 1];
-        for (auto& c : chunked) h_small[2 * c.first] = first[2 * c.first];
-      }
     }
     u64 total = 0;
     std::vector<int> grown;
@@ -1417,10 +1388,10 @@ struct hl_engine {
   static constexpr u64 kTailKeys = u64(1) << 18;
   // On the multi-kernel path a relation keeps a tail run once its full
   // holds this many bytes and the tail stays within an eighth of it.  The
-  // tail costs a second membership pass per iteration (about 100 us of
-  // dependent searches, whatever its size), so it pays only where
-  // rewriting full costs several times that.
-  static constexpr u64 kTailMinFullBytes = u64(512) << 20;
+  // set difference searches the tail for the keys that survive full, in
+  // the same pass; below this size rewriting full costs less than those
+  // searches.
+  static constexpr u64 kTailMinFullBytes = u64(64) << 20;
 
   // Folds R's tail run into its full relation (one merge).
   template <typename K>

@@ -76,11 +76,14 @@ u64 unique_diff_workspace_bytes(u64 n);
 // duplicates.  `tmp` holds n keys.  d_counts[0] = |out|, d_counts[1] =
 // number of distinct keys in `sorted`.  n must be below 2^32.
 // With `model` (a learned index over full), the slice of full each tile
-// spans and the membership tests outside LDS go through the model.
+// spans and the membership tests outside LDS go through the model.  With a
+// tail (ntail sorted unique keys, disjoint from full), keys it holds are
+// dropped too: the result is unique(sorted) \ (full U tail).
 template <typename K>
 hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
                        u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer = nullptr,
-                       const LearnedView<K>* model = nullptr);
+                       const LearnedView<K>* model = nullptr, const K* tail = nullptr,
+                       u64 ntail = 0);
 
 // --------------------------------------------------------------- merge
 u64 merge_workspace_bytes(u64 na, u64 nb);

@@ -80,7 +80,8 @@ template <typename K, bool kModel>
 __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, const K* full,
                                                           u64 nf, K* tmp, u32* tile_counts,
                                                           u32* tile_uniq, LearnedView<K> lv,
-                                                          const u64* part) {
+                                                          const u64* part, const K* tail,
+                                                          u64 ntail) {
   __shared__ u32 wsum[kUdNT / kWave];
   __shared__ u32 wsum2[kUdNT / kWave];
   // one padding slot per kUdItems keys: thread t reads keys t*16 .. t*16+15,
@@ -227,6 +228,51 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
       }
     }
   }
+  // A short sorted tail run kept beside full (disjoint from it): the keys
+  // that survived full are searched there too, kUdLock at a time in
+  // lockstep.
+  if (ntail > 0) {
+    u32 rem = keep_bits;
+    while (rem) {
+      K c[kUdLock];
+      int qi[kUdLock];
+      int k = 0;
+#pragma unroll
+      for (int j = 0; j < kUdLock; ++j) {
+        if (rem) {
+          const int q = __ffs(rem) - 1;
+          rem &= rem - 1;
+          qi[j] = q;
+          c[j] = s_c[pad(b + q)];
+          k = j + 1;
+        } else {
+          qi[j] = -1;
+          c[j] = K(0);
+        }
+      }
+      const K* at[kUdLock];
+#pragma unroll
+      for (int j = 0; j < kUdLock; ++j) at[j] = tail;
+      u64 len = ntail;
+      while (len > 1) {
+        const u64 half = len >> 1;
+#pragma unroll
+        for (int j = 0; j < kUdLock; ++j)
+          if (j < k) at[j] = (at[j][half] < c[j]) ? at[j] + half : at[j];
+        len -= half;
+      }
+#pragma unroll
+      for (int j = 0; j < kUdLock; ++j) {
+        if (j < k) {
+          const u64 p = u64(at[j] - tail) + ((*at[j] < c[j]) ? 1 : 0);
+          if (p < ntail && tail[p] == c[j]) {
+            keep_bits &= ~(1u << qi[j]);
+            --nkeep;
+          }
+        }
+      }
+    }
+  }
   u32 total;
   u32 pos = block_exclusive_scan<kUdNT>(nkeep, wsum, total);
   // survivors go back into s_c at their compacted positions (all reads of
@@ -350,7 +396,7 @@ u64 unique_diff_workspace_bytes(u64 n) {
 template <typename K>
 hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
                        u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer,
-                       const LearnedView<K>* model) {
+                       const LearnedView<K>* model, const K* tail, u64 ntail) {
   zero_u64x2_kernel<<<1, 1, 0, s>>>(d_counts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n == 0) return e;
@@ -373,13 +419,14 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
                                                             *model);
     ud_select_kernel<K, true><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
                                                               tile_counts, tile_uniq, *model,
-                                                              part);
+                                                              part, tail, ntail);
   } else {
     ud_partition_kernel<K, false><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, part,
                                                              LearnedView<K>{});
     ud_select_kernel<K, false><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
                                                                tile_counts, tile_uniq,
-                                                               LearnedView<K>{}, part);
+                                                               LearnedView<K>{}, part, tail,
+                                                               ntail);
   }
   // by definition: every candidate read once, each kept key written once;
   // the count of kept keys is not known here, so only the reads are counted
@@ -420,9 +467,11 @@ hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipSt
 }
 
 template hipError_t unique_diff<u32>(const u32*, u64, const u32*, u64, u32*, u32*, u64*, void*,
-                                     hipStream_t, LaunchTimer*, const LearnedView<u32>*);
+                                     hipStream_t, LaunchTimer*, const LearnedView<u32>*,
+                                     const u32*, u64);
 template hipError_t unique_diff<u64>(const u64*, u64, const u64*, u64, u64*, u64*, u64*, void*,
-                                     hipStream_t, LaunchTimer*, const LearnedView<u64>*);
+                                     hipStream_t, LaunchTimer*, const LearnedView<u64>*,
+                                     const u64*, u64);
 template hipError_t merge<u32>(const u32*, u64, const u32*, u64, u32*, void*, hipStream_t,
                                LaunchTimer*);
 template hipError_t merge<u64>(const u64*, u64, const u64*, u64, u64*, void*, hipStream_t,
