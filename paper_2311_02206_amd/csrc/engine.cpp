@@ -1392,6 +1392,9 @@ struct hl_engine {
   // the same pass; below this size rewriting full costs less than those
   // searches.
   static constexpr u64 kTailMinFullBytes = u64(64) << 20;
+  // Fused iterations fold a long tail into a full below this size (one
+  // merge of well under a millisecond) rather than merge into it each time.
+  static constexpr u64 kFoldLimitBytes = u64(1) << 30;
 
   // Folds R's tail run into its full relation (one merge).
   template <typename K>
@@ -1445,7 +1448,7 @@ struct hl_engine {
   bool fused_next(u64 sum_delta) const {
     if (!fused_on() || sum_delta == 0 || sum_delta >= fz_fail_at) return false;
     const double rate = last_in ? double(last_out) / double(last_in) : 1.0;
-    return double(sum_delta) * std::max(rate, 1.0) <= 0.75 * double(fz_cap_b);
+    return double(sum_delta) * std::max(rate, 1.0) <= 0.9 * double(fz_cap_b);
   }
 
   // One iteration of the recursive stratum as a fused launch plus
@@ -1495,12 +1498,13 @@ struct hl_engine {
       if (!empty_inner) it.plans[it.nplans++] = fp;  // an empty inner joins nothing
     }
     // The tail may grow by C keys this iteration.  Past kTailKeys it is
-    // folded into full first, unless full is so large that the multi-kernel
-    // path would keep the tail too (then it is folded once it reaches an
-    // eighth of full).
+    // folded into full first, unless full is so large that folding costs
+    // more than merging the longer tail for the rest of the fused
+    // iterations (then it is folded once it reaches an eighth of full, as
+    // on the multi-kernel path).
     for (int r : idbs) {
       Relation& R = rels[r];
-      const bool big = R.n_full * sizeof(K) >= kTailMinFullBytes;
+      const bool big = R.n_full * sizeof(K) >= kFoldLimitBytes;
       if (R.n_tail + C > (big ? R.n_full / 8 : kTailKeys)) {
         mark(HL_PHASE_MERGE);
         flush_tail<K>(R);
