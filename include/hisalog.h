@@ -4,10 +4,10 @@
  *
  * The method is that of "Optimizing Datalog for the GPU" (Sun, Shovon,
  * Gilray, Kumar, Micinski): relations are sorted arrays of packed tuples
- * with an open-addressing hash index from join key to run start (Section 3);
+ * with an open-addressing hash index from join key to run start (Section 4);
  * each fixpoint iteration joins the delta of each recursive relation against
  * the indexed full relations (Section 5.1, Algorithm 3), deduplicates the new
- * tuples by sorting (Section 3.2), subtracts full to form the next delta
+ * tuples by sorting (Section 4.2), subtracts full to form the next delta
  * (Section 5.1, "Populating delta") and merges delta into full (Section 5.1,
  * "Merging Full with Delta"), with multi-atom bodies evaluated as a chain of
  * materialised binary joins (Section 5.2) and merge buffers kept and grown
@@ -141,7 +141,7 @@ typedef struct hl_options {
                                 must grow to hold |full| + |delta| is
                                 reallocated to |full| + k |delta| (default 8) */
   float hash_load_factor;    /* HISA hash table load factor in (0, 1]
-                                (default 0.5; Section 6.3 uses 0.8, which
+                                (default 0.5; Section 6.4 uses 0.8, which
                                 costs ~13 slot reads per linear-probing miss
                                 against ~2.5 at 0.5) */
   uint32_t sort_chunk_log2;  /* an iteration's new tuples are sorted in chunks
@@ -251,7 +251,7 @@ int hl_fetch_batched(hl_engine* e, const char* name, uint32_t inst, uint32_t* ro
                      uint64_t cap_rows, uint64_t* n_rows);
 
 /* Requests a HISA on relation `name` keyed by its column cols[0]
- * (Section 3: sorted array + hash index).  Only ncols == 1 is supported.
+ * (Section 4: sorted array + hash index).  Only ncols == 1 is supported.
  * Optional: hl_program declares every index its rules probe. */
 int hl_index(hl_engine* e, const char* name, const uint32_t* cols, uint32_t ncols);
 
@@ -349,12 +349,12 @@ const char* hl_strerror(int code);
  * counts. */
 
 /* Sorts n keys of d_keys ascending in place by their low `bits` bits
- * (all bits when bits == 0); higher bits must be zero (Section 3.2,
+ * (all bits when bits == 0); higher bits must be zero (Section 4.2,
  * Algorithm 1: LSD order over the packed columns).  n < 2^32. */
 int hl_sort_keys(hl_engine* e, void* d_keys, uint64_t n, uint32_t key_bytes, uint32_t bits);
 
 /* d_out = unique(d_sorted) minus d_full (Section 5.1, "Populating delta";
- * Section 3.2, "Deduplication").  d_sorted: n ascending keys (repeats
+ * Section 4.2, "Deduplication").  d_sorted: n ascending keys (repeats
  * allowed); d_full: n_full ascending distinct keys; d_out: room for n keys.
  * *n_out = |d_out|, *n_unique = distinct keys of d_sorted.  n < 2^32. */
 int hl_unique_diff(hl_engine* e, const void* d_sorted, uint64_t n, const void* d_full,
@@ -362,12 +362,12 @@ int hl_unique_diff(hl_engine* e, const void* d_sorted, uint64_t n, const void* d
                    uint32_t key_bytes);
 
 /* d_out (room for na + nb keys) = merge of ascending d_a and d_b
- * (Section 3.2, "Merge operation": merge path). */
+ * (Section 4.2, "Merge operation": merge path). */
 int hl_merge(hl_engine* e, const void* d_a, uint64_t na, const void* d_b, uint64_t nb,
              void* d_out, uint32_t key_bytes);
 
 /* Builds a HISA over n ascending keys d_keys whose join column is
- * key >> shift (Section 3.3, Algorithm 2), then answers nq range queries:
+ * key >> shift (Section 4.3, Algorithm 2), then answers nq range queries:
  * for join value d_queries[i], d_start[i] = position of the first key with
  * that join value and d_len[i] = number of such keys (0 when absent;
  * d_start is then 0).  *n_runs receives the number of distinct join values.

@@ -13,7 +13,10 @@ Contents:
     with the per-iteration delta sizes it implies for the linear and for
     the nonlinear (doubling) closure program;
   * ``sg_tree_closed_form``: the same-generation relation of a rooted tree in
-    closed form, an independent checker of SG (Section 2).
+    closed form, an independent checker of SG (Section 2);
+  * ``reach_verify``, ``reach_verify_many``, ``sg_tree_verify``: whole-relation
+    checks of fetched Reach and SG relations at any size, every row
+    included (``closure_check.cpp``, threads over sources or instances).
 """
 
 from __future__ import annotations
@@ -27,6 +30,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "_build", "liboracle.so")
+_SOURCES = ("semi_naive.cpp", "closure_check.cpp")
 _lib = None
 
 
@@ -36,7 +40,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_SO):
         tmp = _SO + ".tmp"
         subprocess.run(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-pthread",
-                        os.path.join(_HERE, "semi_naive.cpp"), "-o", tmp], check=True)
+                        *[os.path.join(_HERE, f) for f in _SOURCES], "-o", tmp], check=True)
         os.replace(tmp, _SO)
     return _SO
 
@@ -44,8 +48,8 @@ def build(force: bool = True) -> str:
 def lib():
     global _lib
     if _lib is None:
-        src = os.path.join(_HERE, "semi_naive.cpp")
-        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(src):
+        newest = max(os.path.getmtime(os.path.join(_HERE, f)) for f in _SOURCES)
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < newest:
             build()
         L = ctypes.CDLL(_SO)
         vp, cp, u64, u32 = ctypes.c_void_p, ctypes.c_char_p, ctypes.c_uint64, ctypes.c_uint32
@@ -71,6 +75,14 @@ def lib():
         L.or_reach_bfs.restype = ctypes.c_int64
         L.or_reach_from.argtypes = [u32, vp, u64, u32, vp, u64]
         L.or_reach_from.restype = ctypes.c_int64
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.or_reach_verify.argtypes = [u32, vp, u64, vp, u64, vp, ctypes.c_int, ctypes.c_int, i64p]
+        L.or_reach_verify.restype = ctypes.c_int64
+        L.or_reach_verify_many.argtypes = [u32, vp, vp, vp, vp, vp, vp, ctypes.c_int,
+                                           ctypes.c_int, i64p]
+        L.or_reach_verify_many.restype = ctypes.c_int64
+        L.or_sg_tree_verify.argtypes = [u32, vp, u64, vp, u64, ctypes.c_int, i64p]
+        L.or_sg_tree_verify.restype = ctypes.c_int64
         _lib = L
     return _lib
 
@@ -146,7 +158,7 @@ def reach_bfs_histogram(n_nodes: int, edges: np.ndarray, threads: int | None = N
     ``hist[d]`` counts the pairs whose shortest path has ``d`` edges."""
     edges = np.ascontiguousarray(edges, dtype=np.uint32)
     hist = np.zeros(max_dist, dtype=np.uint64)
-    threads = threads or max(1, os.cpu_count() or 1)
+    threads = _threads(threads)
     total = lib().or_reach_bfs(n_nodes, edges.ctypes.data, edges.shape[0], hist.ctypes.data,
                                max_dist, threads)
     if total < 0:
@@ -240,3 +252,80 @@ def sg_tree_closed_form(edges: np.ndarray):
         deltas.pop()
     deltas.append(0)
     return total, deltas
+
+
+def _threads(threads):
+    # at most 16: the share of host cores that goes with one GPU
+    return int(threads or max(1, min(16, os.cpu_count() or 1)))
+
+
+def reach_verify(n_nodes: int, edges: np.ndarray, rows: np.ndarray, threads: int | None = None,
+                 max_dist: int = 1 << 16):
+    """Whole-relation check of a fetched Reach relation: for every source, a
+    breadth-first search over ``edges`` must mark exactly that source's rows
+    (strictly increasing, all marked, as many as marked nodes).  Returns
+    ``(mismatching_sources, first_bad_source, hist)`` with ``hist[d]`` the
+    number of pairs at shortest distance ``d``; raises on unsorted rows or
+    ids out of range."""
+    edges = np.ascontiguousarray(edges, dtype=np.uint32)
+    rows = np.ascontiguousarray(rows, dtype=np.uint32)
+    hist = np.zeros(max_dist, dtype=np.uint64)
+    bad = ctypes.c_int64(-1)
+    r = lib().or_reach_verify(n_nodes, edges.ctypes.data, edges.shape[0],
+                              rows.ctypes.data if len(rows) else None, rows.shape[0],
+                              hist.ctypes.data, max_dist, _threads(threads), ctypes.byref(bad))
+    if r == -1:
+        raise ValueError("reach_verify: rows not strictly increasing or ids out of range")
+    if r == -2:
+        raise ValueError("reach_verify: a distance exceeds max_dist")
+    last = int(np.nonzero(hist)[0].max()) if hist.any() else 0
+    return int(r), int(bad.value), [int(x) for x in hist[:last + 1]]
+
+
+def reach_verify_many(nodes, edges_list, rows_list, threads: int | None = None,
+                      max_dist: int = 1 << 12):
+    """``reach_verify`` over independent instances (instance-local ids).
+    Returns ``(mismatching_instances, first_bad_instance, summed_hist)``."""
+    k = len(nodes)
+    nodes = np.ascontiguousarray(nodes, dtype=np.uint32)
+    e_off = np.zeros(k + 1, dtype=np.uint64)
+    e_off[1:] = np.cumsum([len(x) for x in edges_list])
+    r_off = np.zeros(k + 1, dtype=np.uint64)
+    r_off[1:] = np.cumsum([len(x) for x in rows_list])
+    E = np.ascontiguousarray(np.concatenate([np.asarray(x, np.uint32).reshape(-1, 2)
+                                             for x in edges_list]) if k else
+                             np.zeros((0, 2), np.uint32))
+    R = np.ascontiguousarray(np.concatenate([np.asarray(x, np.uint32).reshape(-1, 2)
+                                             for x in rows_list]) if k else
+                             np.zeros((0, 2), np.uint32))
+    hist = np.zeros(max_dist, dtype=np.uint64)
+    bad = ctypes.c_int64(-1)
+    r = lib().or_reach_verify_many(k, nodes.ctypes.data, e_off.ctypes.data,
+                                   E.ctypes.data if len(E) else None, r_off.ctypes.data,
+                                   R.ctypes.data if len(R) else None, hist.ctypes.data,
+                                   max_dist, _threads(threads), ctypes.byref(bad))
+    if r == -1:
+        raise ValueError("reach_verify_many: rows not strictly increasing or ids out of range")
+    if r == -2:
+        raise ValueError("reach_verify_many: a distance exceeds max_dist")
+    last = int(np.nonzero(hist)[0].max()) if hist.any() else 0
+    return int(r), int(bad.value), [int(x) for x in hist[:last + 1]]
+
+
+def sg_tree_verify(edges: np.ndarray, rows: np.ndarray, threads: int | None = None):
+    """Whole-relation check of a fetched SG relation over a rooted tree
+    (Edge = (parent, child)): rows strictly increasing, every row a pair of
+    distinct nodes of equal depth >= 1.  With the closed-form count this is
+    set equality.  Returns ``(bad_rows, first_bad_row)``."""
+    edges = np.ascontiguousarray(edges, dtype=np.uint32)
+    rows = np.ascontiguousarray(rows, dtype=np.uint32)
+    n = int(edges.max()) + 1 if len(edges) else 1
+    bad = ctypes.c_int64(-1)
+    r = lib().or_sg_tree_verify(n, edges.ctypes.data, edges.shape[0],
+                                rows.ctypes.data if len(rows) else None, rows.shape[0],
+                                _threads(threads), ctypes.byref(bad))
+    if r == -1:
+        raise ValueError("sg_tree_verify: rows not strictly increasing or ids out of range")
+    if r == -3:
+        raise ValueError("sg_tree_verify: the edges are not a rooted tree")
+    return int(r), int(bad.value)

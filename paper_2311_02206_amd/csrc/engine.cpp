@@ -2138,7 +2138,8 @@ int hl_load_batched(hl_engine* e, const char* name, const uint32_t* rows,
   if (rc != HL_OK) return rc;
   std::vector<u32> mapped;
   mapped.swap(e->batch_rows_tmp);
-  const u64 n = mapped.size() / 2;
+  // rows of the relation's declared arity (the guard above found it)
+  const u64 n = mapped.size() / u64(e->rels[e->find(name)].arity);
   return hl_load(e, name, mapped.data(), n);
 }
 

@@ -1,10 +1,10 @@
 // One fused launch per small iteration: every rule of the recursive
 // stratum, for all its delta variants, runs in a single workgroup that
 // joins the deltas with the (EDB) inner indexes (Algorithm 3), sorts and
-// deduplicates the new tuples in LDS (Section 3.2, sort + unique), drops
+// deduplicates the new tuples in LDS (Section 4.2, sort + unique), drops
 // those already in full (Section 5.1, populating delta) and writes each
 // relation's new delta.  A merge whose sizes are read from device memory
-// (Section 3.2, merge) follows, so the whole iteration, with one small
+// (Section 4.2, merge) follows, so the whole iteration, with one small
 // device-to-host copy of the counts at its end, can be captured once in a
 // HIP graph and replayed while the deltas stay small.
 //

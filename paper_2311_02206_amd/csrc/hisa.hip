@@ -1,8 +1,8 @@
-// HISA: hash-indexed sorted array (Section 3).
+// HISA: hash-indexed sorted array (Section 4).
 //
 // The sorted array holds packed keys (join column << w) | other column,
-// sorted ascending (Section 3.2).  The open-addressing hash index with
-// linear probing (Section 3.3) maps a join-column value to the first
+// sorted ascending (Section 4.2).  The open-addressing hash index with
+// linear probing (Section 4.3) maps a join-column value to the first
 // position of its run and, here, also to the run's length, so a range query
 // is one 16-byte slot read followed by a contiguous scan.
 //

@@ -1,4 +1,4 @@
-// LSD radix sort of packed tuple keys (Section 3.2: the sorted index array
+// LSD radix sort of packed tuple keys (Section 4.2: the sorted index array
 // orders tuples lexicographically with the join columns first; Algorithm 1
 // stable-sorts one column at a time from the least significant one, which
 // on a packed key is exactly an LSD radix sort over its bits).

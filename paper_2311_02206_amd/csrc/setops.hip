@@ -2,12 +2,12 @@
 //
 // unique_diff: populating delta (Section 5.1, "Populating delta"): the
 // sorted new tuples are deduplicated by comparing each with its neighbour
-// (Section 3.2, "Deduplication") and every tuple already in full is
+// (Section 4.2, "Deduplication") and every tuple already in full is
 // removed, so delta and full stay disjoint.  Membership in full is a binary
 // search restricted to the slice of full spanned by the tile, staged in
 // LDS when it is small, else run for all of a thread's keys in lockstep.
 //
-// merge: full := full U delta by merge path (Section 3.2, "Merge
+// merge: full := full U delta by merge path (Section 4.2, "Merge
 // operation", after Green, McColl and Bader 2012): a diagonal search splits
 // the output into equal tiles, each tile merges its two input slices in
 // LDS and writes its output with coalesced stores.

@@ -266,11 +266,14 @@ class Engine:
         self._check(self._L.hl_batch_layout(self._h, r.ctypes.data, len(r)), "hl_batch_layout")
 
     def load_batched(self, name: str, instances):
-        """``instances``: list of (n, 2) uint32 arrays with instance-local ids."""
-        rows = np.ascontiguousarray(np.concatenate(
-            [np.asarray(x, dtype=np.uint32).reshape(-1, 2) for x in instances]), dtype=np.uint32)
+        """``instances``: list of (n, arity) uint32 arrays with instance-local
+        ids, arity as declared for ``name``."""
+        ar = self.arity.get(name, 2)
+        parts = [np.asarray(x, dtype=np.uint32).reshape(-1, ar) for x in instances]
+        rows = np.ascontiguousarray(np.concatenate(parts) if parts else
+                                    np.zeros((0, ar), np.uint32), dtype=np.uint32)
         off = np.zeros(len(instances) + 1, dtype=np.uint64)
-        off[1:] = np.cumsum([len(np.asarray(x).reshape(-1, 2)) for x in instances])
+        off[1:] = np.cumsum([len(x) for x in parts])
         self._check(self._L.hl_load_batched(self._h, name.encode(),
                                             rows.ctypes.data if len(rows) else None,
                                             off.ctypes.data), "hl_load_batched")

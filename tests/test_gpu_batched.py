@@ -160,3 +160,37 @@ def test_batched_empty_and_tiny_instances():
                 assert np.array_equal(got, want), k
                 assert e.batch_count("Reach", k) == len(want)
         assert e.count("Reach") == 1 + 16 + 1
+
+
+@pytest.mark.parametrize("mode", ["plain", "fused_graph"])
+def test_batched_unary_edb(mode):
+    """A unary EDB relation loaded per instance (one or two sources each):
+    single-source reachability of every instance against the oracle run on
+    that instance alone.  The batched load must read rows of the declared
+    arity (one id per row here), not pairs."""
+    import torch
+    import paper_2311_02206_amd as pkg
+    say(f"batched unary EDB, {mode}")
+    prog = "R(x) :- S(x).\nR(y) :- R(x), E(x, y).\n"
+    nodes, edges = workloads.batched_reach_instances(24, seed=0x51, lo=32, hi=400)
+    rng = np.random.default_rng(3)
+    srcs = [rng.choice(int(n), size=1 + (k % 2), replace=False).astype(np.uint32).reshape(-1, 1)
+            for k, n in enumerate(nodes)]
+    kw = {"fused": True, "hip_graph": True} if mode == "fused_graph" else {}
+    with pkg.Engine(device=0, stream=torch.cuda.current_stream(), **kw) as e:
+        e.declare("E", 2, True)
+        e.declare("S", 1, True)
+        e.declare("R", 1, False)
+        e.batch_layout(nodes)
+        e.load_batched("E", edges)
+        e.load_batched("S", srcs)
+        e.program(prog)
+        e.run()
+        total = 0
+        for k in range(len(nodes)):
+            want = oracle.evaluate(prog, {"E": edges[k], "S": srcs[k]}, {"R": 1}).relations["R"]
+            got = e.fetch_batched("R", k)
+            assert got.shape[1] == 1
+            assert np.array_equal(got, want), k
+            total += len(want)
+        assert e.count("R") == total

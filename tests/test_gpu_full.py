@@ -1,15 +1,22 @@
 """GPU parity at the benchmark's full sizes, in the launch configuration
-bench.py times (one engine per program, default options).  The std::set
-oracle cannot run at these sizes (tens of GB and hours), so the references
-are exact independent computations the oracle's pins already tie to it:
-  * Reach: per-source BFS gives the tuple count and, through the shortest
-    distance histogram, every per-iteration delta size; sampled sources are
-    compared row by row;
-  * SG on a tree: the closed form gives the count and per-iteration deltas;
-    sampled rows are checked against the same-depth definition, and the
-    output must be sorted, unique, irreflexive and symmetric;
+bench.py times.  The std::set oracle cannot run at these sizes (tens of GB
+and hours), so the references are exact independent computations that the
+oracle's pins tie to it, and every row of every output is compared:
+  * Reach: for every source, a breadth-first search over the edges marks
+    the reachable nodes, and that source's fetched rows must be exactly the
+    marked nodes (oracle.reach_verify: strictly increasing, all marked, as
+    many as marked); the shortest-distance histogram gives every
+    per-iteration delta size;
+  * SG on a tree: every fetched row must be a pair of distinct nodes of equal
+    depth (oracle.sg_tree_verify), the rows strictly increasing, and their
+    number the closed form's, which together is set equality; the closed
+    form also gives every per-iteration delta;
   * the CSPA-shaped program: naive evaluation over boolean matrices of the
-    active ids (every tuple and every per-iteration delta).
+    active ids (every tuple and every per-iteration delta);
+  * the 4,096-instance batch: every instance's rows against its own
+    reachability searches, and the batch's per-iteration deltas against
+    the sum of the instances' distance histograms, in both engine forms
+    bench.py times.
 """
 
 import os
@@ -48,21 +55,27 @@ def engine(program, edb, idb, learned=False, **kw):
     return e
 
 
-def check_reach(wl, sources, learned=False, **kw):
+def verify_all_rows(n_nodes, E, R, deltas, doubling=False):
+    """Every row of a fetched Reach relation against per-source searches,
+    and the per-iteration delta sizes against the distance histogram."""
+    bad, first, hist = oracle.reach_verify(n_nodes, E, R)
+    assert bad == 0, f"{bad} sources differ, first {first}"
+    assert len(R) == sum(hist)
+    want = (oracle.doubling_deltas_from_histogram(hist) if doubling
+            else oracle.reach_deltas_from_histogram(hist))
+    assert deltas == want
+
+
+def check_reach(wl, learned=False, **kw):
     E = wl["edb"]["Edge"]
     e = engine(PROG["reach"], wl["edb"], {"Reach": 2}, learned=learned, **kw)
     try:
         st = e.run()
         say(f"  ran: {st.idb_tuples} tuples, {st.iterations} iterations, {st.seconds:.3f} s")
-        total, hist = oracle.reach_bfs_histogram(wl["n_nodes"], E)
-        assert e.count("Reach") == total
-        assert e.iteration_counts("Reach", 0) == oracle.reach_deltas_from_histogram(hist)
         R = e.fetch("Reach")
-        key = (R[:, 0].astype(np.uint64) << np.uint64(32)) | R[:, 1]
-        assert np.all(key[1:] > key[:-1])
-        for s in sources:
-            lo, hi = np.searchsorted(R[:, 0], [s, s + 1])
-            assert np.array_equal(R[lo:hi, 1], oracle.reach_from(wl["n_nodes"], E, s)), s
+        assert e.count("Reach") == len(R)
+        verify_all_rows(wl["n_nodes"], E, R, e.iteration_counts("Reach", 0))
+        say(f"  all {len(R)} rows verified")
         return st
     finally:
         e.close()
@@ -71,7 +84,7 @@ def check_reach(wl, sources, learned=False, **kw):
 def test_reach_rmat16_200k():
     say("reach rmat 2^16 / 200k")
     wl = workloads.reach_rmat16()
-    st = check_reach(wl, [0, 1, 2, 3, 7, 100, 4095, 20000, 65535])
+    st = check_reach(wl)
     assert st.key_bytes == 4
 
 
@@ -87,21 +100,17 @@ def test_sg_tree_50k():
         assert e.count("SG") == total
         assert e.iteration_counts("SG", 0) == deltas
         S = e.fetch("SG")
+        assert len(S) == total
+        # every row a pair of distinct same-depth nodes, strictly increasing:
+        # with the closed-form count, the fetched set is the definition's
+        bad, first = oracle.sg_tree_verify(E, S)
+        assert bad == 0, f"{bad} rows fail the same-generation predicate, first {first}"
+        say(f"  all {len(S)} rows verified")
         n = int(E.max()) + 1
         depth = np.zeros(n, dtype=np.int64)
         for p, c in E.tolist():
             depth[c] = depth[p] + 1
-        key = (S[:, 0].astype(np.uint64) << np.uint64(32)) | S[:, 1]
-        assert np.all(key[1:] > key[:-1])
-        assert np.all(S[:, 0] != S[:, 1])
-        rng = np.random.default_rng(1)
-        idx = rng.integers(0, len(S), 100_000)
-        assert np.all(depth[S[idx, 0]] == depth[S[idx, 1]])
-        # symmetry on the sample
-        sw = (S[idx, 1].astype(np.uint64) << np.uint64(32)) | S[idx, 0]
-        pos = np.searchsorted(key, sw)
-        assert np.all(key[np.minimum(pos, len(key) - 1)] == sw)
-        # every row of a sampled node: exactly the other nodes of its depth
+        # every row of a few nodes, spelled out: the other nodes of its depth
         for v in (1, 7, 1234, 49_999):
             lo, hi = np.searchsorted(S[:, 0], [v, v + 1])
             want = np.nonzero((depth == depth[v]) & (np.arange(n) != v))[0]
@@ -126,7 +135,7 @@ def test_reach_er_2p22_subcritical(mode):
     say(f"reach er 2^22 subcritical, {mode}")
     wl = workloads.reach_er_2p22()
     kw = dict(ER_MODES[mode])
-    st = check_reach(wl, [0, 1, 12345, (1 << 22) - 1], **kw)
+    st = check_reach(wl, **kw)
     assert st.key_bytes == 8
     if mode == "all_on":
         assert st.fused_iterations > 30 and st.graph_captures >= 1
@@ -139,8 +148,8 @@ NONLINEAR = "T(x, y) :- E(x, y).\nT(x, y) :- T(x, z), T(z, y)."
 def test_nonlinear_closure_er_2p22(learned):
     """The nonlinear closure on the 2^22-node ER graph, where the growing
     relation is itself the join's inner (hash rebuilt, or model refitted,
-    after every merge): count and per-iteration deltas from the distance
-    histogram (doubling), sampled sources row by row."""
+    after every merge): every row against per-source searches, and the
+    per-iteration deltas from the distance histogram (doubling)."""
     say(f"nonlinear closure er 2^22, learned={learned}")
     wl = workloads.reach_er_2p22()
     E = wl["edb"]["Edge"]
@@ -148,13 +157,10 @@ def test_nonlinear_closure_er_2p22(learned):
     try:
         st = e.run()
         say(f"  ran: {st.idb_tuples} tuples, {st.iterations} iterations, {st.seconds:.3f} s")
-        total, hist = oracle.reach_bfs_histogram(wl["n_nodes"], E)
-        assert e.count("T") == total
-        assert e.iteration_counts("T", 0) == oracle.doubling_deltas_from_histogram(hist)
         T = e.fetch("T")
-        for s in (0, 1, 12345, (1 << 22) - 1):
-            lo, hi = np.searchsorted(T[:, 0], [s, s + 1])
-            assert np.array_equal(T[lo:hi, 1], oracle.reach_from(wl["n_nodes"], E, s)), s
+        assert e.count("T") == len(T)
+        verify_all_rows(wl["n_nodes"], E, T, e.iteration_counts("T", 0), doubling=True)
+        say(f"  all {len(T)} rows verified")
     finally:
         e.close()
 
@@ -189,16 +195,42 @@ def test_cspa_literal_2p14(learned):
         e.close()
 
 
-def test_batched_reach_4096_instances():
+def verify_batch(e, nodes, edges, group_rows=200_000_000):
+    """Every instance's rows against its own reachability searches (fetched
+    and checked in groups of instances to bound host memory), and the
+    batch's per-iteration deltas against the summed distance histograms."""
+    k, total, hist = 0, 0, np.zeros(1 << 12, dtype=np.int64)
+    while k < len(nodes):
+        group, rows, n_rows = [], [], 0
+        while k < len(nodes) and (not group or n_rows < group_rows):
+            r = e.fetch_batched("Reach", k)
+            group.append(k)
+            rows.append(r)
+            n_rows += len(r)
+            k += 1
+        bad, first, h = oracle.reach_verify_many(nodes[group], [edges[q] for q in group], rows)
+        assert bad == 0, f"{bad} instances differ, first {group[first] if first >= 0 else first}"
+        hist[:len(h)] += h
+        total += n_rows
+    assert total == e.count("Reach")
+    last = int(np.nonzero(hist)[0].max())
+    assert e.iteration_counts("Reach", 0) == oracle.reach_deltas_from_histogram(hist[:last + 1])
+    return total
+
+
+@pytest.mark.parametrize("form", ["plain", "fused_graph"])
+def test_batched_reach_4096_instances(form):
     """4,096 independent Reach instances (log-uniform 32..4096 nodes, 2-4x
-    edges) in one batched fixpoint, as bench.py runs them: sampled instances
-    row by row against their own BFS closure, and every instance of a wider
-    sample by tuple count."""
+    edges) in one batched fixpoint, in both forms bench.py times (EBM growth
+    1.5; fused small iterations from HIP graphs or not): every row of every
+    instance."""
     import torch
     import paper_2311_02206_amd as pkg
-    say("batched reach, 4096 instances")
+    say(f"batched reach, 4096 instances, {form}")
     nodes, edges = workloads.batched_reach_instances(4096, seed=0xC4)
-    e = pkg.Engine(device=0, stream=torch.cuda.current_stream(), ebm_k=1.5)
+    nodes = np.asarray(nodes)
+    kw = {"fused": True, "hip_graph": True} if form == "fused_graph" else {}
+    e = pkg.Engine(device=0, stream=torch.cuda.current_stream(), ebm_k=1.5, **kw)
     try:
         e.declare("Edge", 2, True)
         e.declare("Reach", 2, False)
@@ -206,16 +238,12 @@ def test_batched_reach_4096_instances():
         e.load_batched("Edge", edges)
         e.program(PROG["reach"])
         st = e.run()
-        say(f"  ran: {st.idb_tuples} tuples, {st.iterations} iterations, {st.seconds:.3f} s")
-        rng = np.random.default_rng(5)
-        for k in rng.choice(4096, 256, replace=False):
-            total, _ = oracle.reach_bfs_histogram(int(nodes[k]), edges[k], threads=8)
-            assert e.batch_count("Reach", int(k)) == total, k
-        for k in (0, 1, 4095, int(np.argmax(nodes))):
-            got = e.fetch_batched("Reach", k)
-            for s in (0, int(nodes[k]) // 2, int(nodes[k]) - 1):
-                lo, hi = np.searchsorted(got[:, 0], [s, s + 1])
-                assert np.array_equal(got[lo:hi, 1], oracle.reach_from(int(nodes[k]), edges[k], s))
+        say(f"  ran: {st.idb_tuples} tuples, {st.iterations} iterations, {st.seconds:.3f} s, "
+            f"{st.fused_iterations} fused")
+        if form == "fused_graph":
+            assert st.fused_iterations > 0
+        n = verify_batch(e, nodes, edges)
+        say(f"  all {n} rows of 4096 instances verified")
     finally:
         e.close()
 

@@ -1,7 +1,7 @@
 """GPU parity of each kernel of an iteration against plain numpy definitions:
-sort (Section 3.2 / Algorithm 1), unique + set difference (Section 5.1,
-populating delta), merge (Section 3.2, merge path) and the HISA range
-query (Section 3.3 / Algorithm 2).  Bit-exact."""
+sort (Section 4.2 / Algorithm 1), unique + set difference (Section 5.1,
+populating delta), merge (Section 4.2, merge path) and the HISA range
+query (Section 4.3 / Algorithm 2).  Bit-exact."""
 
 import sys
 
