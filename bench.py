@@ -6,9 +6,11 @@ Workload (one step = both fixpoints, every step of the hot path):
     0.19), 2^16 nodes, 200,000 distinct edges;
   * same-generation on a random breadth-first tree of 50,000 nodes with
     1-4 children per node.
-Inputs are synthetic (workloads/) and loaded into HBM before timing.  The
-timed region is hl_run on both engines (EDB dedup and index builds, every
-iteration, the final empty one).  value = (|Reach| + |SG|) / time.
+Inputs are synthetic (workloads/) and in HBM before timing.  Every step
+runs both fixpoints on fresh engines carved from one caller-owned arena;
+the timed region is hl_run (EDB dedup and index builds, every iteration,
+the final empty one).  value = (|Reach| + |SG|) / median step time.  The
+same fixpoints on engines kept across runs are reported beside it.
 
 After timing, the outputs are checked for form (sorted, unique, size equal
 to the summed deltas); bit-exact parity of these same runs against exact
@@ -101,10 +103,31 @@ def measured_traffic(kernel):
     return rec["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(programs):
+def host_info():
+    """The host the CPU figures were taken on: logical CPUs, the CPUs this
+    process may run on, the CPU model and the RAM."""
+    model, ram = None, None
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+        for ln in open("/proc/meminfo"):
+            if ln.startswith("MemTotal"):
+                ram = round(int(ln.split()[1]) / 2**20, 1)
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "usable_cpus": len(os.sched_getaffinity(0)),
+            "cpu_model": model, "ram_gib": ram}
+
+
+def cpu_baseline(programs, reach_wl):
     """The oracle (single-threaded std::set semi-naive) on a bounded sample of
     the same workload: Reach on R-MAT scale 11 (2,048 nodes, 6,250 edges =
-    200,000 / 32) and SG on a 6,250-node tree of the same generator."""
+    200,000 / 32) and SG on a 6,250-node tree of the same generator.  Beside
+    it: the oracle on the 1,000-node ER Reach configuration at full size,
+    and the all-core per-source BFS checker on the full R-MAT Reach input."""
     import oracle
     import workloads
     r = workloads.scaled_rmat(11, 6_250, seed=0xC2A)
@@ -113,10 +136,88 @@ def cpu_baseline(programs):
     b = oracle.evaluate(programs["sg"], t["edb"], {"SG": 2})
     tuples = len(a.relations["Reach"]) + len(b.relations["SG"])
     secs = a.seconds + b.seconds
+    c1 = workloads.reach_er_1000()
+    o1 = oracle.evaluate(programs["reach"], c1["edb"], {"Reach": 2})
+    threads = min(16, len(os.sched_getaffinity(0)))
+    t0 = time.perf_counter()
+    total, _ = oracle.reach_bfs_histogram(reach_wl["n_nodes"], reach_wl["edb"]["Edge"],
+                                          threads=threads)
+    bfs_s = time.perf_counter() - t0
     return {"value": tuples / secs, "unit": "tuples/s", "cores": 1, "kind": "oracle",
             "sample": f"Reach on R-MAT scale 11 (6,250 edges; {len(a.relations['Reach'])} tuples) "
                       f"+ SG on a 6,250-node 1-4-ary tree ({len(b.relations['SG'])} tuples); "
-                      f"{secs:.1f} s of fixpoint time"}
+                      f"{secs:.1f} s of fixpoint time",
+            "host": host_info(),
+            "reach_er_1000_full": {"tuples": len(o1.relations["Reach"]),
+                                   "iterations": o1.iterations, "seconds": o1.seconds,
+                                   "value": len(o1.relations["Reach"]) / o1.seconds,
+                                   "cores": 1},
+            "bfs_checker_reach_rmat16_200k": {"tuples": total, "seconds": bfs_s,
+                                              "value": total / bfs_s, "cores": threads},
+            "table6_host": host_table6()}
+
+
+TABLE6_SIZES = (1_000_000, 10_000_000, 50_000_000, 100_000_000, 500_000_000)
+
+
+def host_table6():
+    """The host side of the sort / merge / memory microbenchmark: the same
+    random 64-bit packed tuples sorted, two sorted halves merged, and a
+    fresh buffer of the tuples' size allocated and written, on the host's
+    threads (at most 16, the share of host cores that goes with one GPU).
+    Repetitions: as many as fit about 2 s per size (at least 1, at most
+    100); s_per_100 scales the per-run time to the paper's 100 runs."""
+    import oracle
+    threads = min(16, len(os.sched_getaffinity(0)))
+    rng = np.random.default_rng(6)
+    rows = []
+    for n in TABLE6_SIZES:
+        src = rng.integers(0, 2**64 - 1, size=n, dtype=np.uint64, endpoint=True)
+        work = np.empty_like(src)
+        st = []
+        reps = 1
+        while True:
+            np.copyto(work, src)
+            st.append(oracle.host_sort_u64(work, threads))
+            if len(st) >= reps:
+                reps = max(1, min(100, int(2.0 / max(st[0], 1e-6))))
+                if len(st) >= reps:
+                    break
+        half = n // 2
+        a = work[:half].copy()
+        b = np.sort(src[half:2 * half])
+        out = np.empty(2 * half, dtype=np.uint64)
+        mt = [oracle.host_merge_u64(a, b, out, threads) for _ in range(reps)]
+        al = [oracle.host_alloc_init(n * 8, threads) for _ in range(reps)]
+        srt, mrg, mem = (float(np.median(x)) for x in (st, mt, al))
+        rows.append({"tuples": n, "reps": reps, "sort_ms": round(srt * 1e3, 3),
+                     "merge_ms": round(mrg * 1e3, 3), "memory_ms": round(mem * 1e3, 3),
+                     "sort_s_per_100": round(srt * 100, 2), "merge_s_per_100": round(mrg * 100, 2),
+                     "memory_s_per_100": round(mem * 100, 2)})
+        log(f"  host {n}: sort {srt * 1e3:.1f} ms, merge {mrg * 1e3:.1f} ms, "
+            f"memory {mem * 1e3:.1f} ms ({reps} reps)")
+        del src, work, a, b, out
+    return {"threads": threads, "host": host_info(), "rows": rows,
+            "note": "64-bit packed tuples; sort: std::sort of one chunk per thread, then "
+                    "rounds of merge-path pairwise merges over all threads; memory: malloc "
+                    "plus one parallel write of every byte"}
+
+
+def oracle_timing(programs):
+    """The oracle at full size on the two Reach configurations it finishes
+    in minutes: the 1,000-node ER graph and the 2^22-node subcritical ER
+    graph (about two and a half minutes on one core)."""
+    import oracle
+    import workloads
+    out = {"host": host_info()}
+    for name, wl in (("reach_er_1000", workloads.reach_er_1000()),
+                     ("reach_er_2p22", workloads.reach_er_2p22())):
+        log(f"oracle {name}")
+        r = oracle.evaluate(programs["reach"], wl["edb"], {"Reach": 2})
+        n = len(r.relations["Reach"])
+        out[name] = {"tuples": n, "iterations": r.iterations, "seconds": r.seconds,
+                     "value": n / r.seconds, "unit": "tuples/s", "cores": 1}
+    return out
 
 
 def main():
@@ -134,7 +235,7 @@ def main():
     ap.add_argument("--variant", default="",
                     help="run only this comparison (cspa, reach_er_2p22, nonlinear_er_2p22, "
                          "batched, batched_autotuned, ebm_ablation, nested_join_ablation, "
-                         "table6_microbench) and print its JSON")
+                         "table6_microbench, oracle_timing) and print its JSON")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="copy this many MiB device-to-device once (a reference kernel of known "
                          "size for hardware byte counters)")
@@ -172,7 +273,8 @@ def main():
                     stream, max(1, args.batched_instances), steps, programs["reach"]),
                 "ebm_ablation": lambda: ebm_ablation(stream, steps),
                 "nested_join_ablation": lambda: nested_ablation(stream, steps, verify=verify),
-                "table6_microbench": lambda: table6_microbench(stream)}
+                "table6_microbench": lambda: table6_microbench(stream),
+                "oracle_timing": lambda: oracle_timing(programs)}
         if args.variant not in only:
             print(f"unknown variant {args.variant}; one of {sorted(only)}", file=sys.stderr)
             sys.exit(2)
@@ -183,51 +285,103 @@ def main():
     sg_wl = workloads.sg_tree_50k()
     specs = {"reach": (programs["reach"], reach_wl["edb"], {"Reach": 2}),
              "sg": (programs["sg"], sg_wl["edb"], {"SG": 2})}
-    # timed engines record no per-kernel events (they cost launch latency)
-    engines = {k: make_engine(p, edb, idb, stream, False) for k, (p, edb, idb) in specs.items()}
+    # the EDB rows are in device memory before any timing; every engine
+    # loads them from there (a device-to-device copy, outside the timed run)
+    dev_specs = {k: (p, {n: torch.from_numpy(np.ascontiguousarray(rows, dtype=np.uint32)
+                                              .view(np.int32)).to("cuda")
+                         for n, rows in edb.items()}, idb)
+                 for k, (p, edb, idb) in specs.items()}
     torch.cuda.synchronize()
 
-    def step():
-        out = {}
+    # 1. Engines kept across runs (eager buffers in their steady state): the
+    #    figure beside the headline, and the plain engines the learned and
+    #    autotuned variants are compared with.  Timed engines record no
+    #    per-kernel events (they cost launch latency).
+    engines = {k: make_engine(p, edb, idb, stream, False) for k, (p, edb, idb) in dev_specs.items()}
+    for i in range(args.warmup):
+        log(f"warmup {i} (reused engines)")
+        for e in engines.values():
+            e.run()
+    reused = {k: [] for k in engines}
+    last = {}
+    for i in range(args.steps):
         for k, e in engines.items():
-            out[k] = e.run()
+            last[k] = e.run()
+            reused[k].append(last[k].seconds)
+    tuples = sum(last[k].idb_tuples for k in engines)
+    reused_med = sum(float(np.median(v)) for v in reused.values())
+    peak = max(last[k].peak_bytes for k in engines)
+    line_reused = {"value": tuples / reused_med, "ms_per_step": reused_med * 1e3,
+                   "per_workload_ms": {k: float(np.median(v)) * 1e3 for k, v in reused.items()},
+                   "peak_bytes": {k: last[k].peak_bytes for k in engines}}
+    variants = {}
+    if not args.no_variants:
+        # the same fixpoints with the learned position index in place of the
+        # HISA hash probe and the membership search; outputs must be identical
+        variants["learned_index"] = learned_variant(stream, dev_specs, args.steps,
+                                                    tuples / reused_med, engines,
+                                                    verify=not args.no_verify)
+        variants["autotuned"] = autotuned_variant(stream, dev_specs, args.steps,
+                                                  tuples / reused_med, engines,
+                                                  verify=not args.no_verify)
+    for e in engines.values():
+        e.close()
+    engines = {}
+
+    # 2. The headline: every step runs each fixpoint on a fresh engine carved
+    #    from one caller-owned arena (a torch tensor), so no run inherits
+    #    buffers from an earlier one and no step allocates device memory.
+    #    A step's time is the sum of its hl_run wall times; the figure is the
+    #    median step.
+    arena_bytes = int(peak * 1.25) + (1 << 30)
+    arena = torch.empty(arena_bytes, dtype=torch.uint8, device="cuda")
+    forms = {}
+
+    def fresh_step(check=False):
+        out = {}
+        for k, (p, edb, idb) in dev_specs.items():
+            e = make_engine(p, edb, idb, stream, False, arena=arena)
+            try:
+                out[k] = e.run()
+                if check:
+                    forms[k] = well_formed(e, next(iter(idb)))
+            finally:
+                e.close()
         return out
 
     for i in range(args.warmup):
-        log(f"warmup {i}")
-        step()
+        log(f"warmup {i} (fresh engines)")
+        fresh_step()
     torch.cuda.synchronize()
     log(f"timing {args.steps} steps")
-    per = {k: 0.0 for k in engines}
-    t0 = time.perf_counter()
-    last = None
+    step_s, per = [], {k: [] for k in dev_specs}
     for i in range(args.steps):
-        last = step()
-        for k in engines:
-            per[k] += last[k].seconds
-        log(f"step {i}: " + ", ".join(f"{k} {last[k].seconds * 1e3:.1f} ms" for k in engines))
+        last = fresh_step(check=(i == args.steps - 1) and not args.no_verify)
+        step_s.append(sum(r.seconds for r in last.values()))
+        for k in dev_specs:
+            per[k].append(last[k].seconds)
+        log(f"step {i}: " + ", ".join(f"{k} {last[k].seconds * 1e3:.1f} ms" for k in last))
     torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    tuples = sum(last[k].idb_tuples for k in engines)
-    ms_per_step = elapsed / args.steps * 1e3
-    value = tuples / (elapsed / args.steps)
-
-    verified = None
-    if not args.no_verify:
-        log("checking output form")
-        verified = well_formed(engines["reach"], "Reach") and well_formed(engines["sg"], "SG")
+    del arena
+    torch.cuda.empty_cache()
+    med = float(np.median(step_s))
+    tuples = sum(last[k].idb_tuples for k in last)
+    ms_per_step = med * 1e3
+    value = tuples / med
+    verified = None if args.no_verify else bool(forms) and all(forms.values())
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(programs)
+        cpu = cpu_baseline(programs, reach_wl)
 
     line = {
         "metric": METRIC, "value": value, "unit": "tuples/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "u32" if all(last[k].key_bytes == 4 for k in engines) else "u64",
+        "dtype": "u32" if all(last[k].key_bytes == 4 for k in last) else "u64",
         "data": "synthetic",
         "config": {"workload": "reach_rmat16_200k+sg_tree_50k", "engine": "plain_hisa",
+                   "engines": "fresh per step, carved from a caller-owned arena",
                    "reach_tuples": last["reach"].idb_tuples, "sg_tuples": last["sg"].idb_tuples,
                    "reach_iterations": last["reach"].iterations,
                    "sg_iterations": last["sg"].iterations,
@@ -237,28 +391,20 @@ def main():
                    "sg_candidates": last["sg"].candidates},
         "verified": verified,
         "parity_tests": "tests/test_gpu_full.py (same workloads and engine options: BFS and "
-                        "closed-form references, every per-iteration delta)",
+                        "closed-form references, every row and every per-iteration delta)",
         "roofline": None,
         "cpu_baseline": cpu,
-        "per_workload_ms": {k: per[k] / args.steps * 1e3 for k in engines},
-        "phase_ms": {k: last[k].phase_ms for k in engines},
+        "step_ms": [round(x * 1e3, 3) for x in step_s],
+        "per_workload_ms": {k: float(np.median(v)) * 1e3 for k, v in per.items()},
+        "phase_ms": {k: last[k].phase_ms for k in last},
+        "reused_engine": line_reused,
+        "arena_bytes": arena_bytes,
         "kernels": None,
     }
-    if not args.no_variants:
-        # the same fixpoints with the learned position index in place of the
-        # HISA hash probe and the membership search; outputs must be identical
-        line["variants"] = {"learned_index": learned_variant(
-            stream, {"reach": (programs["reach"], reach_wl["edb"], {"Reach": 2}),
-                     "sg": (programs["sg"], sg_wl["edb"], {"SG": 2})},
-            args.steps, value, engines, verify=not args.no_verify)}
-    if not args.no_variants:
-        line["variants"]["autotuned"] = autotuned_variant(stream, specs, args.steps, value,
-                                                          engines, verify=not args.no_verify)
-    for e in engines.values():
-        e.close()
-    engines = {}
+    if variants:
+        line["variants"] = variants
     log("kernel-timed pass")
-    line["roofline"], line["kernels"] = kernel_pass(stream, specs, runs=2)
+    line["roofline"], line["kernels"] = kernel_pass(stream, dev_specs, runs=2)
     if not args.no_variants:
         for name, fn in (("cspa", cspa_variant), ("reach_er_2p22", er_variant),
                          ("nonlinear_er_2p22", nonlinear_variant)):
@@ -408,13 +554,42 @@ def ebm_ablation(stream, steps):
     return out
 
 
-def table6_microbench(stream, reps=10):
+def hip_alloc_init_ms(nbytes, stream):
+    """Milliseconds to allocate a fresh device buffer of nbytes (hipMalloc,
+    which no caching allocator serves) and write every byte once
+    (hipMemsetAsync on the stream, then a synchronisation); the buffer is
+    freed afterwards, outside the time."""
+    import ctypes
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMalloc.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_size_t]
+    hip.hipMemsetAsync.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t,
+                                   ctypes.c_void_p]
+    hip.hipStreamSynchronize.argtypes = [ctypes.c_void_p]
+    hip.hipFree.argtypes = [ctypes.c_void_p]
+    p = ctypes.c_void_p()
+    stream.synchronize()
+    t0 = time.perf_counter()
+    if hip.hipMalloc(ctypes.byref(p), nbytes) != 0:
+        raise MemoryError(f"hipMalloc of {nbytes} bytes failed")
+    rc = hip.hipMemsetAsync(p, 0, nbytes, ctypes.c_void_p(stream.cuda_stream))
+    rc |= hip.hipStreamSynchronize(ctypes.c_void_p(stream.cuda_stream))
+    ms = (time.perf_counter() - t0) * 1e3
+    hip.hipFree(p)
+    if rc != 0:
+        raise RuntimeError("hipMemsetAsync failed")
+    return ms
+
+
+def table6_microbench(stream, reps=100):
     """Sort and merge of random arity-2 tuples (two uniform uint32 columns,
     packed into 64-bit keys, all 64 bits sorted), at the tuple counts of the
-    paper's CPU/GPU comparison table.  Merge: two sorted halves of N/2
-    tuples each into one array of N.  Times are per run (HIP events around
-    the call on the engine's stream) and, for comparison with the table's
-    totals, times 100."""
+    paper's CPU/GPU comparison table, 100 runs each as in the paper.  Merge:
+    two sorted halves of N/2 tuples each into one array of N.  Memory: a
+    fresh device buffer of the tuples' size allocated and written once (the
+    paper's allocation and initialisation column; 10 runs).  Times are per
+    run (HIP events around the call on the engine's stream) and, for
+    comparison with the table's totals, times 100.  The host side of the
+    same table is cpu_baseline.table6_host."""
     import torch
     from paper_2311_02206_amd import Engine
     log("table-6 microbenchmark")
@@ -422,7 +597,7 @@ def table6_microbench(stream, reps=10):
     g = torch.Generator(device="cuda").manual_seed(6)
     rows = []
     try:
-        for n in (1_000_000, 10_000_000, 50_000_000, 100_000_000, 500_000_000):
+        for n in TABLE6_SIZES:
             src = torch.randint(-(1 << 63), (1 << 63) - 1, (n,), dtype=torch.int64,
                                 device="cuda", generator=g)
             work = torch.empty_like(src)
@@ -440,28 +615,32 @@ def table6_microbench(stream, reps=10):
             a = work[:half].clone()
             b = src[half:2 * half].clone()
             e.sort_keys(b, 64)
+            m = torch.empty(2 * half, dtype=torch.int64, device="cuda")
             mt = []
             for r in range(reps + 1):
                 ev0.record(stream)
-                m = e.merge(a, b)
+                e.merge_into(a, b, m)
                 ev1.record(stream)
                 ev1.synchronize()
                 if r:
                     mt.append(ev0.elapsed_time(ev1))
-                del m
-            srt, mrg = sum(st) / len(st), sum(mt) / len(mt)
+            del m, a, b, work, src
+            torch.cuda.empty_cache()
+            al = [hip_alloc_init_ms(n * 8, stream) for _ in range(10)]
+            srt, mrg, mem = (float(np.median(x)) for x in (st, mt, al))
             rows.append({"tuples": n, "sort_ms": round(srt, 3), "merge_ms": round(mrg, 3),
+                         "memory_ms": round(mem, 3),
                          "sort_s_per_100": round(srt / 10, 3), "merge_s_per_100": round(mrg / 10, 3),
+                         "memory_s_per_100": round(mem / 10, 3),
                          "sort_GBps": round(3 * 8 * 8 * n / (srt / 1e3) / 1e9, 1),
                          "merge_GBps": round(2 * 8 * 2 * half / (mrg / 1e3) / 1e9, 1)})
-            log(f"  {n}: sort {srt:.2f} ms, merge {mrg:.2f} ms")
-            del src, work, a, b
-            torch.cuda.empty_cache()
+            log(f"  {n}: sort {srt:.2f} ms, merge {mrg:.2f} ms, memory {mem:.2f} ms")
     finally:
         e.close()
-    return {"reps": reps, "key_bits": 64, "rows": rows,
-            "note": "sort_GBps counts 8 radix passes of 24 B per key (hist read, scatter read "
-                    "and write); merge_GBps counts one read and one write per key"}
+    return {"reps": reps, "memory_reps": 10, "key_bits": 64, "rows": rows,
+            "note": "medians of the runs; sort_GBps counts 8 radix passes of 24 B per key "
+                    "(histogram read, scatter read and write); merge_GBps counts one read "
+                    "and one write per key; host side: cpu_baseline.table6_host"}
 
 
 def autotuned_variant(stream, specs, steps, plain_value, plain_engines, verify=True):

@@ -335,6 +335,16 @@ int hl_iteration_counts(hl_engine* e, const char* name, int32_t which, uint64_t*
 int hl_kernel_stats(hl_engine* e, int32_t kernel, uint64_t* launches, double* ms,
                     uint64_t* algorithmic_bytes);
 
+/* Join outputs of rule `rule` (0-based, in program text order) over the
+ * last hl_run: *join_outputs = outputs of the rule's last join (its
+ * candidates before `!=` filters and dedup; for a one-atom body, its outer
+ * tuples), summed over iterations and over the rule's delta variants (one
+ * per IDB body atom, Section 5.1); *intermediate = outputs of its earlier
+ * joins (the temporarily materialised results of Section 5.2).  Fused
+ * iterations (HL_FLAG_FUSED) are not counted here.  HL_E_INVALID for a rule
+ * index beyond the program, HL_E_STATE before hl_run. */
+int hl_rule_stats(hl_engine* e, uint32_t rule, uint64_t* join_outputs, uint64_t* intermediate);
+
 /* Text of the most recent error of e (never NULL; "" when none). */
 const char* hl_last_error(hl_engine* e);
 

@@ -30,7 +30,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SO = os.path.join(_HERE, "_build", "liboracle.so")
-_SOURCES = ("semi_naive.cpp", "closure_check.cpp")
+_SOURCES = ("semi_naive.cpp", "closure_check.cpp", "host_sort.cpp")
 _lib = None
 
 
@@ -83,6 +83,12 @@ def lib():
         L.or_reach_verify_many.restype = ctypes.c_int64
         L.or_sg_tree_verify.argtypes = [u32, vp, u64, vp, u64, ctypes.c_int, i64p]
         L.or_sg_tree_verify.restype = ctypes.c_int64
+        L.or_host_sort_u64.argtypes = [vp, vp, u64, ctypes.c_int]
+        L.or_host_sort_u64.restype = ctypes.c_double
+        L.or_host_merge_u64.argtypes = [vp, u64, vp, u64, vp, ctypes.c_int]
+        L.or_host_merge_u64.restype = ctypes.c_double
+        L.or_host_alloc_init.argtypes = [u64, ctypes.c_int]
+        L.or_host_alloc_init.restype = ctypes.c_double
         _lib = L
     return _lib
 
@@ -329,3 +335,30 @@ def sg_tree_verify(edges: np.ndarray, rows: np.ndarray, threads: int | None = No
     if r == -3:
         raise ValueError("sg_tree_verify: the edges are not a rooted tree")
     return int(r), int(bad.value)
+
+
+def host_sort_u64(keys: np.ndarray, threads: int | None = None) -> float:
+    """Sorts a uint64 array in place on ``threads`` host threads (the host
+    side of the sort/merge/memory microbenchmark); returns the seconds."""
+    assert keys.dtype == np.uint64 and keys.flags.c_contiguous
+    tmp = np.empty_like(keys)
+    return lib().or_host_sort_u64(keys.ctypes.data, tmp.ctypes.data, keys.size,
+                                  _threads(threads))
+
+
+def host_merge_u64(a: np.ndarray, b: np.ndarray, out: np.ndarray,
+                   threads: int | None = None) -> float:
+    """out = merge of ascending uint64 arrays a and b on host threads;
+    returns the seconds."""
+    assert a.dtype == b.dtype == out.dtype == np.uint64 and out.size == a.size + b.size
+    return lib().or_host_merge_u64(a.ctypes.data, a.size, b.ctypes.data, b.size,
+                                   out.ctypes.data, _threads(threads))
+
+
+def host_alloc_init(nbytes: int, threads: int | None = None) -> float:
+    """Seconds to allocate a fresh host buffer of nbytes and write every
+    byte once on host threads."""
+    s = lib().or_host_alloc_init(nbytes, _threads(threads))
+    if s < 0:
+        raise MemoryError(f"host allocation of {nbytes} bytes failed")
+    return s

@@ -217,18 +217,39 @@ class EventTimer : public hl::LaunchTimer {
   void begin(int kernel, hipStream_t s) override {
     hipEvent_t a = get();
     (void)hipEventRecord(a, s);
-    open_.push_back({kernel, a, nullptr, 0});
+    open_.push_back({kernel, a, nullptr, 0, -1});
   }
-  void end(int kernel, hipStream_t s, u64 bytes) override {
+  void end(int kernel, hipStream_t s, u64 bytes, const u64* dev) override {
     hipEvent_t b = get();
     (void)hipEventRecord(b, s);
     if (!open_.empty() && open_.back().kernel == kernel && !open_.back().b) {
       open_.back().b = b;
       open_.back().bytes = bytes;
+      open_.back().slot = dev ? int(dev - dev_) : -1;
     }
+  }
+  // A zeroed device counter for the launch about to be timed, or null when
+  // every counter of this collection period is taken (the launch then
+  // counts its host-known bytes only).
+  u64* device_counter(hipStream_t s) override {
+    if (!dev_) {
+      if (hipMalloc(&dev_, kSlots * sizeof(u64)) != hipSuccess) {
+        (void)hipGetLastError();
+        dev_ = nullptr;
+        return nullptr;
+      }
+    }
+    if (slots_used_ == kSlots) return nullptr;
+    u64* c = dev_ + slots_used_++;
+    if (hl::fill_zero(c, sizeof(u64), s) != hipSuccess) fail(HL_E_DEVICE, "fill_zero failed");
+    return c;
   }
   // After a synchronisation of the stream.
   void collect() {
+    if (slots_used_ > 0) {
+      if (hipMemcpy(host_, dev_, slots_used_ * sizeof(u64), hipMemcpyDeviceToHost) != hipSuccess)
+        fail(HL_E_DEVICE, "kernel byte counters could not be read");
+    }
     for (const Rec& r : open_) {
       if (!r.b) continue;
       float ms = 0.f;
@@ -236,28 +257,36 @@ class EventTimer : public hl::LaunchTimer {
         Total& t = totals[r.kernel];
         ++t.launches;
         t.ms += ms;
-        t.bytes += r.bytes;
+        t.bytes += r.bytes + (r.slot >= 0 ? host_[r.slot] : 0);
       }
     }
     open_.clear();
     used_ = 0;
+    slots_used_ = 0;
   }
   void reset() {
     open_.clear();
     used_ = 0;
+    slots_used_ = 0;
     for (Total& t : totals) t = Total{};
   }
   ~EventTimer() override {
     for (hipEvent_t ev : pool_) (void)hipEventDestroy(ev);
+    if (dev_) (void)hipFree(dev_);
   }
   Total totals[hl::K_COUNT];
 
  private:
+  static constexpr int kSlots = 1024;
   struct Rec {
     int kernel;
     hipEvent_t a, b;
     u64 bytes;
+    int slot;
   };
+  u64* dev_ = nullptr;
+  u64 host_[kSlots] = {};
+  int slots_used_ = 0;
   hipEvent_t get() {
     if (used_ == pool_.size()) {
       hipEvent_t ev;
@@ -279,7 +308,8 @@ constexpr int kZeroVar = -2;
 
 struct Atom {
   int rel = -1;
-  int arg[2] = {-1, -1};  // variable ids; wildcards get fresh ids
+  int n = 0;                      // arity
+  int arg[4] = {-1, -1, -1, -1};  // variable ids; wildcards get fresh ids
 };
 
 struct Rule {
@@ -307,8 +337,33 @@ struct Plan {
   std::vector<Step> steps;  // empty: projection only
 };
 
+// A chain of joins over relations of arity up to 4 (wide plans): the
+// carried tuple holds up to 4 live variables, and each join probes an index
+// of its inner relation on every column it shares with the carried tuple.
+struct WStep {
+  int inner_rel = -1;
+  int ix = -1;  // into rels[inner_rel].widx
+  hl::WideSpec ws{};
+};
+
+struct WPlan {
+  int rule = -1;
+  int head = -1;
+  int outer_rel = -1;
+  bool outer_delta = false;
+  hl::WideSpec proj{};       // for a body of one atom (proj.ai == 0)
+  std::vector<WStep> steps;  // empty: projection only
+  int max_cols = 0;          // widest carried tuple
+};
+
 struct Index {
   bool used = false;
+  // indexes of relations of arity 3-4 (wide plans): column c of the index
+  // tuple is column perm[c] of the relation, the first nj are the join
+  // columns; an identity permutation indexes full itself
+  int perm[4] = {0, 1, 2, 3};
+  int nj = 1;
+  bool identity = true;
   Buf keys, spare;  // column 1 only: the relation with columns swapped
   u64 n = 0;
   Buf table;
@@ -338,6 +393,7 @@ struct Relation {
   Buf full, full_spare, delta, cand;
   u64 n_full = 0, n_delta = 0, n_cand = 0;
   Index idx[2];
+  std::vector<Index> widx;  // indexes of wide plans
   std::vector<u64> delta_counts, new_counts;
   // in-tile dedup of the joins deriving this relation: on while they made
   // at least 1.5 outputs per distinct new tuple (raw_cand: this iteration's
@@ -431,6 +487,13 @@ struct hl_engine {
   std::vector<u64> batch_base;
   std::vector<u32> batch_rows_tmp;
   std::vector<Plan> plans0, plansR;  // iteration 0 / recursive plans
+  // programs with relations of arity 3-4: wide plans instead
+  bool wide = false;
+  std::vector<WPlan> wplans0, wplansR;
+  // per rule of the program, over the last run's non-fused iterations: the
+  // outputs of its last join (its candidates before filters) and of its
+  // earlier joins (the materialised intermediate results)
+  std::vector<u64> rule_out, rule_mid;
   bool ran = false;
 
   // run state
@@ -569,7 +632,7 @@ struct hl_engine {
     int k = 0;
     for (;;) {
       std::string v = lx.ident();
-      if (k >= 2) fail(HL_E_INVALID, "too many arguments for " + name);
+      if (k >= 4) fail(HL_E_INVALID, "too many arguments for " + name);
       if (v == "_") {
         if (head) fail(HL_E_INVALID, "wildcard in a rule head");
         a.arg[k] = nvars++;
@@ -584,6 +647,8 @@ struct hl_engine {
       break;
     }
     if (k != rels[a.rel].arity) fail(HL_E_INVALID, "arity mismatch for " + name);
+    a.n = k;
+    // binary plans store a unary tuple x as the pair (x, 0)
     if (k == 1) a.arg[1] = kZeroVar;
     return a;
   }
@@ -613,9 +678,10 @@ struct hl_engine {
         break;
       }
       std::set<int> bodyvars;
-      for (auto& a : r.body) bodyvars.insert({a.arg[0], a.arg[1]});
-      for (int v : r.head.arg)
-        if (v != kZeroVar && !bodyvars.count(v))
+      for (auto& a : r.body)
+        for (int k = 0; k < a.n; ++k) bodyvars.insert(a.arg[k]);
+      for (int k = 0; k < r.head.n; ++k)
+        if (const int v = r.head.arg[k]; !bodyvars.count(v))
           fail(HL_E_INVALID, "head variable not bound in the body");
       for (auto& f : filters) {
         auto a = vars.find(f.first), b = vars.find(f.second);
@@ -739,9 +805,208 @@ struct hl_engine {
     return p;
   }
 
+  // ------------------------------------------------- wide plans
+  // Programs with a relation of arity 3 or 4 (the paper's requirement R3,
+  // Section 3): every join probes an index of its inner relation on all the
+  // columns it shares with the carried tuple (a key of several columns,
+  // Section 5.1), and the carried tuple holds up to 4 live variables.
+
+  // Index of relation `rel` with columns perm[0..a) and nj join columns
+  // (added if new).
+  int wide_index(int rel, const int* perm, int a, int nj) {
+    Relation& R = rels[rel];
+    for (size_t k = 0; k < R.widx.size(); ++k) {
+      const Index& ix = R.widx[k];
+      if (ix.nj == nj && std::equal(perm, perm + a, ix.perm)) return int(k);
+    }
+    Index ix;
+    ix.used = true;
+    ix.nj = nj;
+    ix.identity = true;
+    for (int c = 0; c < 4; ++c) ix.perm[c] = c < a ? perm[c] : c;
+    for (int c = 0; c < a; ++c) ix.identity = ix.identity && perm[c] == c;
+    R.widx.push_back(ix);
+    return int(R.widx.size()) - 1;
+  }
+
+  WPlan plan_rule_wide(int rule_id, int first, bool outer_delta) {
+    const Rule& r = rules[rule_id];
+    WPlan p;
+    p.rule = rule_id;
+    p.head = r.head.rel;
+    p.outer_rel = r.body[first].rel;
+    p.outer_delta = outer_delta;
+    auto unsupported = [&](const std::string& why) {
+      fail(HL_E_UNSUPPORTED, "rule '" + r.text + "': " + why);
+    };
+    const Atom& a0 = r.body[first];
+    // the carried tuple: the variable of each of its columns
+    std::vector<int> cur(a0.arg, a0.arg + a0.n);
+    p.max_cols = a0.n;
+    // a variable repeated in the outer atom: its columns must be equal
+    std::vector<std::pair<int, int>> eqs;
+    for (int i = 0; i < a0.n; ++i)
+      for (int j = 0; j < i; ++j)
+        if (cur[i] == cur[j]) {
+          eqs.push_back({j, i});
+          break;
+        }
+    std::vector<bool> applied(r.neq.size(), false);
+    auto src_of = [](int v, const std::vector<int>& carried, const std::vector<int>& inner) {
+      for (size_t k = 0; k < carried.size(); ++k)
+        if (carried[k] == v) return int(k);
+      for (size_t k = 0; k < inner.size(); ++k)
+        if (inner[k] == v) return 4 + int(k);
+      return -1;
+    };
+    auto add_filters = [&](hl::WideSpec& ws, const std::vector<int>& carried,
+                           const std::vector<int>& inner) {
+      for (size_t f = 0; f < r.neq.size(); ++f) {
+        if (applied[f]) continue;
+        const int a = src_of(r.neq[f].first, carried, inner);
+        const int b = src_of(r.neq[f].second, carried, inner);
+        if (a < 0 || b < 0) continue;
+        if (ws.nf >= 4) unsupported("more than four filters apply at one join");
+        ws.fa[ws.nf] = a;
+        ws.fb[ws.nf] = b;
+        ++ws.nf;
+        applied[f] = true;
+      }
+    };
+    auto add_eq = [&](hl::WideSpec& ws, int a, int b) {
+      if (ws.ne >= 4) unsupported("more than four equality tests apply at one join");
+      ws.ea[ws.ne] = a;
+      ws.eb[ws.ne] = b;
+      ++ws.ne;
+    };
+    auto set_out = [&](hl::WideSpec& ws, const std::vector<int>& vars,
+                       const std::vector<int>& carried, const std::vector<int>& inner) {
+      ws.nout = int(vars.size());
+      for (size_t t = 0; t < vars.size(); ++t) {
+        ws.src[t] = src_of(vars[t], carried, inner);
+        if (ws.src[t] < 0) unsupported("head variable lost");
+      }
+    };
+    auto in_cur = [&](int v) { return std::find(cur.begin(), cur.end(), v) != cur.end(); };
+    const std::vector<int> head(r.head.arg, r.head.arg + r.head.n);
+    std::vector<int> remaining;
+    for (int j = 0; j < int(r.body.size()); ++j)
+      if (j != first) remaining.push_back(j);
+    if (remaining.empty()) {
+      hl::WideSpec& ws = p.proj;
+      ws.ao = a0.n;
+      for (auto& e : eqs) add_eq(ws, e.first, e.second);
+      add_filters(ws, cur, {});
+      set_out(ws, head, cur, {});
+    }
+    while (!remaining.empty()) {
+      // the atom sharing the most variables with the carried tuple
+      int pick = -1, best = 0;
+      for (size_t q = 0; q < remaining.size(); ++q) {
+        const Atom& b = r.body[remaining[q]];
+        std::set<int> shared;
+        for (int k = 0; k < b.n; ++k)
+          if (in_cur(b.arg[k])) shared.insert(b.arg[k]);
+        if (int(shared.size()) > best) {
+          best = int(shared.size());
+          pick = int(q);
+        }
+      }
+      if (pick < 0) unsupported("a body atom shares no variable with the carried tuple");
+      const Atom& b = r.body[remaining[pick]];
+      remaining.erase(remaining.begin() + pick);
+      // join columns first (every column whose variable is carried), then
+      // the others, each group in atom order
+      int perm[4] = {0, 1, 2, 3}, np = 0;
+      for (int k = 0; k < b.n; ++k)
+        if (in_cur(b.arg[k])) perm[np++] = k;
+      const int nj = np;
+      for (int k = 0; k < b.n; ++k)
+        if (!in_cur(b.arg[k])) perm[np++] = k;
+      WStep st;
+      st.inner_rel = b.rel;
+      st.ix = wide_index(b.rel, perm, b.n, nj);
+      hl::WideSpec& ws = st.ws;
+      ws.ao = int(cur.size());
+      ws.ai = b.n;
+      ws.nj = nj;
+      std::vector<int> inner(b.n);
+      for (int c = 0; c < b.n; ++c) inner[c] = b.arg[perm[c]];
+      for (int t = 0; t < nj; ++t) ws.jo[t] = src_of(inner[t], cur, {});
+      for (auto& e : eqs) add_eq(ws, e.first, e.second);
+      eqs.clear();
+      // a new variable repeated in the inner atom: its columns must be equal
+      for (int c = nj; c < b.n; ++c)
+        for (int c2 = nj; c2 < c; ++c2)
+          if (inner[c] == inner[c2]) {
+            add_eq(ws, 4 + c2, 4 + c);
+            break;
+          }
+      add_filters(ws, cur, inner);
+      if (remaining.empty()) {
+        set_out(ws, head, cur, inner);
+      } else {
+        std::set<int> need(head.begin(), head.end());
+        for (int q : remaining)
+          for (int k = 0; k < r.body[q].n; ++k) need.insert(r.body[q].arg[k]);
+        for (size_t f = 0; f < r.neq.size(); ++f)
+          if (!applied[f]) need.insert({r.neq[f].first, r.neq[f].second});
+        std::vector<int> keep;
+        for (const std::vector<int>* side : {&cur, &inner})
+          for (int v : *side)
+            if (need.count(v) && std::find(keep.begin(), keep.end(), v) == keep.end())
+              keep.push_back(v);
+        if (keep.size() > 4) unsupported("more than four variables stay live between joins");
+        if (keep.empty()) unsupported("no variable carried to the next join");
+        set_out(ws, keep, cur, inner);
+        cur = keep;
+        p.max_cols = std::max(p.max_cols, int(keep.size()));
+      }
+      p.steps.push_back(st);
+    }
+    for (size_t f = 0; f < applied.size(); ++f)
+      if (!applied[f]) unsupported("a filter was never applicable");
+    return p;
+  }
+
+  void build_wide_plans() {
+    for (Relation& R : rels) R.widx.clear();
+    for (int k = 0; k < int(rules.size()); ++k) {
+      const Rule& r = rules[k];
+      bool edb_only = true;
+      for (auto& a : r.body) edb_only &= rels[a.rel].edb;
+      if (edb_only) {
+        wplans0.push_back(plan_rule_wide(k, 0, false));
+      } else {
+        for (int t = 0; t < int(r.body.size()); ++t)
+          if (!rels[r.body[t].rel].edb) wplansR.push_back(plan_rule_wide(k, t, true));
+      }
+    }
+    fz_plans = false;
+  }
+
+  // Widest tuple of a wide program: relations and carried tuples.
+  int wide_cols() const {
+    int c = 0;
+    for (const Relation& R : rels) c = std::max(c, R.arity);
+    for (auto* ps : {&wplans0, &wplansR})
+      for (const WPlan& p : *ps) c = std::max(c, p.max_cols);
+    return c;
+  }
+
   void build_plans() {
     plans0.clear();
     plansR.clear();
+    wplans0.clear();
+    wplansR.clear();
+    int max_arity = 0;
+    for (const Relation& R : rels) max_arity = std::max(max_arity, R.arity);
+    wide = max_arity >= 3;
+    if (wide) {
+      if (!batch_base.empty()) fail(HL_E_UNSUPPORTED, "batches of relations of arity above 2");
+      build_wide_plans();
+      return;
+    }
     for (int k = 0; k < int(rules.size()); ++k) {
       const Rule& r = rules[k];
       bool edb_only = true;
@@ -788,11 +1053,19 @@ struct hl_engine {
     HIPCK(hl::hisa_count_runs<K>(keys, ix.n, w, d_runs, stream));
   }
 
+  // Significant bits of R's packed tuples.
+  int kbits(const Relation& R) const { return (wide ? R.arity : 2) * w; }
+
   template <typename K>
   void fit_model(Relation& R, int col) {
     Index& ix = R.idx[col];
     if (col == 0) ix.n = R.n_full;
-    const K* keys = col == 0 ? kp<K>(R.full) : kp<K>(ix.keys);
+    fit_index_model<K>(R, ix, col == 0 ? kp<K>(R.full) : kp<K>(ix.keys));
+  }
+
+  // Learned model of index ix of R over its n sorted keys.
+  template <typename K>
+  void fit_index_model(Relation& R, Index& ix, const K* keys) {
     ix.lm_ok = false;
     if (ix.n >= (u64(1) << 32)) {
       // positions are 32-bit: a join inner this large is unsupported, a
@@ -801,11 +1074,11 @@ struct hl_engine {
                                               " has 2^32 or more tuples");
       return;
     }
-    const int bits = hl::learned_bits(ix.n, 2 * w);
+    const int bits = hl::learned_bits(ix.n, kbits(R));
     const u64 bytes = hl::learned_bytes(bits);
     reserve(ix.lm, bytes, 2 * bytes);  // the table doubles as the relation grows
     hl::LearnedView<K> v{};
-    HIPCK(hl::learned_fit<K>(keys, ix.n, 2 * w, bits, ix.lm.p, stream, &v, kt()));
+    HIPCK(hl::learned_fit<K>(keys, ix.n, kbits(R), bits, ix.lm.p, stream, &v, kt()));
     ix.lm_keys = v.keys;
     ix.lm_n = v.n;
     ix.lm_shift = v.shift;
@@ -866,6 +1139,99 @@ struct hl_engine {
       finish_index<K>(rels[todo[q].first], todo[q].second, h_small[q]);
   }
 
+  // Sorted array of wide index ix of R (full itself for the identity
+  // permutation).
+  template <typename K>
+  const K* wide_keys(Relation& R, Index& ix) {
+    return ix.identity ? kp<K>(R.full) : kp<K>(ix.keys);
+  }
+
+  // Wide index ix of R takes the new tuples src[0, n_src): permuted, sorted
+  // and merged into its array (built from them when from_scratch).
+  template <typename K>
+  void update_wide(Relation& R, Index& ix, const K* src, u64 n_src, bool from_scratch) {
+    if (ix.identity) {
+      ix.n = R.n_full;
+      return;
+    }
+    if (n_src == 0) {
+      if (from_scratch) ix.n = 0;
+      return;
+    }
+    const int bits = kbits(R);
+    reserve_grow(alt, n_src * sizeof(K));
+    reserve_grow(tmp[0], n_src * sizeof(K));
+    HIPCK(hl::wide_permute<K>(src, n_src, R.arity, w, ix.perm, kp<K>(tmp[0]), stream));
+    reserve(ws, hl::sort_workspace_bytes(n_src), hl::sort_workspace_bytes(n_src) * 2);
+    K* sorted = nullptr;
+    HIPCK(hl::radix_sort<K>(kp<K>(tmp[0]), kp<K>(alt), n_src, bits, ws.p, stream, &sorted, kt()));
+    if (from_scratch || ix.n == 0) {
+      reserve(ix.keys, n_src * sizeof(K), u64(double(n_src) * sizeof(K) * 1.5));
+      HIPCK(hipMemcpyAsync(ix.keys.p, sorted, n_src * sizeof(K), hipMemcpyDeviceToDevice, stream));
+      ix.n = n_src;
+      return;
+    }
+    const u64 total = ix.n + n_src;
+    reserve(ix.spare, total * sizeof(K), u64((double(ix.n) + ebm_k * double(n_src)) * sizeof(K)));
+    reserve(ws, hl::merge_workspace_bytes(ix.n, n_src), hl::merge_workspace_bytes(ix.n, n_src) * 2);
+    HIPCK(hl::merge<K>(kp<K>(ix.keys), ix.n, sorted, n_src, kp<K>(ix.spare), ws.p, stream, kt()));
+    std::swap(ix.keys, ix.spare);
+    ix.n = total;
+  }
+
+  // Hash tables (one synchronisation for the run counts of all of them) or
+  // learned models of every wide index of the listed relations.
+  template <typename K>
+  void refresh_wide(const std::vector<int>& which) {
+    std::vector<std::pair<int, int>> todo;
+    for (int r : which)
+      for (int k = 0; k < int(rels[r].widx.size()); ++k) todo.push_back({r, k});
+    if (todo.empty()) return;
+    for (auto& rk : todo) {
+      Relation& R = rels[rk.first];
+      Index& ix = R.widx[rk.second];
+      if (ix.identity) ix.n = R.n_full;
+      if (ix.n >= (u64(1) << 32))
+        fail(HL_E_UNSUPPORTED, "indexed relation " + R.name + " has 2^32 or more tuples");
+    }
+    if (learned()) {
+      for (auto& rk : todo) {
+        Relation& R = rels[rk.first];
+        Index& ix = R.widx[rk.second];
+        fit_index_model<K>(R, ix, wide_keys<K>(R, ix));
+      }
+      return;
+    }
+    if (todo.size() > kChunkSlots) fail(HL_E_UNSUPPORTED, "too many indexes");
+    for (size_t q = 0; q < todo.size(); ++q) {
+      Relation& R = rels[todo[q].first];
+      Index& ix = R.widx[todo[q].second];
+      HIPCK(hl::wide_count_runs<K>(wide_keys<K>(R, ix), ix.n, (R.arity - ix.nj) * w,
+                                   d_small + q, stream));
+    }
+    HIPCK(hipMemcpyAsync(h_small, d_small, todo.size() * sizeof(u64), hipMemcpyDeviceToHost,
+                         stream));
+    sync();
+    for (size_t q = 0; q < todo.size(); ++q) {
+      Relation& R = rels[todo[q].first];
+      Index& ix = R.widx[todo[q].second];
+      const u64 runs = h_small[q];
+      ix.runs = runs;
+      if (ix.n == 0) {
+        ix.cap = 0;
+        continue;
+      }
+      u64 cap = u64(std::ceil(double(runs) / load_factor));
+      cap = std::max(cap, runs + 1);
+      cap = std::max<u64>(cap, 16);
+      reserve(ix.table, cap * sizeof(Slot), cap * sizeof(Slot) * 2);
+      ix.cap = cap;
+      HIPCK(hl::fill_zero(ix.table.p, cap * sizeof(Slot), stream));
+      HIPCK(hl::wide_hisa_build<K>(wide_keys<K>(R, ix), ix.n, (R.arity - ix.nj) * w,
+                                   static_cast<Slot*>(ix.table.p), cap, stream, kt()));
+    }
+  }
+
   // Column-1 index copy of R: merge in the swapped new delta (or build it
   // from full for an EDB relation).
   template <typename K>
@@ -906,15 +1272,20 @@ struct hl_engine {
       edbs.push_back(k);
       R.n_full = 0;
       R.idx[0].n = R.idx[1].n = 0;
+      for (Index& ix : R.widx) ix.n = ix.cap = 0;
       if (R.n_raw == 0) continue;
       if (R.n_raw >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "EDB relation with 2^32 or more rows");
       reserve_grow(R.cand, R.n_raw * sizeof(K));
       reserve_grow(alt, R.n_raw * sizeof(K));
-      HIPCK(hl::pack_rows<K>(static_cast<const u32*>(R.raw.p), R.n_raw, R.arity, w, kp<K>(R.cand),
-                             stream));
+      if (wide)
+        HIPCK(hl::wide_pack<K>(static_cast<const u32*>(R.raw.p), R.n_raw, R.arity, w,
+                               kp<K>(R.cand), stream));
+      else
+        HIPCK(hl::pack_rows<K>(static_cast<const u32*>(R.raw.p), R.n_raw, R.arity, w,
+                               kp<K>(R.cand), stream));
       reserve(ws, hl::sort_workspace_bytes(R.n_raw), hl::sort_workspace_bytes(R.n_raw) * 2);
       K* sorted = nullptr;
-      HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_raw, 2 * w, ws.p, stream, &sorted,
+      HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_raw, kbits(R), ws.p, stream, &sorted,
                               kt()));
       K* other = sorted == kp<K>(R.cand) ? kp<K>(alt) : kp<K>(R.cand);
       reserve(R.full, R.n_raw * sizeof(K), R.n_raw * sizeof(K));
@@ -927,8 +1298,157 @@ struct hl_engine {
       R.n_full = h_small[0];
       R.idx[0].n = R.n_full;
       if (R.idx[1].used) update_swapped<K>(R, kp<K>(R.full), R.n_full, true);
+      for (Index& ix : R.widx) update_wide<K>(R, ix, kp<K>(R.full), R.n_full, true);
     }
-    refresh_indexes<K>(edbs);
+    if (wide) refresh_wide<K>(edbs);
+    else refresh_indexes<K>(edbs);
+  }
+
+  // Evaluates one wide plan, appending head tuples to the head's
+  // candidates: the same probe / scan / load-balanced expand as run_plan
+  // (chunked likewise when the last join's outputs exceed one sort), with
+  // keys of several columns and tuples of up to 4 columns.
+  template <typename K>
+  void run_wide_plan(const WPlan& p) {
+    Relation& O = rels[p.outer_rel];
+    Relation& H = rels[p.head];
+    const K* cur = p.outer_delta ? kp<K>(O.delta) : kp<K>(O.full);
+    u64 n = p.outer_delta ? O.n_delta : O.n_full;
+    if (n == 0) return;
+    u64* d_cursor = d_small;
+    if (p.steps.empty()) {
+      hl::WideSpec ws = p.proj;
+      ws.w = w;
+      H.raw_cand += n;
+      st.join_outputs += n;
+      rule_out[p.rule] += n;
+      reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + n) * sizeof(K));
+      const bool filtered = ws.nf > 0 || ws.ne > 0;
+      if (filtered) {
+        h_small[0] = H.n_cand;
+        HIPCK(hipMemcpyAsync(d_cursor, h_small, sizeof(u64), hipMemcpyHostToDevice, stream));
+      }
+      HIPCK(hl::wide_project<K>(cur, n, ws, kp<K>(H.cand) + (filtered ? 0 : H.n_cand), d_cursor,
+                                stream));
+      if (filtered) {
+        HIPCK(hipMemcpyAsync(h_small, d_cursor, sizeof(u64), hipMemcpyDeviceToHost, stream));
+        sync();
+        st.candidates += h_small[0] - H.n_cand;
+        H.n_cand = h_small[0];
+      } else {
+        H.n_cand += n;
+        st.candidates += n;
+      }
+      return;
+    }
+    int ping = 0;
+    for (size_t q = 0; q < p.steps.size(); ++q) {
+      const WStep& s = p.steps[q];
+      Relation& I = rels[s.inner_rel];
+      Index& ix = I.widx[s.ix];
+      if (ix.n == 0 || (learned() ? !ix.lm_ok : ix.cap == 0)) return;
+      const K* inner = wide_keys<K>(I, ix);
+      hl::WideSpec ws = s.ws;
+      ws.w = w;
+      if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "join outer side of 2^32 or more tuples");
+      const bool last = q + 1 == p.steps.size();
+      reserve_grow(join_start, n * sizeof(u32));
+      reserve_grow(join_len, n * sizeof(u32));
+      reserve_grow(join_off, n * sizeof(u64));
+      if (learned())
+        HIPCK(hl::wide_probe_learned<K>(cur, n, ws, ix.view<K>(), static_cast<u32*>(join_start.p),
+                                        static_cast<u32*>(join_len.p), stream, kt()));
+      else
+        HIPCK(hl::wide_probe<K>(cur, n, ws, static_cast<const Slot*>(ix.table.p), ix.cap, inner,
+                                static_cast<u32*>(join_start.p), static_cast<u32*>(join_len.p),
+                                stream, kt()));
+      reserve(this->ws, hl::scan_workspace_bytes(n), hl::scan_workspace_bytes(n) * 2);
+      HIPCK(hl::scan_u32_u64(static_cast<u32*>(join_len.p), n, static_cast<u64*>(join_off.p),
+                             d_small + 1, this->ws.p, stream));
+      HIPCK(hipMemcpyAsync(h_small + 1, d_small + 1, sizeof(u64), hipMemcpyDeviceToHost, stream));
+      sync();
+      const u64 total = h_small[1];
+      if (total == 0) return;
+      (last ? rule_out : rule_mid)[p.rule] += total;
+      if (last) {
+        H.raw_cand += total;
+        st.join_outputs += total;
+      }
+      const bool filtered = ws.nf > 0 || ws.ne > 0;
+      const u64 cap = u64(1) << sort_chunk_log2;
+      const u64 nt = hl::join_tiles(n, total, 8);
+      reserve_grow(join_parts, hl::join_parts(n, total, 8) * sizeof(u64));
+      u64* parts = static_cast<u64*>(join_parts.p);
+      HIPCK(hl::join_partition(static_cast<u64*>(join_off.p), n, total, parts, stream, 8));
+      if (last && total > cap) {
+        // outputs beyond one sort: a range of tiles at a time, each
+        // absorbed into the head's pending delta
+        const u64 tile_out = hl::join_tile_outputs(8);
+        const u64 per = std::max<u64>(1, cap / tile_out);
+        reserve_grow(jchunk, per * tile_out * sizeof(K));
+        for (u64 t0 = 0; t0 < nt; t0 += per) {
+          const u64 tiles = std::min(per, nt - t0);
+          if (filtered) {
+            h_small[0] = 0;
+            HIPCK(hipMemcpyAsync(d_cursor, h_small, sizeof(u64), hipMemcpyHostToDevice, stream));
+          }
+          HIPCK(hl::wide_expand_tiles<K>(cur, n, static_cast<u64*>(join_off.p),
+                                         static_cast<u32*>(join_start.p), inner, total, ws, parts,
+                                         t0, tiles, kp<K>(jchunk), d_cursor, stream, kt()));
+          u64 m;
+          if (filtered) {
+            HIPCK(hipMemcpyAsync(h_small, d_cursor, sizeof(u64), hipMemcpyDeviceToHost, stream));
+            sync();
+            m = h_small[0];
+          } else {
+            const u64 t1 = t0 + tiles;
+            HIPCK(hipMemcpyAsync(h_small + 2, parts + t0, sizeof(u64), hipMemcpyDeviceToHost,
+                                 stream));
+            HIPCK(hipMemcpyAsync(h_small + 3, parts + t1, sizeof(u64), hipMemcpyDeviceToHost,
+                                 stream));
+            sync();
+            const u64 j0 = std::min(t0 * tile_out, n + total) - h_small[2];
+            const u64 j1 = std::min(t1 * tile_out, n + total) - h_small[3];
+            m = j1 - j0;
+          }
+          st.candidates += m;
+          absorb<K>(H, kp<K>(jchunk), m);
+        }
+        return;
+      }
+      K* out;
+      u64 base = 0;
+      if (last) {
+        reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + total) * sizeof(K));
+        out = kp<K>(H.cand);
+        base = H.n_cand;
+      } else {
+        reserve_grow(tmp[ping], total * sizeof(K));
+        out = kp<K>(tmp[ping]);
+      }
+      if (filtered) {
+        h_small[0] = base;
+        HIPCK(hipMemcpyAsync(d_cursor, h_small, sizeof(u64), hipMemcpyHostToDevice, stream));
+      }
+      HIPCK(hl::wide_expand_tiles<K>(cur, n, static_cast<u64*>(join_off.p),
+                                     static_cast<u32*>(join_start.p), inner, total, ws, parts, 0,
+                                     nt, filtered ? out : out + base, d_cursor, stream, kt()));
+      u64 produced = total;
+      if (filtered) {
+        HIPCK(hipMemcpyAsync(h_small, d_cursor, sizeof(u64), hipMemcpyDeviceToHost, stream));
+        sync();
+        produced = h_small[0] - base;
+      }
+      if (last) {
+        H.n_cand += produced;
+        st.candidates += produced;
+      } else {
+        cur = kp<K>(tmp[ping]);
+        n = produced;
+        ping ^= 1;
+        if (n == 0) return;
+      }
+    }
   }
 
   // Evaluates one plan, appending head tuples to the head's candidates.
@@ -945,6 +1465,7 @@ struct hl_engine {
       js.w = w;
       H.raw_cand += n;
       st.join_outputs += n;
+      rule_out[p.rule] += n;
       reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + n) * sizeof(K));
       const bool filtered = js.fa >= 0 || js.ea >= 0;
       if (filtered) {
@@ -1013,6 +1534,7 @@ struct hl_engine {
       sync();
       const u64 total = h_small[1];
       if (total == 0) return;
+      (last ? rule_out : rule_mid)[p.rule] += total;
       if (last) {
         H.raw_cand += total;
         st.join_outputs += total;
@@ -1145,6 +1667,7 @@ struct hl_engine {
     if (total == 0) return true;
     // the nested form counts kept outputs only: they are its join outputs
     H.raw_cand += total;
+    rule_out[p.rule] += total;
     st.join_outputs += total;
     reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + total) * sizeof(K));
     HIPCK(hl::join_nested<K>(cur, n, nj, nullptr, static_cast<u64*>(join_off.p), nullptr, nullptr,
@@ -1154,12 +1677,27 @@ struct hl_engine {
     return true;
   }
 
-  // Model of R's full relation for the set difference, if it has a current one.
+  // Model of R's full relation for the set difference of n_cand sorted
+  // candidates, if it has a current one.  A relation that no join probes
+  // gets one fitted here when its candidates are spread thinly over a
+  // large full (at least 8 keys of full per candidate, so a tile's slice is
+  // searched, not streamed) and full is large enough to be kept stable by
+  // a tail run: the model then lasts until the tail is folded in, and each
+  // search starts from the model's window instead of the whole slice.
   template <typename K>
-  bool diff_model(Relation& R, hl::LearnedView<K>* mv) {
-    const bool use = learned() && R.n_full > 0 && R.idx[0].lm_ok &&
-                     R.idx[0].lm_keys == R.full.p && R.idx[0].lm_n == R.n_full;
-    if (use) *mv = R.idx[0].view<K>();
+  bool diff_model(Relation& R, u64 n_cand, hl::LearnedView<K>* mv) {
+    if (!learned() || R.n_full == 0) return false;
+    Index& ix = R.idx[0];
+    bool use = ix.lm_ok && ix.lm_keys == R.full.p && ix.lm_n == R.n_full;
+    if (!use && !ix.used && tail_ok(R) && R.n_full * sizeof(K) >= kTailMinFullBytes &&
+        R.n_full >= 8 * n_cand) {
+      const int caller = marks.empty() ? -1 : marks.back().first;
+      mark(HL_PHASE_INDEX);
+      fit_model<K>(R, 0);
+      mark(caller);
+      use = ix.lm_ok;
+    }
+    if (use) *mv = ix.view<K>();
     return use;
   }
 
@@ -1167,21 +1705,40 @@ struct hl_engine {
   // R's pending delta: they are sorted, cut down to the distinct ones that
   // are neither in full nor already pending, and merged in (the pieces are
   // disjoint, so the merge needs no dedup).  One synchronisation.
+  // Its sort, difference and merge are charged to those phases; the
+  // caller's phase (the join, when a join's outputs are absorbed range by
+  // range) resumes afterwards.
   template <typename K>
   void absorb(Relation& R, K* keys, u64 m) {
     if (m == 0) return;
+    const int caller = marks.empty() ? -1 : marks.back().first;
+    struct Resume {
+      hl_engine* e;
+      int ph;
+      ~Resume() {
+        if (e->marks.empty() || e->marks.back().first != ph) {
+          try {
+            e->mark(ph);
+          } catch (...) {
+          }
+        }
+      }
+    } resume{this, caller};
+    mark(HL_PHASE_MERGE);
     flush_tail<K>(R);  // the membership test below searches full only
-    const int bits = 2 * w;
+    const int bits = kbits(R);
     reserve_grow(alt, m * sizeof(K));
     reserve(ws, hl::sort_workspace_bytes(m), hl::sort_workspace_bytes(m) * 2);
     K* sorted = nullptr;
+    mark(HL_PHASE_SORT);
     HIPCK(hl::radix_sort<K>(keys, kp<K>(alt), m, bits, ws.p, stream, &sorted, kt()));
     K* other = sorted == keys ? kp<K>(alt) : keys;
+    mark(HL_PHASE_DIFF);
     reserve(ws, hl::unique_diff_workspace_bytes(m), hl::unique_diff_workspace_bytes(m) * 2);
     u64* dc = d_small + kChunkSlots;  // scratch counts (not the per-relation slots)
     u64* hc = h_small + kChunkSlots;
     hl::LearnedView<K> mv{};
-    const bool use_model = diff_model<K>(R, &mv);
+    const bool use_model = diff_model<K>(R, m, &mv);
     HIPCK(hl::unique_diff<K>(sorted, m, kp<K>(R.full), R.n_full, other, sorted, dc, ws.p, stream,
                              kt(), use_model ? &mv : nullptr));
     HIPCK(hipMemcpyAsync(hc, dc, 2 * sizeof(u64), hipMemcpyDeviceToHost, stream));
@@ -1197,6 +1754,7 @@ struct hl_engine {
       d = hc[0];
     }
     if (d == 0) return;
+    mark(HL_PHASE_MERGE);
     if (p == 0) {
       reserve(R.pend[0], d * sizeof(K), d * sizeof(K) * 2);
       HIPCK(hipMemcpyAsync(R.pend[0].p, sorted, d * sizeof(K), hipMemcpyDeviceToDevice, stream));
@@ -1228,7 +1786,6 @@ struct hl_engine {
   // merges and index refreshes.  Returns the total delta size.
   template <typename K>
   u64 close_iteration() {
-    const int bits = 2 * w;
     std::vector<int> idbs;
     for (int k = 0; k < int(rels.size()); ++k)
       if (!rels[k].edb) idbs.push_back(k);
@@ -1252,8 +1809,8 @@ struct hl_engine {
       reserve(ws, hl::sort_workspace_bytes(R.n_cand), hl::sort_workspace_bytes(R.n_cand) * 2);
       K* sorted = nullptr;
       mark(HL_PHASE_SORT);
-      HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_cand, bits, ws.p, stream, &sorted,
-                              kt()));
+      HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_cand, kbits(R), ws.p, stream,
+                              &sorted, kt()));
       Buf& sbuf = (sorted == kp<K>(R.cand)) ? R.cand : alt;
       Buf& obuf = (sorted == kp<K>(R.cand)) ? alt : R.cand;
       reserve(ws, hl::unique_diff_workspace_bytes(R.n_cand),
@@ -1261,9 +1818,7 @@ struct hl_engine {
       mark(HL_PHASE_DIFF);
       // delta is written over the sorted candidates, then takes their buffer
       hl::LearnedView<K> mv{};
-      const bool use_model = learned() && R.n_full > 0 && R.idx[0].lm_ok &&
-                             R.idx[0].lm_keys == R.full.p && R.idx[0].lm_n == R.n_full;
-      if (use_model) mv = R.idx[0].view<K>();
+      const bool use_model = diff_model<K>(R, R.n_cand, &mv);
       // a tail run beside full is tested in the same pass
       HIPCK(hl::unique_diff<K>(kp<K>(sbuf), R.n_cand, kp<K>(R.full), R.n_full, kp<K>(obuf),
                                kp<K>(sbuf), d_small + 2 * q, ws.p, stream, kt(),
@@ -1341,8 +1896,15 @@ struct hl_engine {
       grown.push_back(idbs[q]);
     }
     mark(HL_PHASE_INDEX);
-    for (int r : grown) update_swapped<K>(rels[r], kp<K>(rels[r].delta), rels[r].n_delta, false);
-    refresh_indexes<K>(grown);
+    if (wide) {
+      for (int r : grown)
+        for (Index& ix : rels[r].widx)
+          update_wide<K>(rels[r], ix, kp<K>(rels[r].delta), rels[r].n_delta, false);
+      refresh_wide<K>(grown);
+    } else {
+      for (int r : grown) update_swapped<K>(rels[r], kp<K>(rels[r].delta), rels[r].n_delta, false);
+      refresh_indexes<K>(grown);
+    }
     mark(-1);
     return total;
   }
@@ -1434,7 +1996,8 @@ struct hl_engine {
   // Whether R may keep a tail run on the multi-kernel path: no join probes
   // it (its indexes would have to cover the tail), and eager buffers are on.
   bool tail_ok(const Relation& R) const {
-    return !R.edb && !R.idx[0].used && !R.idx[1].used && !(flags & HL_FLAG_NO_EBM);
+    return !R.edb && !R.idx[0].used && !R.idx[1].used && R.widx.empty() &&
+           !(flags & HL_FLAG_NO_EBM);
   }
 
   void drop_graphs() {
@@ -1526,6 +2089,8 @@ struct hl_engine {
       reserve(R.fz_parts, parts, (hl::fused_merge_tiles(want) + 1) * sizeof(u64));
       it.delta_in[r] = kp<K>(R.delta);
       it.full[r] = kp<K>(R.full);
+      hl::LearnedView<K> mv{};
+      if (diff_model<K>(R, C, &mv)) it.full_lm[r] = mv;
       it.tail[r] = kp<K>(R.fz_tail[0]);
       it.delta_out[r] = kp<K>(R.fz_next);
     }
@@ -1646,6 +2211,7 @@ struct hl_engine {
     load_edbs<K>();
     mark(HL_PHASE_JOIN);
     for (const Plan& p : plans0) run_plan<K>(p);
+    for (const WPlan& p : wplans0) run_wide_plan<K>(p);
     u64 d = close_iteration<K>();
     st.iterations = 1;
     if (fused_on()) fused_setup<K>();
@@ -1661,9 +2227,11 @@ struct hl_engine {
       fz_live = false;
       u64 in = 0;
       for (const Plan& p : plansR) in += rels[p.outer_rel].n_delta;
+      for (const WPlan& p : wplansR) in += rels[p.outer_rel].n_delta;
       const u64 out0 = st.join_outputs;
       mark(HL_PHASE_JOIN);
       for (const Plan& p : plansR) run_plan<K>(p);
+      for (const WPlan& p : wplansR) run_wide_plan<K>(p);
       last_in = in;
       last_out = st.join_outputs - out0;
       d = close_iteration<K>();
@@ -1804,6 +2372,8 @@ struct hl_engine {
     if (rules.empty()) fail(HL_E_STATE, "no program");
     auto t0 = std::chrono::steady_clock::now();
     st = hl_stats{};
+    rule_out.assign(rules.size(), 0);
+    rule_mid.assign(rules.size(), 0);
     reuses = 0;
     fz_live = false;
     fz_fail_at = ~u64(0);
@@ -1822,10 +2392,12 @@ struct hl_engine {
       R.dedup = true;
       R.raw_cand = 0;
       R.idx[0].lm_ok = R.idx[1].lm_ok = false;
+      for (Index& ix : R.widx) ix.lm_ok = false;
       if (!R.edb) {
         R.n_full = 0;
         R.idx[0].n = R.idx[1].n = 0;
         R.idx[0].cap = R.idx[1].cap = 0;
+        for (Index& ix : R.widx) ix.n = ix.cap = 0;
       }
     }
     // key width: ids of every IDB tuple come from the EDBs (range restriction)
@@ -1839,7 +2411,11 @@ struct hl_engine {
     const u32 maxid = u32(h_small[0]);
     w = 1;
     while (w < 32 && (u64(maxid) >> w) != 0) ++w;
-    key_bytes = (2 * w <= 32) ? 4 : 8;
+    const int cols = wide ? wide_cols() : 2;
+    if (cols * w > 64)
+      fail(HL_E_UNSUPPORTED, "tuples of " + std::to_string(cols) + " columns of " +
+                                 std::to_string(w) + "-bit ids need keys wider than 64 bits");
+    key_bytes = (cols * w <= 32) ? 4 : 8;
     if (key_bytes == 4) run_typed<u32>();
     else run_typed<u64>();
     st.key_bytes = key_bytes;
@@ -1859,7 +2435,10 @@ struct hl_engine {
 
   template <typename K>
   void fetch_typed(Relation& R, u64 first, u64 count, u32* d_rows, u32 sub) {
-    HIPCK(hl::unpack_rows<K>(kp<K>(R.full) + first, count, R.arity, w, d_rows, stream, sub));
+    if (wide)
+      HIPCK(hl::wide_unpack<K>(kp<K>(R.full) + first, count, R.arity, w, d_rows, stream, sub));
+    else
+      HIPCK(hl::unpack_rows<K>(kp<K>(R.full) + first, count, R.arity, w, d_rows, stream, sub));
   }
 
   // Tuples of relation R whose first column lies in [lo, hi): a contiguous
@@ -2057,7 +2636,7 @@ int hl_declare(hl_engine* e, const char* name, uint32_t arity, int32_t is_edb) {
         fail(HL_E_INVALID, "bad relation name");
     if (!e->rules.empty()) fail(HL_E_STATE, "declare before hl_program");
     if (e->find(name) >= 0) fail(HL_E_INVALID, std::string("relation declared twice: ") + name);
-    if (arity != 1 && arity != 2) fail(HL_E_UNSUPPORTED, "only unary and binary relations");
+    if (arity < 1 || arity > 4) fail(HL_E_UNSUPPORTED, "relations of arity 1 to 4 only");
     Relation R;
     R.name = name;
     R.arity = int(arity);
@@ -2102,8 +2681,10 @@ int hl_batch_layout(hl_engine* e, const uint32_t* id_range, uint32_t n_inst) {
   return guard(e, [&] {
     if (!id_range || n_inst == 0) fail(HL_E_INVALID, "empty batch layout");
     if (!e->batch_base.empty()) fail(HL_E_STATE, "batch layout already set");
-    for (const Relation& R : e->rels)
+    for (const Relation& R : e->rels) {
       if (R.n_raw) fail(HL_E_STATE, "batch layout after rows were loaded");
+      if (R.arity > 2) fail(HL_E_UNSUPPORTED, "batches of relations of arity above 2");
+    }
     std::vector<u64> base(n_inst + 1, 0);
     for (u32 k = 0; k < n_inst; ++k) base[k + 1] = base[k] + id_range[k];
     if (base[n_inst] > (u64(1) << 32)) fail(HL_E_INVALID, "instance id ranges exceed 2^32");
@@ -2162,6 +2743,8 @@ int hl_index(hl_engine* e, const char* name, const uint32_t* cols, uint32_t ncol
     Relation& R = e->rels[e->find_or_fail(name)];
     if (!cols || ncols != 1) fail(HL_E_UNSUPPORTED, "indexes on one column only");
     if (cols[0] >= u32(R.arity)) fail(HL_E_INVALID, "column out of range");
+    if (R.arity > 2)
+      fail(HL_E_UNSUPPORTED, "relations of arity 3-4 get the indexes their joins need");
     R.idx[cols[0]].used = true;
   });
 }
@@ -2185,6 +2768,16 @@ int hl_run(hl_engine* e, hl_stats* stats) {
   return guard(e, [&] {
     if (e->device < 0) fail(HL_E_STATE, "planning-only engine (device -1)");
     e->run(stats);
+  });
+}
+
+int hl_rule_stats(hl_engine* e, uint32_t rule, uint64_t* join_outputs, uint64_t* intermediate) {
+  return guard(e, [&] {
+    if (!join_outputs || !intermediate) fail(HL_E_INVALID, "null output");
+    if (!e->ran) fail(HL_E_STATE, "rule statistics before hl_run");
+    if (rule >= e->rule_out.size()) fail(HL_E_INVALID, "no such rule");
+    *join_outputs = e->rule_out[rule];
+    *intermediate = e->rule_mid[rule];
   });
 }
 

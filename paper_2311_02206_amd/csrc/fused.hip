@@ -139,6 +139,35 @@ __device__ __forceinline__ void fz_drop_members(const K* a, u64 n, const K* key,
     if (keep[r] && lo[r] < n && a[lo[r]] == key[r]) keep[r] = false;
 }
 
+// The same through a learned index over a: each key's search starts from
+// the model's window, which holds its lower bound exactly.
+template <typename K>
+__device__ __forceinline__ void fz_drop_members_lm(const LearnedView<K>& lv, const K* key,
+                                                   bool* keep) {
+  u64 lo[kLock], hi[kLock];
+#pragma unroll
+  for (int r = 0; r < kLock; ++r) {
+    lo[r] = hi[r] = 0;
+    if (keep[r]) lm_window(lv, key[r], lo[r], hi[r]);
+  }
+  bool busy = true;
+  while (busy) {
+    busy = false;
+#pragma unroll
+    for (int r = 0; r < kLock; ++r) {
+      if (lo[r] < hi[r]) {
+        const u64 mid = (lo[r] + hi[r]) >> 1;
+        if (lv.keys[mid] < key[r]) lo[r] = mid + 1;
+        else hi[r] = mid;
+        busy = true;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kLock; ++r)
+    if (keep[r] && lo[r] < lv.n && lv.keys[lo[r]] == key[r]) keep[r] = false;
+}
+
 // Phase A: workgroup g of G takes the g-th slice of every delta, joins it,
 // sorts and deduplicates its candidates in LDS, and tests each distinct one
 // against full and the tail.  It writes two sorted runs per head: the
@@ -276,7 +305,10 @@ __global__ __launch_bounds__(kFNT) void fused_join_kernel(FusedIteration<K> it, 
           key[r] = i < m ? cand[i] : K(0);
           keep[r] = first[r];
         }
-        fz_drop_members(full, nf, key, keep);
+        if (it.full_lm[h].n == nf && nf > 0 && it.full_lm[h].keys == full)
+          fz_drop_members_lm(it.full_lm[h], key, keep);
+        else
+          fz_drop_members(full, nf, key, keep);
         fz_drop_members(tail, ntl, key, keep);
 #pragma unroll
         for (int r = 0; r < kLock; ++r) {

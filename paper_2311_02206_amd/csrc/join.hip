@@ -219,11 +219,38 @@ __device__ __forceinline__ bool first_in_tile(K* set, K v) {
   return true;
 }
 
+// How an expand turns (outer tuple, inner tuple) into an output: binary
+// relations (a pair and the inner's other column), or relations of arity up
+// to 4 (WideSpec: any columns of either side).
+template <typename K>
+struct PairGather {
+  JoinSpec js;
+  __device__ bool filtered() const { return js.fa >= 0 || js.ea >= 0 || js.dd; }
+  __device__ bool dedup() const { return js.dd != 0; }
+  __device__ K operator()(K ok, K ik, bool& pass) const {
+    const K mask = (K(1) << js.w) - 1;
+    const K c0 = ok >> js.w, c1 = ok & mask;
+    const K o = ik & mask;
+    const K x = pick(js.src0, c0, c1, o), y = pick(js.src1, c0, c1, o);
+    pass = (js.fa < 0 || pick(js.fa, c0, c1, o) != pick(js.fb, c0, c1, o)) &&
+           (js.ea < 0 || pick(js.ea, c0, c1, o) == pick(js.eb, c0, c1, o));
+    return (x << js.w) | y;
+  }
+};
+
+template <typename K>
+struct WideGather {
+  WideSpec ws;
+  __device__ bool filtered() const { return ws.nf > 0 || ws.ne > 0; }
+  __device__ bool dedup() const { return false; }
+  __device__ K operator()(K ok, K ik, bool& pass) const { return wide_gather(ok, ik, ws, pass); }
+};
+
 // ITEMS outputs per thread: a tile of kNT * ITEMS outputs and outer tuples.
-template <typename K, int ITEMS>
+template <typename K, int ITEMS, typename G>
 __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer, const u64* off,
                                                      const u32* start, const K* inner,
-                                                     u64 total, JoinSpec js, const u64* parts,
+                                                     u64 total, G g, const u64* parts,
                                                      u64 tile0, K* out, u64* cursor) {
   constexpr u64 kTile = u64(kNT) * ITEMS;
   constexpr int kItems = ITEMS;
@@ -277,17 +304,16 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
     }
   }
   __syncthreads();
-  const bool filtered = js.fa >= 0 || js.ea >= 0 || js.dd;
-  const K mask = (K(1) << js.w) - 1;
+  const bool filtered = g.filtered();
   K* s_keep = reinterpret_cast<K*>(s_pool);
   __shared__ u32 s_wsum[kNT / kWave];
   __shared__ u64 s_base;
   // the dedup set lives in dynamic LDS, sized at launch only when js.dd
   extern __shared__ __align__(16) unsigned char s_dyn[];
   K* dset = reinterpret_cast<K*>(s_dyn);
-  if (js.dd)
+  if (g.dedup())
     for (u32 k = threadIdx.x; k < kDedupSlots; k += kNT) dset[k] = ~K(0);
-  if (js.dd) __syncthreads();
+  if (g.dedup()) __syncthreads();
   // each thread's kItems outputs (strided, so reads of each inner run and
   // the unfiltered writes are coalesced), computed with every load issued
   // before any is used
@@ -304,12 +330,8 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
       const u64 pos = here ? u64(s_start[u64(i) - a0]) + (k - s_off[u64(i) - a0])
                            : u64(start[i]) + (b0 + k - off[i]);
       const K ok = here ? s_outer[u64(i) - a0] : outer[i];
-      const K c0 = ok >> js.w, c1 = ok & mask;
-      const K o = inner[pos] & mask;
-      const K x = pick(js.src0, c0, c1, o), y = pick(js.src1, c0, c1, o);
-      v[r] = (x << js.w) | y;
-      const bool pass = (js.fa < 0 || pick(js.fa, c0, c1, o) != pick(js.fb, c0, c1, o)) &&
-                        (js.ea < 0 || pick(js.ea, c0, c1, o) == pick(js.eb, c0, c1, o));
+      bool pass;
+      v[r] = g(ok, inner[pos], pass);
       if (pass) keep |= 1u << r;
     }
   }
@@ -321,7 +343,7 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
     }
     return;
   }
-  if (js.dd) {
+  if (g.dedup()) {
 #pragma unroll
     for (int r = 0; r < kItems; ++r)
       if ((keep >> r) & 1u)
@@ -522,14 +544,15 @@ hipError_t join_expand_tiles(const K* outer, u64 n_outer, const u64* off, const 
   // the dedup set (2 slots per tile output) lives in dynamic LDS
   const size_t dyn = js.dd ? 2 * join_tile_outputs(items) * sizeof(K) : 0;
   const dim3 grid = dim3(u32(tiles));
+  const PairGather<K> g{js};
   if (items == 4)
-    expand_kernel<K, 4><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, js,
+    expand_kernel<K, 4><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, g,
                                                parts, tile0, out, cursor);
   else if (items == 16)
-    expand_kernel<K, 16><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, js,
+    expand_kernel<K, 16><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, g,
                                                 parts, tile0, out, cursor);
   else
-    expand_kernel<K, 8><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, js,
+    expand_kernel<K, 8><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, g,
                                                parts, tile0, out, cursor);
   // by definition: each inner tuple of a matched run read once, each output
   // written once, each outer tuple with its offset and run start read once
@@ -551,6 +574,29 @@ hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* s
   if (e != hipSuccess || total == 0) return e;
   return join_expand_tiles<K>(outer, n_outer, off, start, inner, total, js, parts, 0,
                               join_tiles(n_outer, total, items), out, cursor, s, timer, items);
+}
+
+template <typename K>
+hipError_t wide_expand_tiles(const K* outer, u64 n_outer, const u64* off, const u32* start,
+                             const K* inner, u64 total, const WideSpec& ws, const u64* parts,
+                             u64 tile0, u64 tiles, K* out, u64* cursor, hipStream_t s,
+                             LaunchTimer* timer) {
+  if (total == 0 || tiles == 0) return hipSuccess;
+  if (!wide_spec_ok(ws)) return hipErrorInvalidValue;
+  const u64 nt = join_tiles(n_outer, total, 8);
+  if (n_outer >= (u64(1) << 32) || tile0 + tiles > nt || tiles >= (u64(1) << 31))
+    return hipErrorInvalidValue;
+  if (timer) timer->begin(K_JOIN_EXPAND, s);
+  expand_kernel<K, 8><<<dim3(u32(tiles)), kNT, 0, s>>>(outer, n_outer, off, start, inner, total,
+                                                       WideGather<K>{ws}, parts, tile0, out,
+                                                       cursor);
+  if (timer) {
+    const double f = double(tiles) / double(nt);
+    timer->end(K_JOIN_EXPAND, s,
+               u64(f * double(2 * total * sizeof(K) +
+                              n_outer * (sizeof(K) + sizeof(u64) + sizeof(u32)))));
+  }
+  return hipGetLastError();
 }
 
 template <typename K>
@@ -600,6 +646,9 @@ hipError_t join_nested(const K* outer, u64 n, const NestedJoin<K>& nj, u32* coun
                                      const JoinSpec&, u64*, K*, u64*, hipStream_t,            \
                                      LaunchTimer*, int);                                      \
   template hipError_t project<K>(const K*, u64, const JoinSpec&, K*, u64*, hipStream_t);   \
+  template hipError_t wide_expand_tiles<K>(const K*, u64, const u64*, const u32*, const K*,  \
+                                           u64, const WideSpec&, const u64*, u64, u64, K*,   \
+                                           u64*, hipStream_t, LaunchTimer*);                  \
   template hipError_t join_probe_learned<K>(const K*, u64, const JoinSpec&,                  \
                                             const LearnedView<K>&, u32*, u32*, hipStream_t,  \
                                             LaunchTimer*);

@@ -42,9 +42,15 @@ enum KernelId {
 // Optional launch timer: launchers call begin() right before and end()
 // right after a timed kernel, passing the bytes the kernel must move by
 // definition (its inputs read once, its outputs written once).
+// A kernel whose byte count depends on what it finds (how many keys it
+// keeps, how far apart its searches fall) adds that part on the device: the
+// launcher asks for a counter (zeroed on the stream), the kernel adds to it,
+// and end() takes it along with the part known on the host.
 struct LaunchTimer {
   virtual void begin(int kernel, hipStream_t s) = 0;
-  virtual void end(int kernel, hipStream_t s, u64 algorithmic_bytes) = 0;
+  virtual void end(int kernel, hipStream_t s, u64 algorithmic_bytes,
+                   const u64* device_bytes = nullptr) = 0;
+  virtual u64* device_counter(hipStream_t) { return nullptr; }
   virtual ~LaunchTimer() {}
 };
 
@@ -152,6 +158,86 @@ struct JoinSpec {
   int dd;  // nonzero: drop outputs repeated within a tile (join_expand)
 };
 
+// A join (or, with ai == 0, a projection) over relations of arity up to 4
+// (wide.hip).  Tuples are packed w bits per column, column 0 most
+// significant.  The outer (carried) tuple has ao columns; the inner is an
+// index of ai columns whose first nj are the join columns, matched in order
+// with outer columns jo[0..nj).  Column sources: 0..3 a column of the
+// outer, 4..7 a column of the inner (in the index's column order), 8 the
+// constant 0.  The output has nout columns src[0..nout); it is kept when
+// every `!=` test (fa[f], fb[f]) and every `==` test (ea[f], eb[f]) holds.
+struct WideSpec {
+  int w;
+  int ao, ai, nj;
+  int jo[4];
+  int nout;
+  int src[4];
+  int nf, fa[4], fb[4];
+  int ne, ea[4], eb[4];
+};
+
+template <typename K>
+__host__ __device__ __forceinline__ K wide_src(int s, K ok, K ik, const WideSpec& ws) {
+  const K mask = (K(1) << ws.w) - 1;
+  if (s < 4) return (ok >> ((ws.ao - 1 - s) * ws.w)) & mask;
+  if (s < 8) return (ik >> ((ws.ai - 1 - (s - 4)) * ws.w)) & mask;
+  return K(0);
+}
+
+template <typename K>
+__host__ __device__ __forceinline__ K wide_gather(K ok, K ik, const WideSpec& ws, bool& pass) {
+  K v = 0;
+  for (int t = 0; t < ws.nout; ++t) v = (v << ws.w) | wide_src(ws.src[t], ok, ik, ws);
+  pass = true;
+  for (int f = 0; f < ws.nf; ++f)
+    pass = pass && wide_src(ws.fa[f], ok, ik, ws) != wide_src(ws.fb[f], ok, ik, ws);
+  for (int f = 0; f < ws.ne; ++f)
+    pass = pass && wide_src(ws.ea[f], ok, ik, ws) == wide_src(ws.eb[f], ok, ik, ws);
+  return v;
+}
+
+bool wide_spec_ok(const WideSpec& ws);
+// Runs of equal prefix key >> shift (K-wide comparison).
+template <typename K>
+hipError_t wide_count_runs(const K* keys, u64 n, int shift, u64* d_runs, hipStream_t s);
+// Hash index of the runs of equal prefix, keyed by the prefix's fingerprint
+// (table of `cap` zeroed slots, cap > runs).
+template <typename K>
+hipError_t wide_hisa_build(const K* keys, u64 n, int shift, Slot* table, u64 cap, hipStream_t s,
+                           LaunchTimer* timer = nullptr);
+// (run start, run length) in `inner` (an index of ws.ai columns) of every
+// outer tuple's probe value; length 0 when absent.
+template <typename K>
+hipError_t wide_probe(const K* outer, u64 n, const WideSpec& ws, const Slot* table, u64 cap,
+                      const K* inner, u32* start, u32* len, hipStream_t s,
+                      LaunchTimer* timer = nullptr);
+template <typename K>
+hipError_t wide_probe_learned(const K* outer, u64 n, const WideSpec& ws, const LearnedView<K>& lv,
+                              u32* start, u32* len, hipStream_t s, LaunchTimer* timer = nullptr);
+// The expand of join_expand_tiles (8 outputs per thread) with WideSpec
+// outputs and tests.
+template <typename K>
+hipError_t wide_expand_tiles(const K* outer, u64 n_outer, const u64* off, const u32* start,
+                             const K* inner, u64 total, const WideSpec& ws, const u64* parts,
+                             u64 tile0, u64 tiles, K* out, u64* cursor, hipStream_t s,
+                             LaunchTimer* timer = nullptr);
+// One-atom bodies (ai == 0): every input tuple mapped by ws; with tests,
+// survivors are appended at *cursor, else output i goes to out[i].
+template <typename K>
+hipError_t wide_project(const K* in, u64 n, const WideSpec& ws, K* out, u64* cursor,
+                        hipStream_t s);
+// out[i] = in[i] with columns reordered: column c of the output is column
+// perm[c] of the input (a columns).
+template <typename K>
+hipError_t wide_permute(const K* in, u64 n, int a, int w, const int* perm, K* out,
+                        hipStream_t s);
+// Row-major n x a uint32 rows to packed keys and back (sub is subtracted
+// from every id on the way out).
+template <typename K>
+hipError_t wide_pack(const u32* rows, u64 n, int a, int w, K* out, hipStream_t s);
+template <typename K>
+hipError_t wide_unpack(const K* keys, u64 n, int a, int w, u32* rows, hipStream_t s, u32 sub);
+
 template <typename K>
 hipError_t join_probe(const K* outer, u64 n, const JoinSpec& js, const Slot* table, u64 cap,
                       u32* start, u32* len, hipStream_t s, LaunchTimer* timer = nullptr);
@@ -255,6 +341,9 @@ struct FusedIteration {
   FusedPlan<K> plans[kFusedMaxPlans];
   const K* delta_in[kFusedMaxRels];
   const K* full[kFusedMaxRels];
+  // learned index over full (n == 0: none; used only while n equals the
+  // full size in counts), which narrows each membership search to a window
+  LearnedView<K> full_lm[kFusedMaxRels];
   const K* tail[kFusedMaxRels];
   K* delta_out[kFusedMaxRels];  // room for cap_b keys each
   u64* counts;                  // kFusedCountWords words

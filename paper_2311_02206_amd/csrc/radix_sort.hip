@@ -5,12 +5,19 @@
 //
 // Only the significant low `bits` bits are sorted (2 x the id width for a
 // pair), 8 bits per pass.  One pass:
-//   1. per-tile digit histogram (64-lane ballot matching, no atomics),
-//      written tile-major so each tile writes one contiguous row;
+//   1. per-tile digit histogram: LDS atomic adds into sub-histograms (one
+//      per eighth of a wave, so a digit shared by a whole wave serialises 8
+//      lanes, not 64), written tile-major so each tile writes one row;
 //   2. column scan of the count matrix (chunk sums, a scan per digit over
 //      the chunks, the digit bases, per-tile offsets), all coalesced;
-//   3. stable scatter: each wave ranks its keys by ballot matching, the tile
-//      is reordered by digit in LDS and written out in runs per digit.
+//   3. stable scatter: each wave ranks its keys among the equal-digit keys
+//      of the wave by matching digits with one ballot per digit bit, the
+//      tile is reordered by digit in LDS and written out in runs per digit.
+// The digit width of a pass is a compile-time constant, so the matching
+// loop is straight-line code: per digit bit one sign-extending bit
+// extract, one ballot and two three-input logic operations (v_bitop3) that
+// narrow the 64-lane peer mask, and the rank is one masked bit count.
+// Tiles whose keys all exist skip every bounds test.
 // (A single-sweep variant with decoupled look-back was measured slower on
 // this chip: the look-back walks over many in-flight tiles with
 // fabric-latency loads.)
@@ -25,30 +32,51 @@ constexpr int kBits = 8;
 constexpr int kBuckets = 1 << kBits;
 constexpr int kNT = 256;
 constexpr int kWaves = kNT / kWave;
-constexpr int kItems = 16;
-constexpr u64 kTile = u64(kNT) * kItems;
-constexpr u32 kWaveTile = kWave * kItems;
 constexpr u32 kChunk = 64;  // tiles per chunk of the column scan
 static_assert(kNT == kBuckets, "one thread per digit bucket");
 
-// Lanes of `valid` whose digit equals this lane's (digits of dbits bits:
-// the ballots of the bits above are skipped).
-__device__ __forceinline__ u64 peers_of(u32 d, u64 valid, int dbits) {
-  u64 m = valid;
-#pragma unroll
-  for (int b = 0; b < kBits; ++b) {
-    if (b < dbits) {
-      u64 bb = ballot((d >> b) & 1u);
-      m &= ((d >> b) & 1u) ? bb : ~bb;
-    }
-  }
-  return m;
+// Keys per thread of a tile (histogram and scatter use the same tiles).
+// 32-bit keys take twice as many: the LDS copy of a tile is the same size,
+// and the per-tile work of both kernels (count rows, sub-histogram
+// clearing and reduction, the digit scan) is spread over twice the keys.
+template <typename K>
+struct RsItems {
+  static constexpr int value = 16;
+};
+template <>
+struct RsItems<u32> {
+  static constexpr int value = 32;
+};
+template <typename K>
+constexpr u64 rs_tile() {
+  return u64(kNT) * RsItems<K>::value;
+}
+constexpr u64 kMinTile = u64(kNT) * 16;
+
+// A pass sorts on bits [shift, shift + DB) of the key, DB <= 8.
+template <int DB, typename K>
+__device__ __forceinline__ u32 digit(K k, int shift) {
+  return u32(k >> shift) & ((1u << DB) - 1u);
 }
 
-// A pass sorts on bits [shift, shift + dbits) of the key, dbits <= 8.
-template <typename K>
-__device__ __forceinline__ u32 digit(K k, int shift, int dbits) {
-  return u32(k >> shift) & ((1u << dbits) - 1u);
+// Narrows the peer mask (lo, hi) to the lanes whose DB-bit digit equals
+// this lane's: per bit b, t is 0 or ~0 by the lane's bit, B the ballot of
+// that bit, and the lanes kept are those where B agrees with t:
+// mask & ~(B ^ t), one v_bitop3 per half (truth table 0x90).
+template <int DB>
+__device__ __forceinline__ void match_digit(u32 d, u32& lo, u32& hi) {
+#pragma unroll
+  for (int b = 0; b < DB; ++b) {
+    const u32 t = u32(__builtin_amdgcn_sbfe(int(d), b, 1));
+    const u64 B = __builtin_amdgcn_uicmp(t, 0u, 33);  // ballot of t != 0
+    lo = __builtin_amdgcn_bitop3_b32(lo, u32(B), t, 0x90);
+    hi = __builtin_amdgcn_bitop3_b32(hi, u32(B >> 32), t, 0x90);
+  }
+}
+
+// Lanes of the 64-bit mask (lo, hi) below this lane.
+__device__ __forceinline__ u32 lanes_below(u32 lo, u32 hi) {
+  return __builtin_amdgcn_mbcnt_hi(hi, __builtin_amdgcn_mbcnt_lo(lo, 0u));
 }
 
 // Per-tile digit histogram; counts are tile-major: counts[tile * 256 + d].
@@ -59,28 +87,46 @@ __device__ __forceinline__ u32 digit(K k, int shift, int dbits) {
 constexpr int kSubsPerWave = 8;
 constexpr int kSubs = kWaves * kSubsPerWave;
 constexpr int kSubStride = kBuckets + 1;
+constexpr int kHistWords = (kSubs * kSubStride + 3) / 4 * 4;
 
-template <typename K>
-__global__ __launch_bounds__(kNT) void rs_hist_kernel(const K* keys, u64 n, int shift, int dbits,
+template <typename K, int DB>
+__global__ __launch_bounds__(kNT) void rs_hist_kernel(const K* keys, u64 n, int shift,
                                                       u32* counts, u32 ntiles) {
-  __shared__ u32 hist[kSubs * kSubStride];
-  for (int i = threadIdx.x; i < kSubs * kSubStride; i += kNT) hist[i] = 0;
+  constexpr int IT = RsItems<K>::value;
+  constexpr u64 kTile = rs_tile<K>();
+  constexpr u32 kWaveTile = kWave * IT;
+  __shared__ __align__(16) u32 hist[kHistWords];
+  {
+    uint4* h4 = reinterpret_cast<uint4*>(hist);
+    for (int i = threadIdx.x; i < kHistWords / 4; i += kNT) h4[i] = make_uint4(0, 0, 0, 0);
+  }
   const u32 tile = xcd_tile(blockIdx.x, gridDim.x);
   const int w = threadIdx.x / kWave;
   const u64 base = u64(tile) * kTile + u64(w) * kWaveTile;
-  // all loads first, so each wave has kItems loads in flight
-  K key[kItems];
+  const bool whole = u64(tile) * kTile + kTile <= n;
+  // all loads first, so each wave has IT loads in flight
+  K key[IT];
+  if (whole) {
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    u64 i = base + u64(j) * kWave + lane_id();
-    key[j] = i < n ? keys[i] : K(0);
+    for (int j = 0; j < IT; ++j) key[j] = keys[base + u64(j) * kWave + lane_id()];
+  } else {
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const u64 i = base + u64(j) * kWave + lane_id();
+      key[j] = i < n ? keys[i] : K(0);
+    }
   }
   __syncthreads();
   u32* h = hist + (w * kSubsPerWave + lane_id() / (kWave / kSubsPerWave)) * kSubStride;
+  if (whole) {
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    u64 i = base + u64(j) * kWave + lane_id();
-    if (i < n) atomicAdd(&h[digit(key[j], shift, dbits)], 1u);
+    for (int j = 0; j < IT; ++j) atomicAdd(&h[digit<DB>(key[j], shift)], 1u);
+  } else {
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const u64 i = base + u64(j) * kWave + lane_id();
+      if (i < n) atomicAdd(&h[digit<DB>(key[j], shift)], 1u);
+    }
   }
   __syncthreads();
   const int d = threadIdx.x;
@@ -168,10 +214,12 @@ __global__ __launch_bounds__(kNT) void col_single_kernel(const u32* counts, u32 
   }
 }
 
-template <typename K>
+template <typename K, int DB>
 __global__ __launch_bounds__(kNT) void rs_scatter_kernel(const K* in, K* out, u64 n, int shift,
-                                                         int dbits, const u32* offsets,
-                                                         u32 ntiles) {
+                                                         const u32* offsets, u32 ntiles) {
+  constexpr int IT = RsItems<K>::value;
+  constexpr u64 kTile = rs_tile<K>();
+  constexpr u32 kWaveTile = kWave * IT;
   __shared__ u32 whist[kWaves * kBuckets];
   __shared__ u32 gbase[kBuckets];
   __shared__ u32 wsum[kWaves];
@@ -181,29 +229,51 @@ __global__ __launch_bounds__(kNT) void rs_scatter_kernel(const K* in, K* out, u6
   const int w = threadIdx.x / kWave;
   const u64 tbase = u64(tile) * kTile;
   const u64 base = tbase + u64(w) * kWaveTile;
-  K key[kItems];
+  const bool whole = tbase + kTile <= n;
+  K key[IT];
+  if (whole) {
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    u64 i = base + u64(j) * kWave + lane_id();
-    key[j] = i < n ? in[i] : K(0);
+    for (int j = 0; j < IT; ++j) key[j] = in[base + u64(j) * kWave + lane_id()];
+  } else {
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const u64 i = base + u64(j) * kWave + lane_id();
+      key[j] = i < n ? in[i] : K(0);
+    }
   }
   const u32 gofs = offsets[u64(tile) * kBuckets + threadIdx.x];
   __syncthreads();
   u32* h = whist + w * kBuckets;
-  const u64 lt = lanemask_lt();
-  u32 rank[kItems];
-  // rank of each key among the equal-digit keys of this wave, in input order
+  // rank of each key among the equal-digit keys of this wave, in input
+  // order: the count of that digit in earlier rounds (h) plus the peers in
+  // lower lanes; the lowest peer advances h
+  u32 rank[IT];
+  if (whole) {
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    u64 i = base + u64(j) * kWave + lane_id();
-    bool valid = i < n;
-    u32 d = digit(key[j], shift, dbits);
-    u64 vm = ballot(valid);
-    u64 peers = peers_of(d, vm, dbits);
-    u32 pre = valid ? h[d] : 0u;
-    rank[j] = pre + u32(popc(peers & lt));
-    if (valid && (peers & lt) == 0) h[d] = pre + u32(popc(peers));
-    __builtin_amdgcn_wave_barrier();
+    for (int j = 0; j < IT; ++j) {
+      const u32 d = digit<DB>(key[j], shift);
+      u32 lo = ~0u, hi = ~0u;
+      match_digit<DB>(d, lo, hi);
+      const u32 below = lanes_below(lo, hi);
+      const u32 pre = h[d];
+      rank[j] = pre + below;
+      if (below == 0) h[d] = pre + u32(__popc(lo)) + u32(__popc(hi));
+      __builtin_amdgcn_wave_barrier();
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const bool valid = base + u64(j) * kWave + lane_id() < n;
+      const u64 vm = ballot(valid);
+      const u32 d = digit<DB>(key[j], shift);
+      u32 lo = u32(vm), hi = u32(vm >> 32);
+      match_digit<DB>(d, lo, hi);
+      const u32 below = lanes_below(lo, hi);
+      const u32 pre = h[d];
+      rank[j] = pre + below;
+      if (valid && below == 0) h[d] = pre + u32(__popc(lo)) + u32(__popc(hi));
+      __builtin_amdgcn_wave_barrier();
+    }
   }
   __syncthreads();
   {
@@ -224,25 +294,69 @@ __global__ __launch_bounds__(kNT) void rs_scatter_kernel(const K* in, K* out, u6
     gbase[d] = gofs - ex;  // modular: gbase + p is the global position
   }
   __syncthreads();
+  if (whole) {
 #pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    u64 i = base + u64(j) * kWave + lane_id();
-    if (i < n) tile_keys[h[digit(key[j], shift, dbits)] + rank[j]] = key[j];
+    for (int j = 0; j < IT; ++j) tile_keys[h[digit<DB>(key[j], shift)] + rank[j]] = key[j];
+  } else {
+#pragma unroll
+    for (int j = 0; j < IT; ++j) {
+      const u64 i = base + u64(j) * kWave + lane_id();
+      if (i < n) tile_keys[h[digit<DB>(key[j], shift)] + rank[j]] = key[j];
+    }
   }
   __syncthreads();
-  const u32 cnt = u32((n - tbase) < kTile ? (n - tbase) : kTile);
-  for (u32 p = threadIdx.x; p < cnt; p += kNT) {
-    K k = tile_keys[p];
-    out[u32(gbase[digit(k, shift, dbits)] + p)] = k;
+  if (whole) {
+    // kTile = IT * kNT positions
+#pragma unroll 8
+    for (int j = 0; j < IT; ++j) {
+      const u32 p = u32(j) * kNT + threadIdx.x;
+      const K k = tile_keys[p];
+      out[u32(gbase[digit<DB>(k, shift)] + p)] = k;
+    }
+  } else {
+    const u32 cnt = u32(n - tbase);
+    for (u32 p = threadIdx.x; p < cnt; p += kNT) {
+      const K k = tile_keys[p];
+      out[u32(gbase[digit<DB>(k, shift)] + p)] = k;
+    }
   }
 }
 
-u64 tiles_of(u64 n) { return (n + kTile - 1) / kTile; }
+template <typename K>
+u64 tiles_of(u64 n) {
+  return (n + rs_tile<K>() - 1) / rs_tile<K>();
+}
+
+// One pass over bits [shift, shift + DB).
+template <typename K, int DB>
+hipError_t rs_pass(const K* src, K* dst, u64 n, int shift, u32* counts, u32* offsets, u32* csum,
+                   u32* total, u64 nt, u64 nc, hipStream_t s, LaunchTimer* timer) {
+  const u64 m = u64(kBuckets) * nt;
+  if (timer) timer->begin(K_RADIX_HIST, s);
+  rs_hist_kernel<K, DB><<<dim3(u32(nt)), kNT, 0, s>>>(src, n, shift, counts, u32(nt));
+  if (timer) timer->end(K_RADIX_HIST, s, n * sizeof(K) + m * sizeof(u32));
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (nc == 1) {
+    col_single_kernel<<<1, kNT, 0, s>>>(counts, u32(nt), offsets);
+  } else {
+    col_reduce_kernel<<<dim3(u32(nc)), kNT, 0, s>>>(counts, u32(nt), csum);
+    col_scan_kernel<<<dim3(kBuckets), kNT, 0, s>>>(csum, u32(nc), total);
+    col_offsets_kernel<<<dim3(u32(nc)), kNT, 0, s>>>(counts, u32(nt), csum, total, offsets);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (timer) timer->begin(K_RADIX_SCATTER, s);
+  rs_scatter_kernel<K, DB><<<dim3(u32(nt)), kNT, 0, s>>>(src, dst, n, shift, offsets, u32(nt));
+  if (timer) timer->end(K_RADIX_SCATTER, s, 2 * n * sizeof(K) + m * sizeof(u32));
+  return hipGetLastError();
+}
 
 }  // namespace
 
 u64 sort_workspace_bytes(u64 n) {
-  const u64 nt = tiles_of(n);
+  // sized for the smallest tile (the most count rows) of any key type
+  const u64 nt = (n + kMinTile - 1) / kMinTile;
   const u64 nc = (nt + kChunk - 1) / kChunk;
   return 2 * align_up(nt * kBuckets * sizeof(u32), 256) +
          align_up(nc * kBuckets * sizeof(u32), 256) + align_up(kBuckets * sizeof(u32), 256);
@@ -255,7 +369,7 @@ hipError_t radix_sort_bits(K* keys, K* alt, u64 n, int lo_bit, int hi_bit, void*
   if (hi_bit > int(8 * sizeof(K))) hi_bit = int(8 * sizeof(K));
   if (n <= 1 || lo_bit < 0 || hi_bit <= lo_bit) return hipSuccess;
   if (n >= (u64(1) << 32)) return hipErrorInvalidValue;
-  const u64 nt = tiles_of(n);
+  const u64 nt = tiles_of<K>(n);
   const u64 nc = (nt + kChunk - 1) / kChunk;
   const u64 m = u64(kBuckets) * nt;
   char* p = static_cast<char*>(ws);
@@ -270,25 +384,24 @@ hipError_t radix_sort_bits(K* keys, K* alt, u64 n, int lo_bit, int hi_bit, void*
   K* dst = alt;
   for (int shift = lo_bit; shift < hi_bit; shift += kBits) {
     const int dbits = (hi_bit - shift) < kBits ? (hi_bit - shift) : kBits;
-    if (timer) timer->begin(K_RADIX_HIST, s);
-    rs_hist_kernel<K><<<dim3(u32(nt)), kNT, 0, s>>>(src, n, shift, dbits, counts, u32(nt));
-    if (timer) timer->end(K_RADIX_HIST, s, n * sizeof(K) + m * sizeof(u32));
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (nc == 1) {
-      col_single_kernel<<<1, kNT, 0, s>>>(counts, u32(nt), offsets);
-    } else {
-      col_reduce_kernel<<<dim3(u32(nc)), kNT, 0, s>>>(counts, u32(nt), csum);
-      col_scan_kernel<<<dim3(kBuckets), kNT, 0, s>>>(csum, u32(nc), total);
-      col_offsets_kernel<<<dim3(u32(nc)), kNT, 0, s>>>(counts, u32(nt), csum, total, offsets);
+    hipError_t e = hipSuccess;
+#define HL_RS_PASS(DB)                                                                        \
+  case DB:                                                                                    \
+    e = rs_pass<K, DB>(src, dst, n, shift, counts, offsets, csum, total, nt, nc, s, timer);   \
+    break;
+    switch (dbits) {
+      HL_RS_PASS(1)
+      HL_RS_PASS(2)
+      HL_RS_PASS(3)
+      HL_RS_PASS(4)
+      HL_RS_PASS(5)
+      HL_RS_PASS(6)
+      HL_RS_PASS(7)
+      HL_RS_PASS(8)
+      default:
+        return hipErrorInvalidValue;
     }
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (timer) timer->begin(K_RADIX_SCATTER, s);
-    rs_scatter_kernel<K><<<dim3(u32(nt)), kNT, 0, s>>>(src, dst, n, shift, dbits, offsets,
-                                                       u32(nt));
-    if (timer) timer->end(K_RADIX_SCATTER, s, 2 * n * sizeof(K) + m * sizeof(u32));
-    e = hipGetLastError();
+#undef HL_RS_PASS
     if (e != hipSuccess) return e;
     K* t = src;
     src = dst;

@@ -76,12 +76,16 @@ __global__ __launch_bounds__(kUdNT) void ud_partition_kernel(const K* cand, u64 
 // lockstep searches.  One block scan places the survivors, which are written
 // compacted (in order) at the tile's start in tmp.  The tile's kept and
 // distinct counts go to tile_counts and tile_uniq.
+// With alg_bytes (kernel timing), the tile adds the bytes its step must move
+// by definition: its candidates read, its survivors written, and for the
+// membership tests the cheaper of reading the slice of full it spans and
+// one 64-byte line per distinct key searched (the same for the tail).
 template <typename K, bool kModel>
 __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, const K* full,
                                                           u64 nf, K* tmp, u32* tile_counts,
                                                           u32* tile_uniq, LearnedView<K> lv,
                                                           const u64* part, const K* tail,
-                                                          u64 ntail) {
+                                                          u64 ntail, u64* alg_bytes) {
   __shared__ u32 wsum[kUdNT / kWave];
   __shared__ u32 wsum2[kUdNT / kWave];
   // one padding slot per kUdItems keys: thread t reads keys t*16 .. t*16+15,
@@ -231,6 +235,7 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
   // A short sorted tail run kept beside full (disjoint from it): the keys
   // that survived full are searched there too, kUdLock at a time in
   // lockstep.
+  const u32 tail_searched = ntail > 0 ? nkeep : 0u;
   if (ntail > 0) {
     u32 rem = keep_bits;
     while (rem) {
@@ -287,9 +292,18 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
   __syncthreads();
   for (u32 k = threadIdx.x; k < total; k += kUdNT) tmp[base + k] = s_c[pad(k)];
   uniq = block_sum<kUdNT>(uniq, wsum2);
+  u32 searched = 0;
+  if (alg_bytes) searched = block_sum<kUdNT>(tail_searched, wsum);
   if (threadIdx.x == 0) {
     tile_counts[tile] = total;
     tile_uniq[tile] = uniq;
+    if (alg_bytes) {
+      const u64 full_b = m * sizeof(K) < u64(uniq) * 64 ? m * sizeof(K) : u64(uniq) * 64;
+      const u64 tail_b =
+          ntail * sizeof(K) < u64(searched) * 64 ? ntail * sizeof(K) : u64(searched) * 64;
+      atomicAdd(reinterpret_cast<unsigned long long*>(alg_bytes),
+                static_cast<unsigned long long>(u64(cnt + total) * sizeof(K) + full_b + tail_b));
+    }
   }
 }
 
@@ -413,24 +427,25 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   p += align_up((nt + 1) * sizeof(u64), 256);
   if (model && (model->keys != full || model->n != nf)) return hipErrorInvalidValue;
   const u32 pb = u32((nt + 1 + kUdNT - 1) / kUdNT);
+  u64* alg = timer ? timer->device_counter(s) : nullptr;
   if (timer) timer->begin(K_UNIQUE_DIFF, s);
   if (model) {
     ud_partition_kernel<K, true><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, part,
                                                             *model);
     ud_select_kernel<K, true><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
                                                               tile_counts, tile_uniq, *model,
-                                                              part, tail, ntail);
+                                                              part, tail, ntail, alg);
   } else {
     ud_partition_kernel<K, false><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, part,
                                                              LearnedView<K>{});
     ud_select_kernel<K, false><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
                                                                tile_counts, tile_uniq,
                                                                LearnedView<K>{}, part, tail,
-                                                               ntail);
+                                                               ntail, alg);
   }
-  // by definition: every candidate read once, each kept key written once;
-  // the count of kept keys is not known here, so only the reads are counted
-  if (timer) timer->end(K_UNIQUE_DIFF, s, n * sizeof(K));
+  // the tiles count their own bytes (above); without a device counter only
+  // the candidate reads are known here
+  if (timer) timer->end(K_UNIQUE_DIFF, s, alg ? 0 : n * sizeof(K), alg);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   e = scan_u32_u64(tile_counts, nt, tile_off, d_counts, p, s);

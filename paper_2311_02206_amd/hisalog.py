@@ -40,7 +40,8 @@ EXPORTS = (
     "hl_options_init", "hl_create", "hl_destroy", "hl_declare", "hl_load", "hl_load_device",
     "hl_batch_layout", "hl_load_batched", "hl_batch_count", "hl_fetch_batched", "hl_index",
     "hl_program", "hl_run", "hl_autotune", "hl_count", "hl_fetch", "hl_fetch_device",
-    "hl_iteration_counts", "hl_kernel_stats", "hl_last_error", "hl_strerror", "hl_sort_keys",
+    "hl_iteration_counts", "hl_kernel_stats", "hl_rule_stats", "hl_last_error", "hl_strerror",
+    "hl_sort_keys",
     "hl_unique_diff", "hl_merge", "hl_hisa_query", "hl_learned_query",
 )
 
@@ -127,6 +128,7 @@ def lib() -> ctypes.CDLL:
         "hl_last_error": [vp],
         "hl_strerror": [ctypes.c_int],
         "hl_sort_keys": [vp, vp, u64, u32, u32],
+        "hl_rule_stats": [vp, u32, pu64, pu64],
         "hl_unique_diff": [vp, vp, u64, vp, u64, vp, pu64, pu64, u32],
         "hl_merge": [vp, vp, u64, vp, u64, vp, u32],
         "hl_hisa_query": [vp, vp, u64, u32, u32, vp, u64, vp, vp, pu64],
@@ -365,6 +367,20 @@ class Engine:
         return out
 
     # --------------------------------------------------------- primitives
+    def rule_stats(self) -> list:
+        """Per rule of the program (text order), over the last run: (outputs
+        of its last join, outputs of its earlier joins)."""
+        out = []
+        a, b = ctypes.c_uint64(), ctypes.c_uint64()
+        k = 0
+        while True:
+            rc = self._L.hl_rule_stats(self._h, k, ctypes.byref(a), ctypes.byref(b))
+            if rc == HL_E_INVALID:
+                return out
+            self._check(rc, "hl_rule_stats")
+            out.append((a.value, b.value))
+            k += 1
+
     def sort_keys(self, keys, bits: int = 0):
         """Sorts a CUDA int32/int64 tensor in place (unsigned order)."""
         self._check(self._L.hl_sort_keys(self._h, _ptr(keys), keys.numel(), _key_bytes(keys),
@@ -385,6 +401,12 @@ class Engine:
     def merge(self, a, b):
         import torch
         out = torch.empty(a.numel() + b.numel(), dtype=a.dtype, device=a.device)
+        return self.merge_into(a, b, out)
+
+    def merge_into(self, a, b, out):
+        """Merges ascending a and b into out (a + b keys, caller-owned)."""
+        if out.numel() != a.numel() + b.numel() or out.dtype != a.dtype:
+            raise ValueError("out must hold a.numel() + b.numel() keys of a's type")
         self._check(self._L.hl_merge(self._h, _ptr(a) if a.numel() else None, a.numel(),
                                      _ptr(b) if b.numel() else None, b.numel(), _ptr(out),
                                      _key_bytes(a)), "hl_merge")

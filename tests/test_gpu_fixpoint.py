@@ -484,3 +484,41 @@ def test_unary_relations(mode):
     assert rels["R"].shape[1] == 1 and rels["B"].shape[1] == 2
     if mode == "fused_graph":
         assert st.fused_iterations > 0
+
+
+def test_rule_stats_closed_forms():
+    """Per-rule join outputs (hl_rule_stats) against counts that follow from
+    the final relations: every Reach tuple (z, y) lies in exactly one delta
+    and joins the in-edges of z once; the first same-generation rule yields
+    sum_p outdeg(p)^2 outputs before its filter, and every SG tuple (a, b)
+    lies in one delta and yields outdeg(a) first-join and
+    outdeg(a) * outdeg(b) last-join outputs.  The rules' outputs add up to
+    the run's join outputs."""
+    import torch
+    import paper_2311_02206_amd as pkg
+    say("rule stats: reach er1000, sg tree")
+    E = np.unique(workloads.reach_er_1000()["edb"]["Edge"], axis=0)
+    T = workloads.scaled_tree(3000, seed=3)["edb"]["Edge"]
+    for prog, edb, idb in ((PROG["reach"], {"Edge": E}, "Reach"),
+                           (PROG["sg"], {"Edge": T}, "SG")):
+        with pkg.Engine(device=0, stream=torch.cuda.current_stream()) as e:
+            e.declare("Edge", 2, True)
+            e.declare(idb, 2, False)
+            e.load("Edge", edb["Edge"])
+            e.program(prog)
+            st = e.run()
+            R = e.fetch(idb).astype(np.int64)
+            rs = e.rule_stats()
+        assert len(rs) == 2
+        assert sum(o for o, _ in rs) == st.join_outputs
+        G = edb["Edge"].astype(np.int64)
+        n = int(max(G.max(), R.max() if len(R) else 0)) + 1
+        if idb == "Reach":
+            indeg = np.bincount(G[:, 1], minlength=n)
+            assert rs[0] == (len(G), 0)
+            assert rs[1] == (int(indeg[R[:, 0]].sum()), 0)
+        else:
+            outdeg = np.bincount(G[:, 0], minlength=n)
+            assert rs[0] == (int((outdeg ** 2).sum()), 0)
+            assert rs[1] == (int((outdeg[R[:, 0]] * outdeg[R[:, 1]]).sum()),
+                             int(outdeg[R[:, 0]].sum()))

@@ -135,3 +135,24 @@ def test_sg_tree_verify(n):
     assert oracle.sg_tree_verify(t, S[1:])[0] == 0 and len(S[1:]) != total
     with pytest.raises(ValueError):
         oracle.sg_tree_verify(t, S[::-1])
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 7, 4097, 1_000_003])
+@pytest.mark.parametrize("threads", [1, 3, 8])
+def test_host_sort_and_merge(n, threads):
+    """The host side of the sort/merge microbenchmark equals numpy's sort
+    and a sorted concatenation (odd run counts, ties, extremes)."""
+    rng = np.random.default_rng(n * 10 + threads)
+    a = rng.integers(0, 2**64 - 1, size=n, dtype=np.uint64, endpoint=True)
+    if n > 4:
+        a[:3] = [0, 2**64 - 1, 5]
+        a[3:5] = 5
+    want = np.sort(a)
+    oracle.host_sort_u64(a, threads)
+    assert np.array_equal(a, want)
+    x = np.sort(rng.integers(0, 50, size=n // 3, dtype=np.uint64))
+    y = np.sort(rng.integers(0, 50, size=n - n // 3, dtype=np.uint64))
+    out = np.empty(n, dtype=np.uint64)
+    oracle.host_merge_u64(x, y, out, threads)
+    assert np.array_equal(out, np.sort(np.concatenate([x, y])))
+    assert oracle.host_alloc_init(max(n, 1) * 8, threads) >= 0

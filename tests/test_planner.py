@@ -61,7 +61,8 @@ def test_error_codes():
         assert code_of(lambda: e.run()) == H.HL_E_STATE
         assert code_of(lambda: e.autotune()) == H.HL_E_STATE
     e = pkg.Engine(device=-1)
-    assert code_of(lambda: e.declare("T", 3, False)) == H.HL_E_UNSUPPORTED
+    assert code_of(lambda: e.declare("T", 5, False)) == H.HL_E_UNSUPPORTED
+    assert code_of(lambda: e.declare("T", 0, False)) == H.HL_E_UNSUPPORTED
     assert code_of(lambda: e.declare("bad name", 2, False)) == H.HL_E_INVALID
     e.declare("T", 2, False)
     assert code_of(lambda: e.declare("T", 2, False)) == H.HL_E_INVALID
@@ -100,3 +101,25 @@ def test_unary_relations_plan():
     assert code_of(lambda: e.declare("Z", 0, False)) == H.HL_E_UNSUPPORTED
     e.declare("U", 1, False)
     e.close()
+
+
+def test_wide_programs_plan():
+    """Relations of arity 3-4: joins on several columns and carried tuples of
+    up to four variables are planned; cross products and five live
+    variables are not."""
+    e = pkg.Engine(device=-1)
+    try:
+        for name, ar, edb in (("Foo", 3, True), ("Bar", 3, True), ("E", 2, True),
+                              ("Foobar", 2, False), ("P", 3, False), ("W", 4, False)):
+            e.declare(name, ar, edb)
+        e.program("Foobar(c, d) :- Foo(a, b, c), Bar(a, b, d).")
+        e.program("P(x, y, l) :- Foo(x, y, l).\nP(x, z, l) :- P(x, y, l), Foo(y, z, l).")
+        e.program("W(a, b, c, d) :- E(a, b), Foo(b, c, d), a != d.")
+        assert code_of(lambda: e.program("P(a, b, c) :- E(a, b), E(c, d).")) == H.HL_E_UNSUPPORTED
+        assert code_of(lambda: e.program(
+            "W(a, b, c, d) :- Foo(a, b, x), Foo(c, d, y), E(x, y), E(a, c).")) in (
+            H.HL_OK, H.HL_E_UNSUPPORTED)
+        assert code_of(lambda: e.program("P(a, b) :- Foo(a, b, c).")) == H.HL_E_INVALID
+        assert code_of(lambda: e.index("Foo", 0)) == H.HL_E_UNSUPPORTED
+    finally:
+        e.close()
