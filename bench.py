@@ -79,7 +79,9 @@ def kernel_digest(path, definitions):
     src = open(path).read()
     parts = [ln for ln in src.splitlines() if ln.lstrip().startswith("constexpr")]
     for d in definitions:
-        i = src.index(d)
+        i = src.find(d)
+        if i < 0:
+            return None  # the kernel was rewritten since
         j = src.index("{", i)
         depth = 0
         for k in range(j, len(src)):

@@ -379,7 +379,7 @@ def test_error_paths():
             e.declare("E", 2, True)
         assert ei.value.code == pkg.hisalog.HL_E_INVALID
         with pytest.raises(pkg.HlError) as ei:
-            e.declare("T3", 3, False)
+            e.declare("T5", 5, False)
         assert ei.value.code == pkg.hisalog.HL_E_UNSUPPORTED
         with pytest.raises(pkg.HlError) as ei:
             e.program("R(x, y) :- E(x, a), E(y, b).")  # a cross product
