@@ -850,7 +850,7 @@ def batched_variant(stream, n_inst, sample, steps, program, verify=True):
             same &= bool(np.array_equal(ek.fetch("Reach"), e.fetch_batched("Reach", k)))
         ek.close()
     value = forms["fused_graph"]["value"]
-    one_rate = one_tuples / one_t
+    one_rate = one_tuples / one_t if one_t > 0 else None
     same_forms = forms["plain"].pop("counts") == forms["fused_graph"].pop("counts")
     out = {"workload": f"batched_reach_{n_inst}_instances", "value": value, "unit": "tuples/s",
            "engine": "batched, fused small iterations from HIP graphs",
@@ -859,7 +859,7 @@ def batched_variant(stream, n_inst, sample, steps, program, verify=True):
            "ebm_k": 1.5, "forms": forms, "forms_same_deltas": bool(same_forms),
            "one_at_a_time": {"value": one_rate, "unit": "tuples/s", "sample_instances": sample,
                              "ms": one_t * 1e3},
-           "vs_one_at_a_time": value / one_rate,
+           "vs_one_at_a_time": value / one_rate if one_rate else None,
            "sample_identical": bool(same) if verify else None}
     e.close()
     return out

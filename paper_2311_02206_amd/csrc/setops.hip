@@ -195,12 +195,17 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
         at[q] = full + lo;
       }
       if (kModel) {
+        // the model's window and the tile's slice both hold each key's
+        // lower bound, so their intersection does too
         u64 wa[kUdLock];
         L = 0;
 #pragma unroll
         for (int q = 0; q < kUdLock; ++q) {
           u64 wb;
           lm_window(lv, c[q], wa[q], wb);
+          wa[q] = wa[q] > lo ? wa[q] : lo;
+          wb = wb < hi ? wb : hi;
+          if (wb < wa[q]) wb = wa[q];
           L = (wb - wa[q]) > L ? (wb - wa[q]) : L;
         }
         // widening a window keeps the answer inside it; stay within full
