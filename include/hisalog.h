@@ -363,6 +363,24 @@ const char* hl_strerror(int code);
  * Algorithm 1: LSD order over the packed columns).  n < 2^32. */
 int hl_sort_keys(hl_engine* e, void* d_keys, uint64_t n, uint32_t key_bytes, uint32_t bits);
 
+/* hl_sort_keys without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The sort's second buffer and its
+ * count matrices live in a static device array of 64 MiB that each GPU the
+ * library runs on holds until the process ends; the call makes no
+ * hipMalloc, hipFree or other allocating call (a copy back into d_keys
+ * when the result ends in the scratch copy is a device-to-device copy).
+ * Same arguments, order and result as hl_sort_keys; n keys must fit the
+ * scratch with their count matrices: about 15.7 million 4-byte or 8.1
+ * million 8-byte keys (HL_E_CAPACITY beyond, with the sizes in
+ * hl_last_error).  Every call on one GPU shares that GPU's array: calls
+ * that overlap on one GPU (from several threads or engines) race; calls
+ * made one after another do not, since each synchronises the engine's
+ * stream before returning.  Nothing in the array needs to start at zero:
+ * every count a pass reads was written by that pass. */
+int hl_sort_keys_noalloc(hl_engine* e, void* d_keys, uint64_t n, uint32_t key_bytes,
+                         uint32_t bits);
+
 /* d_out = unique(d_sorted) minus d_full (Section 5.1, "Populating delta";
  * Section 4.2, "Deduplication").  d_sorted: n ascending keys (repeats
  * allowed); d_full: n_full ascending distinct keys; d_out: room for n keys.

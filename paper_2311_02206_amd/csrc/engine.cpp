@@ -494,6 +494,8 @@ struct hl_engine {
   // outputs of its last join (its candidates before filters) and of its
   // earlier joins (the materialised intermediate results)
   std::vector<u64> rule_out, rule_mid;
+  // this device's address of the static scratch of hl_sort_keys_noalloc
+  void* noalloc = nullptr;
   bool ran = false;
 
   // run state
@@ -2594,6 +2596,9 @@ int hl_create(const hl_options* opt, hl_engine** out) {
       HIPCK(hipStreamCreateWithFlags(&e->stream, hipStreamNonBlocking));
       e->own_stream = true;
     }
+    // the device address of the static scratch (the device is current
+    // here); hl_sort_keys_noalloc passes only this address to kernels
+    HIPCK(hl::noalloc_scratch(e->device, &e->noalloc));
     e->mem.init(o.arena, o.arena_bytes, o.hbm_budget_bytes, e->stream);
     e->mem.set_caching(!(o.flags & HL_FLAG_NO_EBM));
     e->d_small = static_cast<u64*>(e->mem.alloc(hl_engine::kSmall * sizeof(u64)));
@@ -2867,6 +2872,42 @@ int hl_sort_keys(hl_engine* e, void* d_keys, uint64_t n, uint32_t key_bytes, uin
       u64* s = nullptr;
       HIPCK(hl::radix_sort<u64>(static_cast<u64*>(d_keys), static_cast<u64*>(e->alt.p), n, b,
                                 e->ws.p, e->stream, &s, nullptr));
+      sorted = s;
+    }
+    if (sorted != d_keys)
+      HIPCK(hipMemcpyAsync(d_keys, sorted, n * key_bytes, hipMemcpyDeviceToDevice, e->stream));
+    e->sync();
+  });
+}
+
+int hl_sort_keys_noalloc(hl_engine* e, void* d_keys, uint64_t n, uint32_t key_bytes,
+                         uint32_t bits) {
+  return guard(e, [&] {
+    if (e->device < 0) fail(HL_E_STATE, "planning-only engine (device -1)");
+    if (!valid_key_bytes(key_bytes)) fail(HL_E_INVALID, "key_bytes must be 4 or 8");
+    const int b = bits ? int(bits) : int(8 * key_bytes);
+    if (b > int(8 * key_bytes)) fail(HL_E_INVALID, "bits exceed the key width");
+    if (n <= 1) return;
+    if (!d_keys) fail(HL_E_INVALID, "null keys");
+    // the second buffer of the sort, then its count matrices
+    const u64 room = hl::noalloc_scratch_bytes();
+    const u64 alt_bytes = hl::align_up(n * key_bytes, 256);
+    if (n >= room || alt_bytes + hl::sort_workspace_bytes(n) > room)
+      fail(HL_E_CAPACITY, std::to_string(n) + " keys of " + std::to_string(key_bytes) +
+                              " bytes need more than the " + std::to_string(room >> 20) +
+                              " MiB of static scratch");
+    if (!e->noalloc) fail(HL_E_STATE, "no static scratch on this device");
+    char* sc = static_cast<char*>(e->noalloc);
+    void* sorted = nullptr;
+    if (key_bytes == 4) {
+      u32* s = nullptr;
+      HIPCK(hl::radix_sort<u32>(static_cast<u32*>(d_keys), reinterpret_cast<u32*>(sc), n, b,
+                                sc + alt_bytes, e->stream, &s, nullptr));
+      sorted = s;
+    } else {
+      u64* s = nullptr;
+      HIPCK(hl::radix_sort<u64>(static_cast<u64*>(d_keys), reinterpret_cast<u64*>(sc), n, b,
+                                sc + alt_bytes, e->stream, &s, nullptr));
       sorted = s;
     }
     if (sorted != d_keys)

@@ -125,6 +125,14 @@ hipError_t learned_query(const LearnedView<u32>& lv, const u32* q, u64 nq, u32* 
 hipError_t learned_query(const LearnedView<u64>& lv, const u64* q, u64 nq, u32* out,
                          hipStream_t s);
 
+// ------------------------------------------------- static scratch
+// Bytes of the file-scope device array behind the entry point that
+// allocates nothing (noalloc.hip).
+u64 noalloc_scratch_bytes();
+// With `device` current: that device's address of the array (looked up
+// with hipGetSymbolAddress on the first call for the device, then kept).
+hipError_t noalloc_scratch(int device, void** ptr);
+
 // ---------------------------------------------------------------- misc
 hipError_t fill_zero(void* p, u64 bytes, hipStream_t s);
 // *d_max = max(*d_max, v[i]); *d_max must be initialised.

@@ -24,6 +24,8 @@ HL_E_DEVICE = -3
 HL_E_STATE = -4
 HL_E_CAPACITY = -5
 HL_E_UNSUPPORTED = -6
+# size of the static device scratch behind hl_sort_keys_noalloc
+NOALLOC_SCRATCH_BYTES = 64 << 20
 HL_FLAG_NO_EBM = 0x1
 HL_FLAG_KERNEL_TIMING = 0x2
 HL_FLAG_LEARNED_INDEX = 0x4
@@ -41,7 +43,7 @@ EXPORTS = (
     "hl_batch_layout", "hl_load_batched", "hl_batch_count", "hl_fetch_batched", "hl_index",
     "hl_program", "hl_run", "hl_autotune", "hl_count", "hl_fetch", "hl_fetch_device",
     "hl_iteration_counts", "hl_kernel_stats", "hl_rule_stats", "hl_last_error", "hl_strerror",
-    "hl_sort_keys",
+    "hl_sort_keys", "hl_sort_keys_noalloc",
     "hl_unique_diff", "hl_merge", "hl_hisa_query", "hl_learned_query",
 )
 
@@ -128,6 +130,7 @@ def lib() -> ctypes.CDLL:
         "hl_last_error": [vp],
         "hl_strerror": [ctypes.c_int],
         "hl_sort_keys": [vp, vp, u64, u32, u32],
+        "hl_sort_keys_noalloc": [vp, vp, u64, u32, u32],
         "hl_rule_stats": [vp, u32, pu64, pu64],
         "hl_unique_diff": [vp, vp, u64, vp, u64, vp, pu64, pu64, u32],
         "hl_merge": [vp, vp, u64, vp, u64, vp, u32],
@@ -385,6 +388,14 @@ class Engine:
         """Sorts a CUDA int32/int64 tensor in place (unsigned order)."""
         self._check(self._L.hl_sort_keys(self._h, _ptr(keys), keys.numel(), _key_bytes(keys),
                                          bits), "hl_sort_keys")
+        return keys
+
+    def sort_keys_noalloc(self, keys, bits: int = 0):
+        """sort_keys through the entry point that allocates nothing (its
+        scratch is a static device array of NOALLOC_SCRATCH_BYTES)."""
+        self._check(self._L.hl_sort_keys_noalloc(self._h, _ptr(keys), keys.numel(),
+                                                 _key_bytes(keys), bits),
+                    "hl_sort_keys_noalloc")
         return keys
 
     def unique_diff(self, sorted_keys, full):
