@@ -99,6 +99,17 @@ extern "C" {
                                      outputs.  Bodies whose outputs exceed one
                                      sort chunk keep the materialised form */
 
+#define HL_FLAG_NO_LEVELS 0x80u /* keep every relation probed as a join inner
+                                  as one sorted array, its indexes rebuilt
+                                  (or refitted) after every merge, instead
+                                  of two levels: full with its indexes plus
+                                  a short tail run with indexes of its own,
+                                  which joins probe both of and whose
+                                  deltas leave full and its indexes
+                                  untouched until the tail is folded in (the
+                                  merge-cost problem of Section 6.5).
+                                  Results are identical */
+
 /* Kernels reported by hl_kernel_stats. */
 #define HL_KERNEL_RADIX_HIST 0    /* digit histogram of one radix pass */
 #define HL_KERNEL_RADIX_SCATTER 1 /* stable scatter of one radix pass */
@@ -159,7 +170,19 @@ typedef struct hl_options {
                                 expand workgroup handles: 1024, 2048 or
                                 4096 (0: 2048); hl_autotune measures all
                                 three */
-  uint32_t reserved[5];      /* must be zero */
+  uint32_t sort_tile;        /* keys per radix sort tile: 4096 or 8192 (0:
+                                8192); hl_autotune measures both */
+  uint32_t diff_tile;        /* sorted candidates per set difference tile:
+                                2048 or 4096 (0: 4096); hl_autotune
+                                measures both */
+  uint32_t reserved0;        /* must be zero */
+  uint64_t tail_min_bytes;   /* a relation's new tuples go to a sorted tail
+                                run beside its full relation (folded in when
+                                the tail passes an eighth of full) once full
+                                holds this many bytes (0: 64 MiB); for a
+                                relation probed as a join inner the tail
+                                has indexes of its own (see
+                                HL_FLAG_NO_LEVELS).  Results are identical */
 } hl_options;
 
 typedef struct hl_stats {
@@ -285,6 +308,8 @@ typedef struct hl_tuning {
   double first_seconds;    /* fixpoint time under the engine's settings
                               before tuning */
   uint32_t expand_tile;    /* the chosen hl_options.expand_tile */
+  uint32_t sort_tile;      /* the chosen hl_options.sort_tile */
+  uint32_t diff_tile;      /* the chosen hl_options.diff_tile */
   uint32_t reserved;
 } hl_tuning;
 
@@ -292,7 +317,9 @@ typedef struct hl_tuning {
  * settings are searched one dimension at a time, starting from the
  * engine's own: how join inners are probed (HISA hash at load factor 0.5,
  * at 0.8, or the learned position index), the join expand tile (1024,
- * 2048 or 4096 outputs per workgroup), the eager buffer growth factor
+ * 2048 or 4096 outputs per workgroup), the radix sort tile (4096 or 8192
+ * keys), the set difference tile (2048 or 4096 candidates), the eager
+ * buffer growth factor
  * (1.5 or 8), in-tile dedup of join outputs (off or on), nested
  * evaluation of two-join bodies (off or on, where a rule has one) and,
  * where the recursive rules qualify, fused small iterations (off, on, or

@@ -393,6 +393,10 @@ struct Relation {
   Buf full, full_spare, delta, cand;
   u64 n_full = 0, n_delta = 0, n_cand = 0;
   Index idx[2];
+  // indexes of the tail run of a relation probed as a join inner (kept as
+  // two levels): tidx[0] over the tail itself, tidx[1] over its
+  // column-swapped copy (tidx[1].keys)
+  Index tidx[2];
   std::vector<Index> widx;  // indexes of wide plans
   std::vector<u64> delta_counts, new_counts;
   // in-tile dedup of the joins deriving this relation: on while they made
@@ -477,6 +481,8 @@ struct hl_engine {
   int sort_chunk_log2 = 31;
   u32 fused_capacity = 0;  // 0: the largest that fits
   int join_items = 8;      // join expand outputs per thread (4, 8, 16)
+  int sort_items = 32;     // radix sort keys per thread of a tile (16, 32)
+  int diff_items = 16;     // set difference candidates per thread of a tile (8, 16)
   Memory mem;
   std::string err;
 
@@ -1166,7 +1172,8 @@ struct hl_engine {
     HIPCK(hl::wide_permute<K>(src, n_src, R.arity, w, ix.perm, kp<K>(tmp[0]), stream));
     reserve(ws, hl::sort_workspace_bytes(n_src), hl::sort_workspace_bytes(n_src) * 2);
     K* sorted = nullptr;
-    HIPCK(hl::radix_sort<K>(kp<K>(tmp[0]), kp<K>(alt), n_src, bits, ws.p, stream, &sorted, kt()));
+    HIPCK(hl::radix_sort<K>(kp<K>(tmp[0]), kp<K>(alt), n_src, bits, ws.p, stream, &sorted, kt(),
+                            sort_items));
     if (from_scratch || ix.n == 0) {
       reserve(ix.keys, n_src * sizeof(K), u64(double(n_src) * sizeof(K) * 1.5));
       HIPCK(hipMemcpyAsync(ix.keys.p, sorted, n_src * sizeof(K), hipMemcpyDeviceToDevice, stream));
@@ -1250,7 +1257,8 @@ struct hl_engine {
     HIPCK(hl::swap_cols<K>(src, n_src, w, kp<K>(tmp[0]), stream));
     reserve(ws, hl::sort_workspace_bytes(n_src), hl::sort_workspace_bytes(n_src) * 2);
     K* sorted = nullptr;
-    HIPCK(hl::radix_sort<K>(kp<K>(tmp[0]), kp<K>(alt), n_src, bits, ws.p, stream, &sorted, kt()));
+    HIPCK(hl::radix_sort<K>(kp<K>(tmp[0]), kp<K>(alt), n_src, bits, ws.p, stream, &sorted, kt(),
+                            sort_items));
     if (from_scratch || ix.n == 0) {
       reserve(ix.keys, n_src * sizeof(K), u64(double(n_src) * sizeof(K) * 1.5));
       HIPCK(hipMemcpyAsync(ix.keys.p, sorted, n_src * sizeof(K), hipMemcpyDeviceToDevice, stream));
@@ -1288,13 +1296,14 @@ struct hl_engine {
       reserve(ws, hl::sort_workspace_bytes(R.n_raw), hl::sort_workspace_bytes(R.n_raw) * 2);
       K* sorted = nullptr;
       HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_raw, kbits(R), ws.p, stream, &sorted,
-                              kt()));
+                              kt(), sort_items));
       K* other = sorted == kp<K>(R.cand) ? kp<K>(alt) : kp<K>(R.cand);
       reserve(R.full, R.n_raw * sizeof(K), R.n_raw * sizeof(K));
       reserve(ws, hl::unique_diff_workspace_bytes(R.n_raw),
               hl::unique_diff_workspace_bytes(R.n_raw) * 2);
       HIPCK(hl::unique_diff<K>(sorted, R.n_raw, static_cast<const K*>(nullptr), 0, other,
-                               kp<K>(R.full), d_small, ws.p, stream, kt()));
+                               kp<K>(R.full), d_small, ws.p, stream, kt(), nullptr, nullptr, 0,
+                               diff_items));
       HIPCK(hipMemcpyAsync(h_small, d_small, sizeof(u64), hipMemcpyDeviceToHost, stream));
       sync();
       R.n_full = h_small[0];
@@ -1495,9 +1504,16 @@ struct hl_engine {
       Index& ix = I.idx[s.inner_col];
       if (ix.n == 0 || (learned() ? !ix.lm_ok : ix.cap == 0)) return;
       const K* inner = s.inner_col == 0 ? kp<K>(I.full) : kp<K>(ix.keys);
+      // an inner kept as two levels: its tail run is probed through the
+      // tail's own index, and the expand covers both runs of every outer
+      // tuple (entries n + i are outer tuple i's runs in the tail)
+      Index& tx = I.tidx[s.inner_col];
+      const bool two = I.n_tail > 0 && tx.n > 0 && levels_ok(I);
+      const K* inner2 = two ? (s.inner_col == 0 ? kp<K>(I.fz_tail[0]) : kp<K>(tx.keys)) : nullptr;
       JoinSpec js = s.js;
       js.w = w;
-      if (n >= (u64(1) << 32)) fail(HL_E_UNSUPPORTED, "join outer side of 2^32 or more tuples");
+      if (n >= (u64(1) << 32) || (two && 2 * n >= (u64(1) << 32)))
+        fail(HL_E_UNSUPPORTED, "join outer side of 2^32 or more probes");
       const bool last = q + 1 == p.steps.size();
       js.dd = (last && H.dedup && (flags & HL_FLAG_JOIN_DEDUP)) ? 1 : 0;
       if (js.dd) {
@@ -1514,23 +1530,27 @@ struct hl_engine {
           reserve(ws, hl::sort_workspace_bytes(n), hl::sort_workspace_bytes(n) * 2);
           K* grouped = nullptr;
           HIPCK(hl::radix_sort_bits<K>(kp<K>(grp[0]), kp<K>(grp[1]), n, g == 0 ? w : 0,
-                                       g == 0 ? 2 * w : w, ws.p, stream, &grouped, kt()));
+                                       g == 0 ? 2 * w : w, ws.p, stream, &grouped, kt(),
+                                       sort_items));
           cur = grouped;
         }
       }
-      reserve_grow(join_start, n * sizeof(u32));
-      reserve_grow(join_len, n * sizeof(u32));
-      reserve_grow(join_off, n * sizeof(u64));
-      if (learned())
-        HIPCK(hl::join_probe_learned<K>(cur, n, js, ix.view<K>(),
-                                        static_cast<u32*>(join_start.p),
-                                        static_cast<u32*>(join_len.p), stream, kt()));
-      else
-        HIPCK(hl::join_probe<K>(cur, n, js, static_cast<const Slot*>(ix.table.p), ix.cap,
-                                static_cast<u32*>(join_start.p), static_cast<u32*>(join_len.p),
-                                stream, kt()));
-      reserve(ws, hl::scan_workspace_bytes(n), hl::scan_workspace_bytes(n) * 2);
-      HIPCK(hl::scan_u32_u64(static_cast<u32*>(join_len.p), n, static_cast<u64*>(join_off.p),
+      const u64 ne = two ? 2 * n : n;  // probe entries
+      reserve_grow(join_start, ne * sizeof(u32));
+      reserve_grow(join_len, ne * sizeof(u32));
+      reserve_grow(join_off, ne * sizeof(u64));
+      for (int level = 0; level < (two ? 2 : 1); ++level) {
+        Index& lx = level ? tx : ix;
+        u32* st_p = static_cast<u32*>(join_start.p) + (level ? n : 0);
+        u32* ln_p = static_cast<u32*>(join_len.p) + (level ? n : 0);
+        if (learned())
+          HIPCK(hl::join_probe_learned<K>(cur, n, js, lx.view<K>(), st_p, ln_p, stream, kt()));
+        else
+          HIPCK(hl::join_probe<K>(cur, n, js, static_cast<const Slot*>(lx.table.p), lx.cap, st_p,
+                                  ln_p, stream, kt()));
+      }
+      reserve(ws, hl::scan_workspace_bytes(ne), hl::scan_workspace_bytes(ne) * 2);
+      HIPCK(hl::scan_u32_u64(static_cast<u32*>(join_len.p), ne, static_cast<u64*>(join_off.p),
                              d_small + 1, ws.p, stream));
       HIPCK(hipMemcpyAsync(h_small + 1, d_small + 1, sizeof(u64), hipMemcpyDeviceToHost, stream));
       sync();
@@ -1546,10 +1566,10 @@ struct hl_engine {
         // One join's outputs exceed one sort: expand a range of tiles at a
         // time (at most `cap` outputs) and absorb each range into the head
         // relation's pending delta, so memory stays bounded by the range.
-        const u64 nt = hl::join_tiles(n, total, join_items);
-        reserve_grow(join_parts, hl::join_parts(n, total, join_items) * sizeof(u64));
+        const u64 nt = hl::join_tiles(ne, total, join_items);
+        reserve_grow(join_parts, hl::join_parts(ne, total, join_items) * sizeof(u64));
         u64* parts = static_cast<u64*>(join_parts.p);
-        HIPCK(hl::join_partition(static_cast<u64*>(join_off.p), n, total, parts, stream,
+        HIPCK(hl::join_partition(static_cast<u64*>(join_off.p), ne, total, parts, stream,
                                  join_items));
         const u64 tile_out = hl::join_tile_outputs(join_items);
         const u64 per = std::max<u64>(1, cap / tile_out);
@@ -1561,10 +1581,10 @@ struct hl_engine {
             h_small[0] = 0;
             HIPCK(hipMemcpyAsync(d_cursor, h_small, sizeof(u64), hipMemcpyHostToDevice, stream));
           }
-          HIPCK(hl::join_expand_tiles<K>(cur, n, static_cast<u64*>(join_off.p),
+          HIPCK(hl::join_expand_tiles<K>(cur, ne, static_cast<u64*>(join_off.p),
                                          static_cast<u32*>(join_start.p), inner, total, js, parts,
                                          t0, tiles, kp<K>(jchunk), d_cursor, stream, kt(),
-                                         join_items));
+                                         join_items, inner2, two ? n : ne));
           u64 m;
           if (filt) {
             HIPCK(hipMemcpyAsync(h_small, d_cursor, sizeof(u64), hipMemcpyDeviceToHost, stream));
@@ -1578,8 +1598,8 @@ struct hl_engine {
             HIPCK(hipMemcpyAsync(h_small + 3, parts + t1, sizeof(u64), hipMemcpyDeviceToHost,
                                  stream));
             sync();
-            const u64 j0 = std::min(t0 * tile_out, n + total) - h_small[2];
-            const u64 j1 = std::min(t1 * tile_out, n + total) - h_small[3];
+            const u64 j0 = std::min(t0 * tile_out, ne + total) - h_small[2];
+            const u64 j1 = std::min(t1 * tile_out, ne + total) - h_small[3];
             m = j1 - j0;
           }
           st.candidates += m;
@@ -1602,11 +1622,11 @@ struct hl_engine {
         h_small[0] = base;
         HIPCK(hipMemcpyAsync(d_cursor, h_small, sizeof(u64), hipMemcpyHostToDevice, stream));
       }
-      reserve_grow(join_parts, hl::join_parts(n, total, join_items) * sizeof(u64));
-      HIPCK(hl::join_expand<K>(cur, n, static_cast<u64*>(join_off.p),
+      reserve_grow(join_parts, hl::join_parts(ne, total, join_items) * sizeof(u64));
+      HIPCK(hl::join_expand<K>(cur, ne, static_cast<u64*>(join_off.p),
                                static_cast<u32*>(join_start.p), inner, total, js,
                                static_cast<u64*>(join_parts.p), filtered ? out : out + base,
-                               d_cursor, stream, kt(), join_items));
+                               d_cursor, stream, kt(), join_items, inner2, two ? n : ne));
       u64 produced = total;
       if (filtered) {
         HIPCK(hipMemcpyAsync(h_small, d_cursor, sizeof(u64), hipMemcpyDeviceToHost, stream));
@@ -1632,6 +1652,9 @@ struct hl_engine {
   // sort chunk (the materialised chain then runs instead).
   template <typename K>
   bool run_nested(const Plan& p, const K* cur, u64 n) {
+    for (const Step& s : p.steps)
+      if (rels[s.inner_rel].n_tail > 0 && levels_ok(rels[s.inner_rel]))
+        return false;  // an inner kept as two levels: the materialised chain
     Relation& H = rels[p.head];
     hl::NestedJoin<K> nj{};
     for (int q = 0; q < 2; ++q) {
@@ -1691,7 +1714,7 @@ struct hl_engine {
     if (!learned() || R.n_full == 0) return false;
     Index& ix = R.idx[0];
     bool use = ix.lm_ok && ix.lm_keys == R.full.p && ix.lm_n == R.n_full;
-    if (!use && !ix.used && tail_ok(R) && R.n_full * sizeof(K) >= kTailMinFullBytes &&
+    if (!use && !ix.used && tail_ok(R) && R.n_full * sizeof(K) >= tail_min_bytes &&
         R.n_full >= 8 * n_cand) {
       const int caller = marks.empty() ? -1 : marks.back().first;
       mark(HL_PHASE_INDEX);
@@ -1726,14 +1749,12 @@ struct hl_engine {
         }
       }
     } resume{this, caller};
-    mark(HL_PHASE_MERGE);
-    flush_tail<K>(R);  // the membership test below searches full only
     const int bits = kbits(R);
     reserve_grow(alt, m * sizeof(K));
     reserve(ws, hl::sort_workspace_bytes(m), hl::sort_workspace_bytes(m) * 2);
     K* sorted = nullptr;
     mark(HL_PHASE_SORT);
-    HIPCK(hl::radix_sort<K>(keys, kp<K>(alt), m, bits, ws.p, stream, &sorted, kt()));
+    HIPCK(hl::radix_sort<K>(keys, kp<K>(alt), m, bits, ws.p, stream, &sorted, kt(), sort_items));
     K* other = sorted == keys ? kp<K>(alt) : keys;
     mark(HL_PHASE_DIFF);
     reserve(ws, hl::unique_diff_workspace_bytes(m), hl::unique_diff_workspace_bytes(m) * 2);
@@ -1741,8 +1762,10 @@ struct hl_engine {
     u64* hc = h_small + kChunkSlots;
     hl::LearnedView<K> mv{};
     const bool use_model = diff_model<K>(R, m, &mv);
+    // the tail run beside full, if any, is tested in the same pass
     HIPCK(hl::unique_diff<K>(sorted, m, kp<K>(R.full), R.n_full, other, sorted, dc, ws.p, stream,
-                             kt(), use_model ? &mv : nullptr));
+                             kt(), use_model ? &mv : nullptr,
+                             R.n_tail ? kp<K>(R.fz_tail[0]) : nullptr, R.n_tail, diff_items));
     HIPCK(hipMemcpyAsync(hc, dc, 2 * sizeof(u64), hipMemcpyDeviceToHost, stream));
     sync();
     u64 d = hc[0];
@@ -1750,7 +1773,7 @@ struct hl_engine {
     const u64 p = R.n_pend;
     if (p > 0 && d > 0) {
       HIPCK(hl::unique_diff<K>(sorted, d, kp<K>(R.pend[0]), p, other, sorted, dc, ws.p, stream,
-                               kt()));
+                               kt(), nullptr, nullptr, 0, diff_items));
       HIPCK(hipMemcpyAsync(hc, dc, sizeof(u64), hipMemcpyDeviceToHost, stream));
       sync();
       d = hc[0];
@@ -1812,7 +1835,7 @@ struct hl_engine {
       K* sorted = nullptr;
       mark(HL_PHASE_SORT);
       HIPCK(hl::radix_sort<K>(kp<K>(R.cand), kp<K>(alt), R.n_cand, kbits(R), ws.p, stream,
-                              &sorted, kt()));
+                              &sorted, kt(), sort_items));
       Buf& sbuf = (sorted == kp<K>(R.cand)) ? R.cand : alt;
       Buf& obuf = (sorted == kp<K>(R.cand)) ? alt : R.cand;
       reserve(ws, hl::unique_diff_workspace_bytes(R.n_cand),
@@ -1825,7 +1848,7 @@ struct hl_engine {
       HIPCK(hl::unique_diff<K>(kp<K>(sbuf), R.n_cand, kp<K>(R.full), R.n_full, kp<K>(obuf),
                                kp<K>(sbuf), d_small + 2 * q, ws.p, stream, kt(),
                                use_model ? &mv : nullptr,
-                               R.n_tail ? kp<K>(R.fz_tail[0]) : nullptr, R.n_tail));
+                               R.n_tail ? kp<K>(R.fz_tail[0]) : nullptr, R.n_tail, diff_items));
       std::swap(R.delta, sbuf);
     }
     HIPCK(hipMemcpyAsync(h_small, d_small, 2 * idbs.size() * sizeof(u64), hipMemcpyDeviceToHost,
@@ -1838,7 +1861,10 @@ struct hl_engine {
       h_small[2 * c.first + 1] = c.second.second;
     }
     u64 total = 0;
-    std::vector<int> grown;
+    // grown: full took the delta (indexes refreshed with it); folded: full
+    // took a two-level relation's tail, whose indexes already hold the
+    // delta; tail_grown: only the tail of a two-level relation grew
+    std::vector<int> grown, folded, tail_grown;
     mark(HL_PHASE_MERGE);
     for (size_t q = 0; q < idbs.size(); ++q) {
       Relation& R = rels[idbs[q]];
@@ -1852,7 +1878,26 @@ struct hl_engine {
       total += D;
       if (D == 0) continue;
       const u64 F = R.n_full;
-      if (tail_ok(R) && F * sizeof(K) >= kTailMinFullBytes && (R.n_tail + D) * 8 <= F) {
+      if (levels_ok(R) && F * sizeof(K) >= tail_min_bytes) {
+        // a relation probed as a join inner, kept as two levels: a small
+        // delta goes into the tail run and the tail's indexes, so full and
+        // its indexes stay as they are; a delta that would make the tail
+        // larger than an eighth of full folds the tail into full, whose
+        // indexes are then refreshed
+        delta_into_tail<K>(R);
+        if (R.n_tail * 8 <= F) {
+          tail_grown.push_back(idbs[q]);
+        } else {
+          fold_inner_tail<K>(R);
+          folded.push_back(idbs[q]);
+        }
+        continue;
+      }
+      if (R.n_tail > 0 && levels_ok(R)) {
+        // full shrank below the threshold (a new run): fold first
+        fold_inner_tail<K>(R);
+      }
+      if (tail_ok(R) && F * sizeof(K) >= tail_min_bytes && (R.n_tail + D) * 8 <= F) {
         // small delta against a large full: merge it into the tail run only
         const u64 T = R.n_tail;
         if (T == 0) {
@@ -1905,7 +1950,9 @@ struct hl_engine {
       refresh_wide<K>(grown);
     } else {
       for (int r : grown) update_swapped<K>(rels[r], kp<K>(rels[r].delta), rels[r].n_delta, false);
+      grown.insert(grown.end(), folded.begin(), folded.end());
       refresh_indexes<K>(grown);
+      refresh_tail_indexes<K>(tail_grown);
     }
     mark(-1);
     return total;
@@ -1956,9 +2003,121 @@ struct hl_engine {
   // the same pass; below this size rewriting full costs less than those
   // searches.
   static constexpr u64 kTailMinFullBytes = u64(64) << 20;
+  u64 tail_min_bytes = kTailMinFullBytes;  // hl_options.tail_min_bytes
   // Fused iterations fold a long tail into a full below this size (one
   // merge of well under a millisecond) rather than merge into it each time.
   static constexpr u64 kFoldLimitBytes = u64(1) << 30;
+
+  // Whether relation R, probed as a join inner, may be kept as two levels
+  // (full with its indexes, plus a tail run with indexes of its own).
+  bool levels_ok(const Relation& R) const {
+    return !R.edb && !wide && (R.idx[0].used || R.idx[1].used) &&
+           !(flags & (HL_FLAG_NO_EBM | HL_FLAG_NO_LEVELS));
+  }
+
+  // Merges R's delta into its tail run (and the tail's column-swapped copy
+  // when column 1 is probed).
+  template <typename K>
+  void delta_into_tail(Relation& R) {
+    const u64 T = R.n_tail, D = R.n_delta;
+    if (T == 0) {
+      reserve(R.fz_tail[0], D * sizeof(K), u64(ebm_k * double(D) * sizeof(K)));
+      HIPCK(hipMemcpyAsync(R.fz_tail[0].p, R.delta.p, D * sizeof(K), hipMemcpyDeviceToDevice,
+                           stream));
+    } else {
+      reserve(R.fz_tail[1], (T + D) * sizeof(K), u64((double(T) + ebm_k * double(D)) * sizeof(K)));
+      reserve(ws, hl::merge_workspace_bytes(T, D), hl::merge_workspace_bytes(T, D) * 2);
+      HIPCK(hl::merge<K>(kp<K>(R.fz_tail[0]), T, kp<K>(R.delta), D, kp<K>(R.fz_tail[1]), ws.p,
+                         stream, kt()));
+      std::swap(R.fz_tail[0], R.fz_tail[1]);
+    }
+    R.n_tail = T + D;
+    R.tidx[0].n = R.n_tail;
+    if (R.idx[1].used) {
+      // the tail's swapped copy takes the swapped, sorted delta
+      Index& tx = R.tidx[1];
+      reserve_grow(alt, D * sizeof(K));
+      reserve_grow(tmp[0], D * sizeof(K));
+      HIPCK(hl::swap_cols<K>(kp<K>(R.delta), D, w, kp<K>(tmp[0]), stream));
+      reserve(ws, hl::sort_workspace_bytes(D), hl::sort_workspace_bytes(D) * 2);
+      K* sorted = nullptr;
+      HIPCK(hl::radix_sort<K>(kp<K>(tmp[0]), kp<K>(alt), D, 2 * w, ws.p, stream, &sorted, kt(),
+                              sort_items));
+      if (tx.n == 0) {
+        reserve(tx.keys, D * sizeof(K), u64(ebm_k * double(D) * sizeof(K)));
+        HIPCK(hipMemcpyAsync(tx.keys.p, sorted, D * sizeof(K), hipMemcpyDeviceToDevice, stream));
+      } else {
+        reserve(tx.spare, (tx.n + D) * sizeof(K),
+                u64((double(tx.n) + ebm_k * double(D)) * sizeof(K)));
+        reserve(ws, hl::merge_workspace_bytes(tx.n, D), hl::merge_workspace_bytes(tx.n, D) * 2);
+        HIPCK(hl::merge<K>(kp<K>(tx.keys), tx.n, sorted, D, kp<K>(tx.spare), ws.p, stream, kt()));
+        std::swap(tx.keys, tx.spare);
+      }
+      tx.n += D;
+    }
+  }
+
+  // Folds the tail of a two-level relation into full, and the tail's
+  // swapped copy into full's; full's indexes must be refreshed afterwards.
+  template <typename K>
+  void fold_inner_tail(Relation& R) {
+    if (R.idx[1].used && R.tidx[1].n > 0) {
+      Index& ix = R.idx[1];
+      Index& tx = R.tidx[1];
+      const u64 total = ix.n + tx.n;
+      reserve(ix.spare, total * sizeof(K), u64((double(ix.n) + ebm_k * double(tx.n)) * sizeof(K)));
+      reserve(ws, hl::merge_workspace_bytes(ix.n, tx.n), hl::merge_workspace_bytes(ix.n, tx.n) * 2);
+      HIPCK(hl::merge<K>(kp<K>(ix.keys), ix.n, kp<K>(tx.keys), tx.n, kp<K>(ix.spare), ws.p, stream,
+                         kt()));
+      std::swap(ix.keys, ix.spare);
+      ix.n = total;
+    }
+    flush_tail<K>(R);
+  }
+
+  // Hash tables (one synchronisation for the run counts of all of them) or
+  // learned models of the tail indexes of the listed two-level relations.
+  template <typename K>
+  void refresh_tail_indexes(const std::vector<int>& which) {
+    std::vector<std::pair<int, int>> todo;
+    for (int r : which)
+      for (int c = 0; c < 2; ++c)
+        if (rels[r].idx[c].used) todo.push_back({r, c});
+    if (todo.empty()) return;
+    auto keys_of = [&](Relation& R, int c) {
+      return c == 0 ? kp<K>(R.fz_tail[0]) : kp<K>(R.tidx[1].keys);
+    };
+    if (learned()) {
+      for (auto& rc : todo) {
+        Relation& R = rels[rc.first];
+        fit_index_model<K>(R, R.tidx[rc.second], keys_of(R, rc.second));
+      }
+      return;
+    }
+    if (todo.size() > kChunkSlots) fail(HL_E_UNSUPPORTED, "too many indexes");
+    for (size_t q = 0; q < todo.size(); ++q) {
+      Relation& R = rels[todo[q].first];
+      HIPCK(hl::hisa_count_runs<K>(keys_of(R, todo[q].second), R.tidx[todo[q].second].n, w,
+                                   d_small + q, stream));
+    }
+    HIPCK(hipMemcpyAsync(h_small, d_small, todo.size() * sizeof(u64), hipMemcpyDeviceToHost,
+                         stream));
+    sync();
+    for (size_t q = 0; q < todo.size(); ++q) {
+      Relation& R = rels[todo[q].first];
+      Index& tx = R.tidx[todo[q].second];
+      const u64 runs = h_small[q];
+      tx.runs = runs;
+      u64 cap = u64(std::ceil(double(runs) / load_factor));
+      cap = std::max(cap, runs + 1);
+      cap = std::max<u64>(cap, 16);
+      reserve(tx.table, cap * sizeof(Slot), cap * sizeof(Slot) * 2);
+      tx.cap = cap;
+      HIPCK(hl::fill_zero(tx.table.p, cap * sizeof(Slot), stream));
+      HIPCK(hl::hisa_build<K>(keys_of(R, todo[q].second), tx.n, w,
+                              static_cast<Slot*>(tx.table.p), cap, stream, kt()));
+    }
+  }
 
   // Folds R's tail run into its full relation (one merge).
   template <typename K>
@@ -1979,6 +2138,10 @@ struct hl_engine {
     R.n_full = F + T;
     R.idx[0].n = R.n_full;
     R.n_tail = 0;
+    for (Index& tx : R.tidx) {
+      tx.n = tx.cap = 0;
+      tx.lm_ok = false;
+    }
     fz_live = false;  // the fused path's device counts describe the old split
   }
 
@@ -2249,6 +2412,8 @@ struct hl_engine {
     float lf, k;
     u32 fl;  // kTunedFlags bits
     int items;  // join expand outputs per thread
+    int sort_items = 32;  // radix sort keys per thread of a tile
+    int diff_items = 16;  // set difference candidates per thread of a tile
   };
   static constexpr u32 kTunedFlags = HL_FLAG_LEARNED_INDEX | HL_FLAG_JOIN_DEDUP | HL_FLAG_FUSED |
                                      HL_FLAG_HIP_GRAPH | HL_FLAG_NESTED_JOINS;
@@ -2258,6 +2423,8 @@ struct hl_engine {
     ebm_k = t.k;
     flags = (flags & ~kTunedFlags) | t.fl;
     join_items = t.items;
+    sort_items = t.sort_items;
+    diff_items = t.diff_items;
   }
 
   // Fastest of `reps` timed runs after a warm-up; +inf if the device ran
@@ -2284,7 +2451,7 @@ struct hl_engine {
 
   void autotune(u32 reps, hl_tuning* out) {
     if (rules.empty()) fail(HL_E_STATE, "no program");
-    Setting best{load_factor, ebm_k, flags & kTunedFlags, join_items};
+    Setting best{load_factor, ebm_k, flags & kTunedFlags, join_items, sort_items, diff_items};
     std::vector<std::vector<u64>> ref, got;
     u32 trials = 1;
     double best_t = trial(best, reps, &ref);
@@ -2308,9 +2475,12 @@ struct hl_engine {
     // 1. how join inners are probed
     const Setting base = best;
     for (const Setting& t :
-         {Setting{0.5f, base.k, base.fl & ~u32(HL_FLAG_LEARNED_INDEX), base.items},
-          Setting{0.8f, base.k, base.fl & ~u32(HL_FLAG_LEARNED_INDEX), base.items},
-          Setting{base.lf, base.k, base.fl | HL_FLAG_LEARNED_INDEX, base.items}})
+         {Setting{0.5f, base.k, base.fl & ~u32(HL_FLAG_LEARNED_INDEX), base.items,
+                  base.sort_items, base.diff_items},
+          Setting{0.8f, base.k, base.fl & ~u32(HL_FLAG_LEARNED_INDEX), base.items,
+                  base.sort_items, base.diff_items},
+          Setting{base.lf, base.k, base.fl | HL_FLAG_LEARNED_INDEX, base.items, base.sort_items,
+                  base.diff_items}})
       if (t.lf != base.lf || t.fl != base.fl) consider(t);
     // join expand tile: outputs per thread
     {
@@ -2320,6 +2490,18 @@ struct hl_engine {
         t.items = it;
         if (it != b.items) consider(t);
       }
+    }
+    // radix sort tile (4,096 or 8,192 keys) and set difference tile (2,048
+    // or 4,096 candidates)
+    {
+      Setting t = best;
+      t.sort_items = best.sort_items == 32 ? 16 : 32;
+      consider(t);
+    }
+    {
+      Setting t = best;
+      t.diff_items = best.diff_items == 16 ? 8 : 16;
+      consider(t);
     }
     // 2. eager buffer growth factor
     {
@@ -2365,6 +2547,8 @@ struct hl_engine {
       out->flags = best.fl;
       out->trials = trials;
       out->expand_tile = u32(256 * best.items);
+      out->sort_tile = u32(256 * best.sort_items);
+      out->diff_tile = u32(256 * best.diff_items);
       out->best_seconds = best_t;
       out->first_seconds = first_t;
     }
@@ -2395,6 +2579,10 @@ struct hl_engine {
       R.raw_cand = 0;
       R.idx[0].lm_ok = R.idx[1].lm_ok = false;
       for (Index& ix : R.widx) ix.lm_ok = false;
+      for (Index& tx : R.tidx) {
+        tx.n = tx.cap = 0;
+        tx.lm_ok = false;
+      }
       if (!R.edb) {
         R.n_full = 0;
         R.idx[0].n = R.idx[1].n = 0;
@@ -2556,8 +2744,7 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   if (opt) o = *opt;
   if (!(o.ebm_k >= 1.0f) || !(o.hash_load_factor > 0.0f && o.hash_load_factor <= 1.0f))
     return HL_E_INVALID;
-  for (u32 r : o.reserved)
-    if (r) return HL_E_INVALID;
+  if (o.reserved0) return HL_E_INVALID;
   if (o.arena && o.arena_bytes < 4096) return HL_E_INVALID;
   if (o.sort_chunk_log2 != 0 && (o.sort_chunk_log2 < 12 || o.sort_chunk_log2 > 31))
     return HL_E_INVALID;
@@ -2567,6 +2754,8 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   if (o.expand_tile != 0 && o.expand_tile != 1024 && o.expand_tile != 2048 &&
       o.expand_tile != 4096)
     return HL_E_INVALID;
+  if (o.sort_tile != 0 && o.sort_tile != 4096 && o.sort_tile != 8192) return HL_E_INVALID;
+  if (o.diff_tile != 0 && o.diff_tile != 2048 && o.diff_tile != 4096) return HL_E_INVALID;
   if (o.device == -1) {
     // planning-only engine: declarations and programs, no device work
     hl_engine* e = new (std::nothrow) hl_engine();
@@ -2589,6 +2778,9 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   e->sort_chunk_log2 = o.sort_chunk_log2 ? int(o.sort_chunk_log2) : 31;
   e->fused_capacity = o.fused_capacity;
   e->join_items = o.expand_tile ? int(o.expand_tile / 256) : 8;
+  e->sort_items = o.sort_tile ? int(o.sort_tile / 256) : 32;
+  e->tail_min_bytes = o.tail_min_bytes ? o.tail_min_bytes : hl_engine::kTailMinFullBytes;
+  e->diff_items = o.diff_tile ? int(o.diff_tile / 256) : 16;
   int rc = guard(e, [&] {
     if (o.stream) {
       e->stream = static_cast<hipStream_t>(o.stream);

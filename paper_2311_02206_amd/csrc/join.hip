@@ -247,11 +247,16 @@ struct WideGather {
 };
 
 // ITEMS outputs per thread: a tile of kNT * ITEMS outputs and outer tuples.
+// An inner relation kept as two sorted runs (a large run and a short tail
+// beside it) is joined in one pass: entries i < n_split of off/start are
+// runs of outer tuple i in `inner`, entries n_split + i runs of the same
+// outer tuple in `inner2` (n_split == n_outer when there is one run).
 template <typename K, int ITEMS, typename G>
 __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer, const u64* off,
                                                      const u32* start, const K* inner,
-                                                     u64 total, G g, const u64* parts,
-                                                     u64 tile0, K* out, u64* cursor) {
+                                                     const K* inner2, u64 n_split, u64 total,
+                                                     G g, const u64* parts, u64 tile0, K* out,
+                                                     u64* cursor) {
   constexpr u64 kTile = u64(kNT) * ITEMS;
   constexpr int kItems = ITEMS;
   constexpr u32 kDedupSlots = 2 * u32(kTile);
@@ -278,7 +283,8 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   for (u32 k = threadIdx.x; k < la; k += kNT) {
     s_off[k] = u32(off[a0 + k] - b0);
     s_start[k] = start[a0 + k];
-    s_outer[k] = outer[a0 + k];
+    const u64 i = a0 + k;
+    s_outer[k] = outer[i < n_split ? i : i - n_split];
   }
   __syncthreads();
   // serial merge of this thread's slice of the tile's merged sequence
@@ -329,9 +335,10 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
       const bool here = u64(i) >= a0;
       const u64 pos = here ? u64(s_start[u64(i) - a0]) + (k - s_off[u64(i) - a0])
                            : u64(start[i]) + (b0 + k - off[i]);
-      const K ok = here ? s_outer[u64(i) - a0] : outer[i];
+      const K ok = here ? s_outer[u64(i) - a0] : outer[u64(i) < n_split ? i : i - n_split];
+      const K* in = u64(i) < n_split ? inner : inner2;
       bool pass;
-      v[r] = g(ok, inner[pos], pass);
+      v[r] = g(ok, in[pos], pass);
       if (pass) keep |= 1u << r;
     }
   }
@@ -534,7 +541,7 @@ template <typename K>
 hipError_t join_expand_tiles(const K* outer, u64 n_outer, const u64* off, const u32* start,
                              const K* inner, u64 total, const JoinSpec& js, const u64* parts,
                              u64 tile0, u64 tiles, K* out, u64* cursor, hipStream_t s,
-                             LaunchTimer* timer, int items) {
+                             LaunchTimer* timer, int items, const K* inner2, u64 n_split) {
   if (total == 0 || tiles == 0) return hipSuccess;
   if (!join_items_ok(items)) return hipErrorInvalidValue;
   const u64 nt = join_tiles(n_outer, total, items);
@@ -545,15 +552,19 @@ hipError_t join_expand_tiles(const K* outer, u64 n_outer, const u64* off, const 
   const size_t dyn = js.dd ? 2 * join_tile_outputs(items) * sizeof(K) : 0;
   const dim3 grid = dim3(u32(tiles));
   const PairGather<K> g{js};
+  if (!inner2 || n_split > n_outer) {
+    inner2 = inner;
+    n_split = n_outer;
+  }
   if (items == 4)
-    expand_kernel<K, 4><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, g,
-                                               parts, tile0, out, cursor);
+    expand_kernel<K, 4><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, inner2,
+                                               n_split, total, g, parts, tile0, out, cursor);
   else if (items == 16)
-    expand_kernel<K, 16><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, g,
-                                                parts, tile0, out, cursor);
+    expand_kernel<K, 16><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, inner2,
+                                                n_split, total, g, parts, tile0, out, cursor);
   else
-    expand_kernel<K, 8><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, total, g,
-                                               parts, tile0, out, cursor);
+    expand_kernel<K, 8><<<grid, kNT, dyn, s>>>(outer, n_outer, off, start, inner, inner2,
+                                               n_split, total, g, parts, tile0, out, cursor);
   // by definition: each inner tuple of a matched run read once, each output
   // written once, each outer tuple with its offset and run start read once
   // (apportioned to the launch's share of the tiles)
@@ -569,11 +580,13 @@ hipError_t join_expand_tiles(const K* outer, u64 n_outer, const u64* off, const 
 template <typename K>
 hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* start,
                        const K* inner, u64 total, const JoinSpec& js, u64* parts, K* out,
-                       u64* cursor, hipStream_t s, LaunchTimer* timer, int items) {
+                       u64* cursor, hipStream_t s, LaunchTimer* timer, int items,
+                       const K* inner2, u64 n_split) {
   hipError_t e = join_partition(off, n_outer, total, parts, s, items);
   if (e != hipSuccess || total == 0) return e;
   return join_expand_tiles<K>(outer, n_outer, off, start, inner, total, js, parts, 0,
-                              join_tiles(n_outer, total, items), out, cursor, s, timer, items);
+                              join_tiles(n_outer, total, items), out, cursor, s, timer, items,
+                              inner2, n_split);
 }
 
 template <typename K>
@@ -587,9 +600,9 @@ hipError_t wide_expand_tiles(const K* outer, u64 n_outer, const u64* off, const 
   if (n_outer >= (u64(1) << 32) || tile0 + tiles > nt || tiles >= (u64(1) << 31))
     return hipErrorInvalidValue;
   if (timer) timer->begin(K_JOIN_EXPAND, s);
-  expand_kernel<K, 8><<<dim3(u32(tiles)), kNT, 0, s>>>(outer, n_outer, off, start, inner, total,
-                                                       WideGather<K>{ws}, parts, tile0, out,
-                                                       cursor);
+  expand_kernel<K, 8><<<dim3(u32(tiles)), kNT, 0, s>>>(outer, n_outer, off, start, inner, inner,
+                                                       n_outer, total, WideGather<K>{ws}, parts,
+                                                       tile0, out, cursor);
   if (timer) {
     const double f = double(tiles) / double(nt);
     timer->end(K_JOIN_EXPAND, s,
@@ -641,10 +654,11 @@ hipError_t join_nested(const K* outer, u64 n, const NestedJoin<K>& nj, u32* coun
                                     u32*, hipStream_t, LaunchTimer*);                         \
   template hipError_t join_expand_tiles<K>(const K*, u64, const u64*, const u32*, const K*,  \
                                            u64, const JoinSpec&, const u64*, u64, u64, K*,   \
-                                           u64*, hipStream_t, LaunchTimer*, int);            \
+                                           u64*, hipStream_t, LaunchTimer*, int, const K*,   \
+                                           u64);                                               \
   template hipError_t join_expand<K>(const K*, u64, const u64*, const u32*, const K*, u64,  \
                                      const JoinSpec&, u64*, K*, u64*, hipStream_t,            \
-                                     LaunchTimer*, int);                                      \
+                                     LaunchTimer*, int, const K*, u64);                        \
   template hipError_t project<K>(const K*, u64, const JoinSpec&, K*, u64*, hipStream_t);   \
   template hipError_t wide_expand_tiles<K>(const K*, u64, const u64*, const u32*, const K*,  \
                                            u64, const WideSpec&, const u64*, u64, u64, K*,   \

@@ -61,20 +61,22 @@ u64 scan_workspace_bytes(u64 n);
 hipError_t scan_u32_u64(const u32* in, u64 n, u64* out, u64* d_total, void* ws, hipStream_t s);
 
 // ---------------------------------------------------------- radix sort
+// Workspace of a sort of n keys with any tile size.
 u64 sort_workspace_bytes(u64 n);
 // LSD radix sort of the low `bits` bits of n keys (the bits above must be
 // zero).  Ping-pongs between `keys` and `alt`; *sorted receives whichever
 // holds the result (the other one is free afterwards).  n must be below
-// 2^32.
+// 2^32.  tile_items: keys per thread of a tile, 32 (8,192-key tiles) or 16.
 template <typename K>
 hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted,
-                      LaunchTimer* timer = nullptr);
+                      LaunchTimer* timer = nullptr, int tile_items = 32);
 // Stable LSD radix sort on bits [lo_bit, hi_bit) of the keys only: keys
 // equal on those bits keep their input order (used to group an array by one
 // column).  Same buffers and limits as radix_sort.
 template <typename K>
 hipError_t radix_sort_bits(K* keys, K* alt, u64 n, int lo_bit, int hi_bit, void* ws,
-                           hipStream_t s, K** sorted, LaunchTimer* timer = nullptr);
+                           hipStream_t s, K** sorted, LaunchTimer* timer = nullptr,
+                           int tile_items = 32);
 
 // --------------------------------------------- unique + set difference
 u64 unique_diff_workspace_bytes(u64 n);
@@ -85,11 +87,12 @@ u64 unique_diff_workspace_bytes(u64 n);
 // spans and the membership tests outside LDS go through the model.  With a
 // tail (ntail sorted unique keys, disjoint from full), keys it holds are
 // dropped too: the result is unique(sorted) \ (full U tail).
+// `items`: candidates per thread of a tile, 16 (4,096-candidate tiles) or 8.
 template <typename K>
 hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
                        u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer = nullptr,
                        const LearnedView<K>* model = nullptr, const K* tail = nullptr,
-                       u64 ntail = 0);
+                       u64 ntail = 0, int items = 16);
 
 // --------------------------------------------------------------- merge
 u64 merge_workspace_bytes(u64 na, u64 nb);
@@ -269,10 +272,14 @@ hipError_t join_partition(const u64* off, u64 n_outer, u64 total, u64* parts, hi
 // Unfiltered outputs go to out[j - j0], j0 the first output index of tile0;
 // filtered ones (or with js.dd) are appended at *cursor.
 template <typename K>
+// An inner kept as two sorted runs: with inner2, entries n_split + i of
+// off/start (n_outer = 2 * n_split entries) are the runs of outer tuple i
+// in inner2; the outer array then holds n_split tuples.
 hipError_t join_expand_tiles(const K* outer, u64 n_outer, const u64* off, const u32* start,
                              const K* inner, u64 total, const JoinSpec& js, const u64* parts,
                              u64 tile0, u64 tiles, K* out, u64* cursor, hipStream_t s,
-                             LaunchTimer* timer = nullptr, int items = 8);
+                             LaunchTimer* timer = nullptr, int items = 8,
+                             const K* inner2 = nullptr, u64 n_split = ~u64(0));
 // Expands every (outer, inner run) pair.  Without a filter, output j goes
 // to out[j]; with one, survivors are appended at *cursor (device, u64).
 // With js.dd, an output equal to an earlier output of the same tile (its
@@ -281,7 +288,8 @@ hipError_t join_expand_tiles(const K* outer, u64 n_outer, const u64* off, const 
 template <typename K>
 hipError_t join_expand(const K* outer, u64 n_outer, const u64* off, const u32* start,
                        const K* inner, u64 total, const JoinSpec& js, u64* parts, K* out,
-                       u64* cursor, hipStream_t s, LaunchTimer* timer = nullptr, int items = 8);
+                       u64* cursor, hipStream_t s, LaunchTimer* timer = nullptr, int items = 8,
+                       const K* inner2 = nullptr, u64 n_split = ~u64(0));
 // A rule body of one atom: projects (and filters) every outer pair.
 template <typename K>
 hipError_t project(const K* in, u64 n, const JoinSpec& js, K* out, u64* cursor, hipStream_t s);

@@ -36,22 +36,15 @@ constexpr u32 kChunk = 64;  // tiles per chunk of the column scan
 static_assert(kNT == kBuckets, "one thread per digit bucket");
 
 // Keys per thread of a tile (histogram and scatter use the same tiles):
-// 8,192-key tiles for both key widths.  The per-tile work of both kernels
-// (count rows, sub-histogram clearing and reduction, the digit scan) is
-// spread over more keys than with 4,096-key tiles, and each digit's run in
-// a tile is longer, so the scatter's writes are less fragmented.  Measured
-// on 2^28 32-bit keys: 108 against 89 Gkeys/s with 4,096-key tiles; on 5e8
-// 64-bit keys: 16.4 against 18.5 ms (the 64 KB LDS copy of a 64-bit tile
-// leaves two workgroups per CU, which is enough).
-template <typename K>
-struct RsItems {
-  static constexpr int value = 32;
-};
-template <typename K>
-constexpr u64 rs_tile() {
-  return u64(kNT) * RsItems<K>::value;
-}
-constexpr u64 kMinTile = u64(kNT) * 32;
+// 32 (8,192-key tiles) by default, or 16 (4,096), a run-time choice that
+// the autotuner measures.  Larger tiles spread the per-tile work of both
+// kernels (count rows, sub-histogram clearing and reduction, the digit
+// scan) over more keys, and each digit's run in a tile is longer, so the
+// scatter's writes are less fragmented: on 2^28 32-bit keys 108 against 89
+// Gkeys/s; on 5e8 64-bit keys 16.4 against 18.5 ms (the 64 KB LDS copy of a
+// 64-bit tile leaves two workgroups per CU, which is enough).  Smaller
+// sorts (2^24 keys and below) gain a little from the smaller tiles.
+constexpr u64 kMinTile = u64(kNT) * 16;  // the smallest tile
 
 // A pass sorts on bits [shift, shift + DB) of the key, DB <= 8.
 template <int DB, typename K>
@@ -89,11 +82,10 @@ constexpr int kSubs = kWaves * kSubsPerWave;
 constexpr int kSubStride = kBuckets + 1;
 constexpr int kHistWords = (kSubs * kSubStride + 3) / 4 * 4;
 
-template <typename K, int DB>
+template <typename K, int DB, int IT>
 __global__ __launch_bounds__(kNT) void rs_hist_kernel(const K* keys, u64 n, int shift,
                                                       u32* counts, u32 ntiles) {
-  constexpr int IT = RsItems<K>::value;
-  constexpr u64 kTile = rs_tile<K>();
+  constexpr u64 kTile = u64(kNT) * IT;
   constexpr u32 kWaveTile = kWave * IT;
   __shared__ __align__(16) u32 hist[kHistWords];
   {
@@ -214,11 +206,10 @@ __global__ __launch_bounds__(kNT) void col_single_kernel(const u32* counts, u32 
   }
 }
 
-template <typename K, int DB>
+template <typename K, int DB, int IT>
 __global__ __launch_bounds__(kNT) void rs_scatter_kernel(const K* in, K* out, u64 n, int shift,
                                                          const u32* offsets, u32 ntiles) {
-  constexpr int IT = RsItems<K>::value;
-  constexpr u64 kTile = rs_tile<K>();
+  constexpr u64 kTile = u64(kNT) * IT;
   constexpr u32 kWaveTile = kWave * IT;
   __shared__ u32 whist[kWaves * kBuckets];
   __shared__ u32 gbase[kBuckets];
@@ -322,18 +313,18 @@ __global__ __launch_bounds__(kNT) void rs_scatter_kernel(const K* in, K* out, u6
   }
 }
 
-template <typename K>
-u64 tiles_of(u64 n) {
-  return (n + rs_tile<K>() - 1) / rs_tile<K>();
+u64 tiles_of(u64 n, int items) {
+  const u64 t = u64(kNT) * u64(items);
+  return (n + t - 1) / t;
 }
 
-// One pass over bits [shift, shift + DB).
-template <typename K, int DB>
+// One pass over bits [shift, shift + DB) with tiles of IT keys per thread.
+template <typename K, int DB, int IT>
 hipError_t rs_pass(const K* src, K* dst, u64 n, int shift, u32* counts, u32* offsets, u32* csum,
                    u32* total, u64 nt, u64 nc, hipStream_t s, LaunchTimer* timer) {
   const u64 m = u64(kBuckets) * nt;
   if (timer) timer->begin(K_RADIX_HIST, s);
-  rs_hist_kernel<K, DB><<<dim3(u32(nt)), kNT, 0, s>>>(src, n, shift, counts, u32(nt));
+  rs_hist_kernel<K, DB, IT><<<dim3(u32(nt)), kNT, 0, s>>>(src, n, shift, counts, u32(nt));
   if (timer) timer->end(K_RADIX_HIST, s, n * sizeof(K) + m * sizeof(u32));
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -347,7 +338,8 @@ hipError_t rs_pass(const K* src, K* dst, u64 n, int shift, u32* counts, u32* off
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (timer) timer->begin(K_RADIX_SCATTER, s);
-  rs_scatter_kernel<K, DB><<<dim3(u32(nt)), kNT, 0, s>>>(src, dst, n, shift, offsets, u32(nt));
+  rs_scatter_kernel<K, DB, IT><<<dim3(u32(nt)), kNT, 0, s>>>(src, dst, n, shift, offsets,
+                                                             u32(nt));
   if (timer) timer->end(K_RADIX_SCATTER, s, 2 * n * sizeof(K) + m * sizeof(u32));
   return hipGetLastError();
 }
@@ -364,12 +356,13 @@ u64 sort_workspace_bytes(u64 n) {
 
 template <typename K>
 hipError_t radix_sort_bits(K* keys, K* alt, u64 n, int lo_bit, int hi_bit, void* ws,
-                           hipStream_t s, K** sorted, LaunchTimer* timer) {
+                           hipStream_t s, K** sorted, LaunchTimer* timer, int tile_items) {
   *sorted = keys;
   if (hi_bit > int(8 * sizeof(K))) hi_bit = int(8 * sizeof(K));
   if (n <= 1 || lo_bit < 0 || hi_bit <= lo_bit) return hipSuccess;
   if (n >= (u64(1) << 32)) return hipErrorInvalidValue;
-  const u64 nt = tiles_of<K>(n);
+  if (tile_items != 16 && tile_items != 32) return hipErrorInvalidValue;
+  const u64 nt = tiles_of(n, tile_items);
   const u64 nc = (nt + kChunk - 1) / kChunk;
   const u64 m = u64(kBuckets) * nt;
   char* p = static_cast<char*>(ws);
@@ -387,7 +380,11 @@ hipError_t radix_sort_bits(K* keys, K* alt, u64 n, int lo_bit, int hi_bit, void*
     hipError_t e = hipSuccess;
 #define HL_RS_PASS(DB)                                                                        \
   case DB:                                                                                    \
-    e = rs_pass<K, DB>(src, dst, n, shift, counts, offsets, csum, total, nt, nc, s, timer);   \
+    e = tile_items == 32                                                                      \
+            ? rs_pass<K, DB, 32>(src, dst, n, shift, counts, offsets, csum, total, nt, nc, s, \
+                                 timer)                                                       \
+            : rs_pass<K, DB, 16>(src, dst, n, shift, counts, offsets, csum, total, nt, nc, s, \
+                                 timer);                                                      \
     break;
     switch (dbits) {
       HL_RS_PASS(1)
@@ -413,17 +410,17 @@ hipError_t radix_sort_bits(K* keys, K* alt, u64 n, int lo_bit, int hi_bit, void*
 
 template <typename K>
 hipError_t radix_sort(K* keys, K* alt, u64 n, int bits, void* ws, hipStream_t s, K** sorted,
-                      LaunchTimer* timer) {
-  return radix_sort_bits<K>(keys, alt, n, 0, bits, ws, s, sorted, timer);
+                      LaunchTimer* timer, int tile_items) {
+  return radix_sort_bits<K>(keys, alt, n, 0, bits, ws, s, sorted, timer, tile_items);
 }
 
 template hipError_t radix_sort<u32>(u32*, u32*, u64, int, void*, hipStream_t, u32**,
-                                    LaunchTimer*);
+                                    LaunchTimer*, int);
 template hipError_t radix_sort<u64>(u64*, u64*, u64, int, void*, hipStream_t, u64**,
-                                    LaunchTimer*);
+                                    LaunchTimer*, int);
 template hipError_t radix_sort_bits<u32>(u32*, u32*, u64, int, int, void*, hipStream_t, u32**,
-                                         LaunchTimer*);
+                                         LaunchTimer*, int);
 template hipError_t radix_sort_bits<u64>(u64*, u64*, u64, int, int, void*, hipStream_t, u64**,
-                                         LaunchTimer*);
+                                         LaunchTimer*, int);
 
 }  // namespace hl

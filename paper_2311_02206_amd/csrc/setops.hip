@@ -23,13 +23,19 @@ namespace {
 // ------------------------------------------------------------ unique_diff
 
 constexpr int kUdNT = 256;
-constexpr int kUdItems = 16;
-constexpr u64 kUdTile = u64(kUdNT) * kUdItems;
+// Candidates per thread of a tile: 16 (4,096-candidate tiles) by default, or
+// 8 (2,048), a run-time choice that the autotuner measures.
+constexpr u64 kUdMinTile = u64(kUdNT) * 8;
 constexpr u64 kUdStage = 2048;  // keys of full staged in LDS per chunk
 constexpr int kUdLock = 8;      // keys searched in lockstep by one thread
 constexpr u64 kUdStreamMax = 16 * kUdStage;  // longest slice streamed through LDS
 
-__device__ __forceinline__ u32 pad(u32 i) { return i + i / kUdItems; }
+// One padding slot per ITEMS keys: thread t reads keys t*ITEMS .. t*ITEMS +
+// ITEMS - 1, which without padding would all fall in the same LDS banks.
+template <int ITEMS>
+__device__ __forceinline__ u32 pad(u32 i) {
+  return i + i / ITEMS;
+}
 
 template <typename K>
 __device__ __forceinline__ u64 lower_bound(const K* a, u64 lo, u64 hi, K x) {
@@ -51,20 +57,21 @@ __device__ __forceinline__ u64 upper_bound(const K* a, u64 lo, u64 hi, K x) {
   return lo;
 }
 
-// part[t] = lower_bound(full, first candidate of tile t); part[ntiles] = nf.
-// One thread per tile, so the searches' latency overlaps across tiles.
+// part[2t] = lower_bound(full, first candidate of tile t) and part[2t + 1] =
+// lower_bound(full, last candidate of tile t): every candidate of the tile
+// has its lower bound between them, so the tile searches only that slice
+// (keys of full between two tiles' candidates are never read).  One thread
+// per bound, so the searches' latency overlaps across tiles.
 template <typename K, bool kModel>
 __global__ __launch_bounds__(kUdNT) void ud_partition_kernel(const K* cand, u64 n, const K* full,
-                                                             u64 nf, u64 ntiles, u64* part,
-                                                             LearnedView<K> lv) {
-  const u64 t = u64(blockIdx.x) * kUdNT + threadIdx.x;
-  if (t > ntiles) return;
-  if (t == ntiles) {
-    part[t] = nf;
-    return;
-  }
-  const K x = cand[t * kUdTile];
-  part[t] = kModel ? u64(lm_lower_bound(lv, x)) : lower_bound(full, u64(0), nf, x);
+                                                             u64 nf, u64 ntiles, u64 tile_keys,
+                                                             u64* part, LearnedView<K> lv) {
+  const u64 u = u64(blockIdx.x) * kUdNT + threadIdx.x;
+  if (u >= 2 * ntiles) return;
+  const u64 t = u >> 1;
+  const u64 end = (t + 1) * tile_keys < n ? (t + 1) * tile_keys : n;
+  const K x = (u & 1) ? cand[end - 1] : cand[t * tile_keys];
+  part[u] = kModel ? u64(lm_lower_bound(lv, x)) : lower_bound(full, u64(0), nf, x);
 }
 
 // One tile of sorted candidates: each thread takes kUdItems consecutive
@@ -80,28 +87,28 @@ __global__ __launch_bounds__(kUdNT) void ud_partition_kernel(const K* cand, u64 
 // by definition: its candidates read, its survivors written, and for the
 // membership tests the cheaper of reading the slice of full it spans and
 // one 64-byte line per distinct key searched (the same for the tail).
-template <typename K, bool kModel>
+template <typename K, bool kModel, int kUdItems>
 __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, const K* full,
                                                           u64 nf, K* tmp, u32* tile_counts,
                                                           u32* tile_uniq, LearnedView<K> lv,
                                                           const u64* part, const K* tail,
                                                           u64 ntail, u64* alg_bytes) {
+  constexpr u64 kUdTile = u64(kUdNT) * kUdItems;
   __shared__ u32 wsum[kUdNT / kWave];
   __shared__ u32 wsum2[kUdNT / kWave];
-  // one padding slot per kUdItems keys: thread t reads keys t*16 .. t*16+15,
-  // which without padding would all fall in the same LDS banks
   __shared__ K s_c[kUdTile + kUdTile / kUdItems];
   __shared__ K staged[kUdStage];
   const u32 tile = blockIdx.x;
   const u64 base = u64(tile) * kUdTile;
   const u32 cnt = u32((n - base) < kUdTile ? (n - base) : kUdTile);
-  // every candidate of the tile lies between the tile's first key and the
-  // next tile's first key, so its lower bound in full is in this slice.
-  // Each thread reads the bounds itself (one address for the whole block),
-  // so the first chunk of the slice can be requested together with the
+  // every candidate of the tile lies between the tile's first and last
+  // keys, so its lower bound in full is in this slice (one past the last
+  // key's lower bound, so that key's equal in full is in it too).  Each
+  // thread reads the bounds itself (one address for the whole block), so
+  // the first chunk of the slice can be requested together with the
   // candidates instead of after a barrier.
-  const u64 lo = part[tile];
-  const u64 hi = (part[tile + 1] + 1) < nf ? (part[tile + 1] + 1) : nf;
+  const u64 lo = part[2 * u64(tile)];
+  const u64 hi = (part[2 * u64(tile) + 1] + 1) < nf ? (part[2 * u64(tile) + 1] + 1) : nf;
   const K before = base > 0 ? cand[base - 1] : K(0);
   const u64 m = hi - lo;
   constexpr int kPer = int(kUdStage / kUdNT);
@@ -113,7 +120,7 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
       next[r] = i < hi ? full[i] : K(0);
     }
   }
-  for (u32 k = threadIdx.x; k < cnt; k += kUdNT) s_c[pad(k)] = cand[base + k];
+  for (u32 k = threadIdx.x; k < cnt; k += kUdNT) s_c[pad<kUdItems>(k)] = cand[base + k];
   __syncthreads();
   const u32 b = threadIdx.x * kUdItems;
   u32 keep_bits = 0, nkeep = 0, uniq = 0;
@@ -121,12 +128,12 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
     // first-of-run flags, then resolution chunk by chunk
     u32 first_bits = 0;
     if (b < cnt) {
-      K prevk = b > 0 ? s_c[pad(b - 1)] : before;
+      K prevk = b > 0 ? s_c[pad<kUdItems>(b - 1)] : before;
 #pragma unroll
       for (int q = 0; q < kUdItems; ++q) {
         const u32 idx = b + q;
         if (idx < cnt) {
-          const K c = s_c[pad(idx)];
+          const K c = s_c[pad<kUdItems>(idx)];
           if ((base + idx == 0) || prevk != c) first_bits |= 1u << q;
           prevk = c;
         }
@@ -154,12 +161,12 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
       if (pending) {
         const K clast = staged[cm - 1];
         const int q0 = __ffs(pending) - 1;
-        if (s_c[pad(b + q0)] <= clast) {
+        if (s_c[pad<kUdItems>(b + q0)] <= clast) {
           // search the first pending key, walk forward for the others
-          u32 p = u32(lower_bound(staged, u64(0), u64(cm), s_c[pad(b + q0)]));
+          u32 p = u32(lower_bound(staged, u64(0), u64(cm), s_c[pad<kUdItems>(b + q0)]));
           for (int q = q0; q < kUdItems; ++q) {
             if (!(pending & (1u << q))) continue;
-            const K c = s_c[pad(b + q)];
+            const K c = s_c[pad<kUdItems>(b + q)];
             if (c > clast) break;
             while (staged[p] < c) ++p;  // stops at or before cm - 1
             pending &= ~(1u << q);
@@ -176,23 +183,34 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
     nkeep += u32(__popc(pending));
   } else if (b < cnt) {
     // The slice is too long to stream, so candidates may be far apart in
-    // full.  Groups of kUdLock keys of the thread are searched together, one
-    // halving step at a time for all of them, so their global loads are in
-    // flight at once instead of forming one chain of dependent reads.
-    // Every key of a group has a search range of the same length L (the
-    // tile's slice, or the widest of the model's windows), so the steps are
-    // the same for all.
-    K prevk = b > 0 ? s_c[pad(b - 1)] : before;
+    // full.  Only the distinct keys of a thread are searched, in groups of
+    // kUdLock whose halving steps run together, so a wave keeps many loads
+    // in flight instead of forming one chain of dependent reads.  Every key
+    // of a group has a search range of the same length L (the tile's slice,
+    // or the widest of the model's windows intersected with it), so the
+    // steps are the same for all.
+    K prevk = b > 0 ? s_c[pad<kUdItems>(b - 1)] : before;
+    int qd[kUdItems];
+    int nd = 0;
+#pragma unroll
+    for (int q = 0; q < kUdItems; ++q) {
+      const u32 idx = b + q;
+      if (idx < cnt) {
+        const K c = s_c[pad<kUdItems>(idx)];
+        if ((base + idx == 0) || prevk != c) qd[nd++] = q;
+        prevk = c;
+      }
+    }
+    uniq = u32(nd);
 #pragma unroll 1
-    for (int g = 0; g < kUdItems; g += kUdLock) {
+    for (int g = 0; g < nd; g += kUdLock) {
       K c[kUdLock];
       const K* at[kUdLock];
       u64 L = m;
 #pragma unroll
-      for (int q = 0; q < kUdLock; ++q) {
-        const u32 idx = (b + g + q < cnt) ? b + g + q : cnt - 1;
-        c[q] = s_c[pad(idx)];
-        at[q] = full + lo;
+      for (int r = 0; r < kUdLock; ++r) {
+        c[r] = s_c[pad<kUdItems>(b + qd[(g + r < nd) ? g + r : nd - 1])];
+        at[r] = full + lo;
       }
       if (kModel) {
         // the model's window and the tile's slice both hold each key's
@@ -200,38 +218,32 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
         u64 wa[kUdLock];
         L = 0;
 #pragma unroll
-        for (int q = 0; q < kUdLock; ++q) {
+        for (int r = 0; r < kUdLock; ++r) {
           u64 wb;
-          lm_window(lv, c[q], wa[q], wb);
-          wa[q] = wa[q] > lo ? wa[q] : lo;
+          lm_window(lv, c[r], wa[r], wb);
+          wa[r] = wa[r] > lo ? wa[r] : lo;
           wb = wb < hi ? wb : hi;
-          if (wb < wa[q]) wb = wa[q];
-          L = (wb - wa[q]) > L ? (wb - wa[q]) : L;
+          if (wb < wa[r]) wb = wa[r];
+          L = (wb - wa[r]) > L ? (wb - wa[r]) : L;
         }
         // widening a window keeps the answer inside it; stay within full
 #pragma unroll
-        for (int q = 0; q < kUdLock; ++q) at[q] = full + (wa[q] < nf - L ? wa[q] : nf - L);
+        for (int r = 0; r < kUdLock; ++r) at[r] = full + (wa[r] < nf - L ? wa[r] : nf - L);
       }
       u64 len = L;
       while (len > 1) {
         const u64 half = len >> 1;
 #pragma unroll
-        for (int q = 0; q < kUdLock; ++q) at[q] = (at[q][half] < c[q]) ? at[q] + half : at[q];
+        for (int r = 0; r < kUdLock; ++r) at[r] = (at[r][half] < c[r]) ? at[r] + half : at[r];
         len -= half;
       }
 #pragma unroll
-      for (int q = 0; q < kUdLock; ++q) {
-        const u32 idx = b + g + q;
-        if (idx < cnt) {
-          const bool first = (base + idx == 0) || prevk != c[q];
-          prevk = c[q];
-          if (first) {
-            ++uniq;
-            const u64 pos = u64(at[q] - full) + ((L > 0 && *at[q] < c[q]) ? 1 : 0);
-            if (!(pos < nf && full[pos] == c[q])) {
-              keep_bits |= 1u << (g + q);
-              ++nkeep;
-            }
+      for (int r = 0; r < kUdLock; ++r) {
+        if (g + r < nd) {
+          const u64 pos = u64(at[r] - full) + ((L > 0 && *at[r] < c[r]) ? 1 : 0);
+          if (!(pos < nf && full[pos] == c[r])) {
+            keep_bits |= 1u << qd[g + r];
+            ++nkeep;
           }
         }
       }
@@ -253,7 +265,7 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
           const int q = __ffs(rem) - 1;
           rem &= rem - 1;
           qi[j] = q;
-          c[j] = s_c[pad(b + q)];
+          c[j] = s_c[pad<kUdItems>(b + q)];
           k = j + 1;
         } else {
           qi[j] = -1;
@@ -289,13 +301,13 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
   // s_c happened before the scan's barriers), then out coalesced
   K mine[kUdItems];
 #pragma unroll
-  for (int q = 0; q < kUdItems; ++q) mine[q] = (b + q < cnt) ? s_c[pad(b + q)] : K(0);
+  for (int q = 0; q < kUdItems; ++q) mine[q] = (b + q < cnt) ? s_c[pad<kUdItems>(b + q)] : K(0);
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < kUdItems; ++q)
-    if (keep_bits & (1u << q)) s_c[pad(pos++)] = mine[q];
+    if (keep_bits & (1u << q)) s_c[pad<kUdItems>(pos++)] = mine[q];
   __syncthreads();
-  for (u32 k = threadIdx.x; k < total; k += kUdNT) tmp[base + k] = s_c[pad(k)];
+  for (u32 k = threadIdx.x; k < total; k += kUdNT) tmp[base + k] = s_c[pad<kUdItems>(k)];
   uniq = block_sum<kUdNT>(uniq, wsum2);
   u32 searched = 0;
   if (alg_bytes) searched = block_sum<kUdNT>(tail_searched, wsum);
@@ -314,10 +326,11 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
 
 template <typename K>
 __global__ __launch_bounds__(kUdNT) void ud_gather_kernel(const K* tmp, const u32* tile_counts,
-                                                          const u64* tile_off, K* out) {
+                                                          const u64* tile_off, u64 tile_keys,
+                                                          K* out) {
   const u32 tile = blockIdx.x;
   const u32 c = tile_counts[tile];
-  const u64 src = u64(tile) * kUdTile;
+  const u64 src = u64(tile) * tile_keys;
   const u64 dst = tile_off[tile];
   for (u32 k = threadIdx.x; k < c; k += kUdNT) out[dst + k] = tmp[src + k];
 }
@@ -401,26 +414,28 @@ __global__ __launch_bounds__(kMgNT) void merge_kernel(const K* a, u64 na, const 
   for (u32 k = threadIdx.x; k < total; k += kMgNT) out[d0 + k] = s[k];
 }
 
-u64 ud_tiles(u64 n) { return (n + kUdTile - 1) / kUdTile; }
+u64 ud_tiles(u64 n, u64 tile) { return (n + tile - 1) / tile; }
 u64 mg_tiles(u64 n) { return (n + kMgTile - 1) / kMgTile; }
 
 }  // namespace
 
 u64 unique_diff_workspace_bytes(u64 n) {
-  u64 nt = ud_tiles(n);
-  return 2 * align_up(nt * sizeof(u32), 256) + 2 * align_up((nt + 1) * sizeof(u64), 256) +
-         scan_workspace_bytes(nt);
+  u64 nt = ud_tiles(n, kUdMinTile);  // the smallest tile: the most tiles
+  return 2 * align_up(nt * sizeof(u32), 256) + align_up((nt + 1) * sizeof(u64), 256) +
+         align_up((2 * nt + 1) * sizeof(u64), 256) + scan_workspace_bytes(nt);
 }
 
 template <typename K>
 hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
                        u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer,
-                       const LearnedView<K>* model, const K* tail, u64 ntail) {
+                       const LearnedView<K>* model, const K* tail, u64 ntail, int items) {
   zero_u64x2_kernel<<<1, 1, 0, s>>>(d_counts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n == 0) return e;
   if (n >= (u64(1) << 32)) return hipErrorInvalidValue;
-  const u64 nt = ud_tiles(n);
+  if (items != 8 && items != 16) return hipErrorInvalidValue;
+  const u64 tile_keys = u64(kUdNT) * u64(items);
+  const u64 nt = ud_tiles(n, tile_keys);
   char* p = static_cast<char*>(ws);
   u32* tile_counts = reinterpret_cast<u32*>(p);
   p += align_up(nt * sizeof(u32), 256);
@@ -428,26 +443,36 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   p += align_up(nt * sizeof(u32), 256);
   u64* tile_off = reinterpret_cast<u64*>(p);
   p += align_up((nt + 1) * sizeof(u64), 256);
-  u64* part = reinterpret_cast<u64*>(p);
-  p += align_up((nt + 1) * sizeof(u64), 256);
+  u64* part = reinterpret_cast<u64*>(p);  // 2 nt bounds, later nt + 1 offsets
+  p += align_up((2 * nt + 1) * sizeof(u64), 256);
   if (model && (model->keys != full || model->n != nf)) return hipErrorInvalidValue;
-  const u32 pb = u32((nt + 1 + kUdNT - 1) / kUdNT);
+  // Candidates at least one per 8 keys of full leave tiles' slices short
+  // enough to stream, where the model is not used; the kernel without it
+  // needs fewer registers and runs more waves per SIMD.
+  if (model && nf < 8 * n) model = nullptr;
+  const u32 pb = u32((2 * nt + kUdNT - 1) / kUdNT);
   u64* alg = timer ? timer->device_counter(s) : nullptr;
+  const LearnedView<K> lv = model ? *model : LearnedView<K>{};
+  const dim3 grid = dim3(u32(nt));
   if (timer) timer->begin(K_UNIQUE_DIFF, s);
-  if (model) {
-    ud_partition_kernel<K, true><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, part,
-                                                            *model);
-    ud_select_kernel<K, true><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
-                                                              tile_counts, tile_uniq, *model,
-                                                              part, tail, ntail, alg);
-  } else {
-    ud_partition_kernel<K, false><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, part,
-                                                             LearnedView<K>{});
-    ud_select_kernel<K, false><<<dim3(u32(nt)), kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
-                                                               tile_counts, tile_uniq,
-                                                               LearnedView<K>{}, part, tail,
-                                                               ntail, alg);
-  }
+  if (model)
+    ud_partition_kernel<K, true><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, tile_keys,
+                                                            part, lv);
+  else
+    ud_partition_kernel<K, false><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, tile_keys,
+                                                             part, lv);
+  if (model && items == 16)
+    ud_select_kernel<K, true, 16><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
+                                                          tile_uniq, lv, part, tail, ntail, alg);
+  else if (model)
+    ud_select_kernel<K, true, 8><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
+                                                         tile_uniq, lv, part, tail, ntail, alg);
+  else if (items == 16)
+    ud_select_kernel<K, false, 16><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
+                                                           tile_uniq, lv, part, tail, ntail, alg);
+  else
+    ud_select_kernel<K, false, 8><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
+                                                          tile_uniq, lv, part, tail, ntail, alg);
   // the tiles count their own bytes (above); without a device counter only
   // the candidate reads are known here
   if (timer) timer->end(K_UNIQUE_DIFF, s, alg ? 0 : n * sizeof(K), alg);
@@ -459,7 +484,7 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   // part, which the select no longer needs)
   e = scan_u32_u64(tile_uniq, nt, part, d_counts + 1, p, s);
   if (e != hipSuccess) return e;
-  ud_gather_kernel<K><<<dim3(u32(nt)), kUdNT, 0, s>>>(tmp, tile_counts, tile_off, out);
+  ud_gather_kernel<K><<<grid, kUdNT, 0, s>>>(tmp, tile_counts, tile_off, tile_keys, out);
   return hipGetLastError();
 }
 
@@ -488,10 +513,10 @@ hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipSt
 
 template hipError_t unique_diff<u32>(const u32*, u64, const u32*, u64, u32*, u32*, u64*, void*,
                                      hipStream_t, LaunchTimer*, const LearnedView<u32>*,
-                                     const u32*, u64);
+                                     const u32*, u64, int);
 template hipError_t unique_diff<u64>(const u64*, u64, const u64*, u64, u64*, u64*, u64*, void*,
                                      hipStream_t, LaunchTimer*, const LearnedView<u64>*,
-                                     const u64*, u64);
+                                     const u64*, u64, int);
 template hipError_t merge<u32>(const u32*, u64, const u32*, u64, u32*, void*, hipStream_t,
                                LaunchTimer*);
 template hipError_t merge<u64>(const u64*, u64, const u64*, u64, u64*, void*, hipStream_t,

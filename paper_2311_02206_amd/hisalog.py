@@ -33,6 +33,7 @@ HL_FLAG_JOIN_DEDUP = 0x8
 HL_FLAG_FUSED = 0x10
 HL_FLAG_HIP_GRAPH = 0x20
 HL_FLAG_NESTED_JOINS = 0x40
+HL_FLAG_NO_LEVELS = 0x80
 KERNELS = ("radix_hist", "radix_scatter", "unique_diff", "merge", "join_probe", "join_expand",
            "hisa_build", "learned_fit")
 PHASES = ("index_edb", "join", "sort", "diff", "merge", "index", "fused")
@@ -61,7 +62,8 @@ class Options(ctypes.Structure):
         ("stream", ctypes.c_void_p), ("ebm_k", ctypes.c_float),
         ("hash_load_factor", ctypes.c_float), ("sort_chunk_log2", ctypes.c_uint32),
         ("fused_capacity", ctypes.c_uint32), ("expand_tile", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32 * 5),
+        ("sort_tile", ctypes.c_uint32), ("diff_tile", ctypes.c_uint32),
+        ("reserved0", ctypes.c_uint32), ("tail_min_bytes", ctypes.c_uint64),
     ]
 
 
@@ -88,7 +90,8 @@ class Tuning(ctypes.Structure):
         ("hash_load_factor", ctypes.c_float), ("ebm_k", ctypes.c_float),
         ("flags", ctypes.c_uint32), ("trials", ctypes.c_uint32),
         ("best_seconds", ctypes.c_double), ("first_seconds", ctypes.c_double),
-        ("expand_tile", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+        ("expand_tile", ctypes.c_uint32), ("sort_tile", ctypes.c_uint32),
+        ("diff_tile", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
     ]
 
 
@@ -186,7 +189,9 @@ class Engine:
                  ebm_k: float = 8.0, load_factor: float = 0.5, budget_bytes: int = 0,
                  kernel_timing: bool = False, learned: bool = False, sort_chunk_log2: int = 0,
                  join_dedup: bool = False, fused: bool = False, hip_graph: bool = False,
-                 fused_capacity: int = 0, nested_joins: bool = False, expand_tile: int = 0):
+                 fused_capacity: int = 0, nested_joins: bool = False, expand_tile: int = 0,
+                 sort_tile: int = 0, diff_tile: int = 0, levels: bool = True,
+                 tail_min_bytes: int = 0):
         L = lib()
         opt = Options()
         L.hl_options_init(ctypes.byref(opt))
@@ -197,13 +202,17 @@ class Engine:
                      (HL_FLAG_JOIN_DEDUP if join_dedup else 0) |
                      (HL_FLAG_FUSED if fused else 0) |
                      (HL_FLAG_HIP_GRAPH if hip_graph else 0) |
-                     (HL_FLAG_NESTED_JOINS if nested_joins else 0))
+                     (HL_FLAG_NESTED_JOINS if nested_joins else 0) |
+                     (0 if levels else HL_FLAG_NO_LEVELS))
         opt.ebm_k = ebm_k
         opt.hash_load_factor = load_factor
         opt.hbm_budget_bytes = budget_bytes
         opt.sort_chunk_log2 = sort_chunk_log2
         opt.fused_capacity = fused_capacity
         opt.expand_tile = expand_tile
+        opt.sort_tile = sort_tile
+        opt.diff_tile = diff_tile
+        opt.tail_min_bytes = tail_min_bytes
         self._arena = arena  # keep the caller's tensor alive
         if arena is not None:
             opt.arena = _ptr(arena)
@@ -323,7 +332,7 @@ class Engine:
                 "nested_joins": bool(t.flags & HL_FLAG_NESTED_JOINS),
                 "fused": bool(t.flags & (HL_FLAG_FUSED | HL_FLAG_HIP_GRAPH)),
                 "hip_graph": bool(t.flags & HL_FLAG_HIP_GRAPH), "expand_tile": t.expand_tile,
-                "trials": t.trials,
+                "sort_tile": t.sort_tile, "diff_tile": t.diff_tile, "trials": t.trials,
                 "best_seconds": t.best_seconds, "first_seconds": t.first_seconds}
 
     def count(self, name: str) -> int:

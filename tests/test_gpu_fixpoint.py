@@ -262,6 +262,7 @@ def test_autotune_keeps_results(case):
         say(f"  chose {t}")
         assert t["trials"] >= 4 and t["best_seconds"] <= t["first_seconds"]
         assert t["hash_load_factor"] in (0.5, 0.8) and t["ebm_k"] in (1.5, 8.0)
+        assert t["sort_tile"] in (4096, 8192) and t["diff_tile"] in (2048, 4096)
         for _ in range(2):
             for n in idb:
                 assert np.array_equal(e.fetch(n), want.relations[n]), n
@@ -454,6 +455,23 @@ def test_expand_tiles_match_oracle(tile):
                expand_tile=tile, join_dedup=True)
 
 
+@pytest.mark.parametrize("sort_tile,diff_tile", [(4096, 2048), (4096, 4096), (8192, 2048)])
+def test_sort_and_difference_tiles_match_oracle(sort_tile, diff_tile):
+    """Radix sort tiles of 4,096 keys and set difference tiles of 2,048
+    candidates (8,192 and 4,096 are the defaults everywhere else), with
+    32- and 64-bit keys, chunked sorts and the learned index's windows."""
+    say(f"sort tile {sort_tile}, difference tile {diff_tile}")
+    kw = dict(sort_tile=sort_tile, diff_tile=diff_tile)
+    wl = workloads.scaled_rmat(12, 12_000, seed=0xC2A)
+    check_same(PROG["reach"], wl["edb"], {"Reach": 2}, **kw)
+    check_same(PROG["reach"], wl["edb"], {"Reach": 2}, learned=True, sort_chunk_log2=14, **kw)
+    tr = workloads.scaled_tree(2000, seed=31)
+    check_same(PROG["sg"], tr["edb"], {"SG": 2}, **kw)
+    E = workloads.reach_er_1000()["edb"]["Edge"].astype(np.uint64)
+    E = ((E * np.uint64(4294967291) + np.uint64(12345)) % np.uint64(1 << 32)).astype(np.uint32)
+    check_same(PROG["reach"], {"Edge": E}, {"Reach": 2}, **kw)
+
+
 UNARY = ("R(x) :- S(x).\nR(y) :- R(x), E(x, y).\nN(x) :- E(x, _).\nN(y) :- E(_, y).\n"
          "B(x, y) :- R(x), E(y, x), x != y.\nL(x) :- E(x, x).\nC(x, x) :- R(x), L(x).\n")
 UNARY_IDB = {"R": 1, "N": 1, "B": 2, "L": 1, "C": 2}
@@ -522,3 +540,31 @@ def test_rule_stats_closed_forms():
             assert rs[0] == (int((outdeg ** 2).sum()), 0)
             assert rs[1] == (int((outdeg[R[:, 0]] * outdeg[R[:, 1]]).sum()),
                              int(outdeg[R[:, 0]].sum()))
+
+
+@pytest.mark.parametrize("learned", [False, True])
+@pytest.mark.parametrize("case", ["nonlinear", "cspa", "reach", "sg"])
+def test_tail_runs_and_levels_match_oracle(case, learned):
+    """Tail runs forced at small sizes (tail_min_bytes 1): relations probed as
+    join inners kept as two levels (the nonlinear closure probes both
+    columns of its own relation; CSPA's three mutually recursive relations),
+    relations no join probes with a plain tail run (Reach, SG), with hash and
+    learned probes, chunked new tuples (absorbed chunk by chunk against full
+    and the tail), and the same with levels off."""
+    say(f"tails and levels: {case}, learned={learned}")
+    if case == "nonlinear":
+        prog = "T(x, y) :- E(x, y).\nT(x, y) :- T(x, z), T(z, y)."
+        edb, idb = {"E": workloads.scaled_rmat(10, 2500, seed=3)["edb"]["Edge"]}, {"T": 2}
+    elif case == "cspa":
+        prog, edb = PROG["cspa_shaped"], workloads.cspa(10)["edb"]
+        idb = {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2}
+    elif case == "reach":
+        prog, edb, idb = PROG["reach"], workloads.scaled_rmat(11, 6000, seed=4)["edb"], {"Reach": 2}
+    else:
+        prog, edb, idb = PROG["sg"], workloads.scaled_tree(3000, seed=3)["edb"], {"SG": 2}
+    want = oracle.evaluate(prog, edb, idb, max_iterations=100_000)
+    for kw in ({}, {"sort_chunk_log2": 12}, {"levels": False}):
+        rels, deltas, st = gpu_eval(prog, edb, idb, learned=learned, tail_min_bytes=1, **kw)
+        for name in idb:
+            assert np.array_equal(rels[name], want.relations[name]), (name, kw)
+            assert deltas[name] == want.deltas[name], (name, kw)

@@ -168,3 +168,21 @@ def test_learned_query(eng, kb, n, dist):
     pos = eng.learned_query(to_dev(keys, kb), key_bits, to_dev(q, kb))
     want = np.searchsorted(keys, q, side="left")
     assert np.array_equal(pos.cpu().numpy().astype(np.int64), want)
+
+
+@pytest.mark.parametrize("kb", [4, 8])
+@pytest.mark.parametrize("reps,nf,span", [(4, 2_000_000, 4_000_000), (3, 3_000_000, 1 << 31),
+                                           (1, 5_000_000, 6_000_000)])
+def test_unique_diff_repeats_far_apart(eng, kb, reps, nf, span):
+    """Candidates far apart in a large full (tiles whose slice of full is
+    searched through the sampled index, not streamed), each repeated: only
+    the first of a run is tested and kept; the result is the set definition's."""
+    rng = np.random.default_rng(reps * 11 + nf)
+    f = np.unique(rng.integers(0, span, size=nf).astype(np.uint64)).astype(U[kb])
+    d = np.unique(rng.integers(0, span, size=30_000).astype(np.uint64))
+    # half of the distinct candidates are members of full
+    d = np.unique(np.concatenate([d[: len(d) // 2], rng.choice(f.astype(np.uint64), 15_000)]))
+    c = np.sort(np.repeat(d.astype(U[kb]), reps))
+    out, nu = eng.unique_diff(to_dev(c, kb), to_dev(f, kb))
+    assert nu == len(d)
+    assert np.array_equal(to_host(out, kb), np.setdiff1d(d.astype(U[kb]), f))
