@@ -266,6 +266,7 @@ def main():
         steps = max(1, min(args.steps, 3))
         verify = not args.no_verify
         only = {"cspa": lambda: cspa_variant(stream, steps, verify=verify),
+                "cspa_rules": lambda: cspa_rules(stream),
                 "reach_er_2p22": lambda: er_variant(stream, steps, verify=verify),
                 "nonlinear_er_2p22": lambda: nonlinear_variant(stream, steps, verify=verify),
                 "batched": lambda: batched_variant(stream, max(1, args.batched_instances),
@@ -747,6 +748,39 @@ def cspa_variant(stream, steps, verify=True):
                             {"ValueFlow": 2, "ValueAlias": 2, "MemoryAlias": 2}, steps, verify,
                             {"assign_pairs": len(wl["edb"]["Assign"]),
                              "dereference_pairs": len(wl["edb"]["Dereference"])})
+
+
+def cspa_rules(stream, scales=(12, 13, 14, 15)):
+    """Per-rule join outputs of the CSPA-shaped program (literal reading) as
+    the id space doubles: the outputs of each rule's last join and of its
+    earlier ones, summed over the run, with the final IDB sizes.  Shows
+    which rules drive the growth of the candidates."""
+    import workloads
+    from paper_2311_02206_amd import Engine
+    prog = open(os.path.join(ROOT, "workloads", "programs", "cspa_shaped.dl")).read()
+    rules = [ln.strip() for ln in prog.splitlines()
+             if ln.strip() and not ln.strip().startswith("//")]
+    out = {"rules": rules, "scales": {}}
+    for lg in scales:
+        log(f"cspa rules: 2^{lg} ids")
+        wl = workloads.cspa(lg)
+        with Engine(device=0, stream=stream) as e:
+            for name in ("Assign", "Dereference"):
+                e.declare(name, 2, True)
+            for name in ("ValueFlow", "ValueAlias", "MemoryAlias"):
+                e.declare(name, 2, False)
+            for name, rows in wl["edb"].items():
+                e.load(name, rows)
+            e.program(prog)
+            st = e.run()
+            per = e.rule_stats()
+            out["scales"][f"2^{lg}"] = {
+                "ms": st.seconds * 1e3, "iterations": st.iterations,
+                "idb_tuples": st.idb_tuples, "join_outputs": st.join_outputs,
+                "per_rule_last_join": [a for a, _ in per],
+                "per_rule_earlier_joins": [b for _, b in per],
+                "sizes": {n: e.count(n) for n in ("ValueFlow", "ValueAlias", "MemoryAlias")}}
+    return out
 
 
 def er_variant(stream, steps, verify=True):

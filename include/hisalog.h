@@ -175,7 +175,11 @@ typedef struct hl_options {
   uint32_t diff_tile;        /* sorted candidates per set difference tile:
                                 2048 or 4096 (0: 4096); hl_autotune
                                 measures both */
-  uint32_t reserved0;        /* must be zero */
+  uint32_t outer_slice_log2; /* a join's outer side is taken at most
+                                2^outer_slice_log2 tuples at a time
+                                (8..31; 0: 28), which bounds the join's
+                                scratch (16 bytes per outer tuple) and a
+                                multi-atom rule's intermediate result */
   uint64_t tail_min_bytes;   /* a relation's new tuples go to a sorted tail
                                 run beside its full relation (folded in when
                                 the tail passes an eighth of full) once full
@@ -282,10 +286,15 @@ int hl_index(hl_engine* e, const char* name, const uint32_t* cols, uint32_t ncol
  * Positive rules over declared relations; variables are identifiers, `_`
  * is a wildcard in body atoms; `x != y` filters two body variables; `//`
  * and `#` start comments.  Every head variable must occur in the body.
- * A rule body is evaluated as a chain of binary joins (Section 5.2) in
- * which each further atom shares exactly one variable with the pair
- * carried so far and at most two variables stay live; other shapes give
- * HL_E_UNSUPPORTED. */
+ * A rule body is evaluated as a chain of binary joins (Section 5.2).  A
+ * program whose relations are unary or binary and whose every rule is a
+ * chain in which each further atom shares one variable with the pair
+ * carried so far runs on keys of two columns; any other program (a relation
+ * of arity 3-4, a join on two columns, three or four variables live between
+ * joins, a cross product: an atom sharing no variable, whose relation is
+ * then scanned whole per carried tuple) runs as wide plans.  More than four
+ * variables live between joins, or more than four filters or equality
+ * tests at one join, give HL_E_UNSUPPORTED. */
 int hl_program(hl_engine* e, const char* text);
 
 /* Runs semi-naive evaluation to the fixpoint (Section 5.1), Jacobi order:

@@ -577,8 +577,16 @@ struct hl_engine {
     b.p = mem.alloc(sz, &b.bytes);
   }
   void reserve_grow(Buf& b, u64 need) { reserve(b, need, need + need / 2); }
-  // Like reserve_grow, but keeps the first `used` bytes of the buffer.
-  void reserve_keep(Buf& b, u64 used, u64 need) {
+  // Largest array of keys one sort takes (a chunk), in bytes.
+  u64 chunk_bytes() const { return (u64(1) << sort_chunk_log2) * key_bytes; }
+  // Like reserve_grow for a buffer that holds at most one chunk of keys in
+  // its steady use: its growth stops at the chunk's size.
+  void reserve_chunk(Buf& b, u64 need) {
+    reserve(b, need, std::max(need, std::min(need + need / 2, chunk_bytes())));
+  }
+  // Like reserve_grow, but keeps the first `used` bytes of the buffer; the
+  // growth stops at `limit` bytes (the candidate buffer: one chunk).
+  void reserve_keep(Buf& b, u64 used, u64 need, u64 limit = ~u64(0)) {
     if (need <= b.bytes && !(flags & HL_FLAG_NO_EBM)) {
       ++reuses;
       return;
@@ -588,7 +596,8 @@ struct hl_engine {
       return;
     }
     Buf nb;
-    const u64 sz = (flags & HL_FLAG_NO_EBM) ? need : need + need / 2;
+    const u64 sz =
+        (flags & HL_FLAG_NO_EBM) ? need : std::max(need, std::min(need + need / 2, limit));
     nb.p = mem.alloc(sz, &nb.bytes);
     if (used) HIPCK(hipMemcpyAsync(nb.p, b.p, used, hipMemcpyDeviceToDevice, stream));
     drop(b);
@@ -920,7 +929,9 @@ struct hl_engine {
           pick = int(q);
         }
       }
-      if (pick < 0) unsupported("a body atom shares no variable with the carried tuple");
+      // no atom shares a variable: a cross product with the first of them
+      // (an index with no join columns; every outer tuple takes all of it)
+      if (pick < 0) pick = 0;
       const Atom& b = r.body[remaining[pick]];
       remaining.erase(remaining.begin() + pick);
       // join columns first (every column whose variable is carried), then
@@ -965,7 +976,9 @@ struct hl_engine {
             if (need.count(v) && std::find(keep.begin(), keep.end(), v) == keep.end())
               keep.push_back(v);
         if (keep.size() > 4) unsupported("more than four variables stay live between joins");
-        if (keep.empty()) unsupported("no variable carried to the next join");
+        // the joins so far only need to be non-empty: carry one variable
+        // (any; the head takes none of them)
+        if (keep.empty()) keep.push_back(cur[0]);
         set_out(ws, keep, cur, inner);
         cur = keep;
         p.max_cols = std::max(p.max_cols, int(keep.size()));
@@ -1010,11 +1023,30 @@ struct hl_engine {
     int max_arity = 0;
     for (const Relation& R : rels) max_arity = std::max(max_arity, R.arity);
     wide = max_arity >= 3;
-    if (wide) {
-      if (!batch_base.empty()) fail(HL_E_UNSUPPORTED, "batches of relations of arity above 2");
-      build_wide_plans();
-      return;
+    if (!wide) {
+      // binary chains first; a rule outside their form (three live
+      // variables, a cross product) makes the whole program wide
+      std::vector<std::pair<bool, bool>> used;
+      for (const Relation& R : rels) used.push_back({R.idx[0].used, R.idx[1].used});
+      try {
+        build_binary_plans();
+        return;
+      } catch (const Error& x) {
+        if (x.code != HL_E_UNSUPPORTED || !batch_base.empty()) throw;
+        plans0.clear();
+        plansR.clear();
+        for (size_t k = 0; k < rels.size(); ++k) {
+          rels[k].idx[0].used = used[k].first;
+          rels[k].idx[1].used = used[k].second;
+        }
+        wide = true;
+      }
     }
+    if (!batch_base.empty()) fail(HL_E_UNSUPPORTED, "batches of wide programs");
+    build_wide_plans();
+  }
+
+  void build_binary_plans() {
     for (int k = 0; k < int(rules.size()); ++k) {
       const Rule& r = rules[k];
       bool edb_only = true;
@@ -1203,6 +1235,13 @@ struct hl_engine {
       if (ix.n >= (u64(1) << 32))
         fail(HL_E_UNSUPPORTED, "indexed relation " + R.name + " has 2^32 or more tuples");
     }
+    // an index with no join columns (a cross product's inner) is scanned
+    // whole: neither a table nor a model
+    todo.erase(std::remove_if(todo.begin(), todo.end(),
+                              [&](const std::pair<int, int>& rk) {
+                                return rels[rk.first].widx[rk.second].nj == 0;
+                              }),
+               todo.end());
     if (learned()) {
       for (auto& rk : todo) {
         Relation& R = rels[rk.first];
@@ -1308,7 +1347,7 @@ struct hl_engine {
       sync();
       R.n_full = h_small[0];
       R.idx[0].n = R.n_full;
-      if (R.idx[1].used) update_swapped<K>(R, kp<K>(R.full), R.n_full, true);
+      if (R.idx[1].used && !wide) update_swapped<K>(R, kp<K>(R.full), R.n_full, true);
       for (Index& ix : R.widx) update_wide<K>(R, ix, kp<K>(R.full), R.n_full, true);
     }
     if (wide) refresh_wide<K>(edbs);
@@ -1322,9 +1361,15 @@ struct hl_engine {
   template <typename K>
   void run_wide_plan(const WPlan& p) {
     Relation& O = rels[p.outer_rel];
+    const K* outer = p.outer_delta ? kp<K>(O.delta) : kp<K>(O.full);
+    const u64 n = p.outer_delta ? O.n_delta : O.n_full;
+    for (u64 o = 0; o < n; o += outer_slice)
+      run_wide_plan_on<K>(p, outer + o, std::min(outer_slice, n - o));
+  }
+
+  template <typename K>
+  void run_wide_plan_on(const WPlan& p, const K* cur, u64 n) {
     Relation& H = rels[p.head];
-    const K* cur = p.outer_delta ? kp<K>(O.delta) : kp<K>(O.full);
-    u64 n = p.outer_delta ? O.n_delta : O.n_full;
     if (n == 0) return;
     u64* d_cursor = d_small;
     if (p.steps.empty()) {
@@ -1357,7 +1402,7 @@ struct hl_engine {
       const WStep& s = p.steps[q];
       Relation& I = rels[s.inner_rel];
       Index& ix = I.widx[s.ix];
-      if (ix.n == 0 || (learned() ? !ix.lm_ok : ix.cap == 0)) return;
+      if (ix.n == 0 || (ix.nj > 0 && (learned() ? !ix.lm_ok : ix.cap == 0))) return;
       const K* inner = wide_keys<K>(I, ix);
       hl::WideSpec ws = s.ws;
       ws.w = w;
@@ -1366,7 +1411,10 @@ struct hl_engine {
       reserve_grow(join_start, n * sizeof(u32));
       reserve_grow(join_len, n * sizeof(u32));
       reserve_grow(join_off, n * sizeof(u64));
-      if (learned())
+      if (ws.nj == 0)
+        HIPCK(hl::wide_probe_all(n, ix.n, static_cast<u32*>(join_start.p),
+                                 static_cast<u32*>(join_len.p), stream, kt()));
+      else if (learned())
         HIPCK(hl::wide_probe_learned<K>(cur, n, ws, ix.view<K>(), static_cast<u32*>(join_start.p),
                                         static_cast<u32*>(join_len.p), stream, kt()));
       else
@@ -1396,7 +1444,7 @@ struct hl_engine {
         // absorbed into the head's pending delta
         const u64 tile_out = hl::join_tile_outputs(8);
         const u64 per = std::max<u64>(1, cap / tile_out);
-        reserve_grow(jchunk, per * tile_out * sizeof(K));
+        reserve(jchunk, per * tile_out * sizeof(K), per * tile_out * sizeof(K));
         for (u64 t0 = 0; t0 < nt; t0 += per) {
           const u64 tiles = std::min(per, nt - t0);
           if (filtered) {
@@ -1430,7 +1478,8 @@ struct hl_engine {
       K* out;
       u64 base = 0;
       if (last) {
-        reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + total) * sizeof(K));
+        reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + total) * sizeof(K),
+                     chunk_bytes());
         out = kp<K>(H.cand);
         base = H.n_cand;
       } else {
@@ -1462,13 +1511,25 @@ struct hl_engine {
     }
   }
 
+  // Outer tuples one join pass takes: a larger outer joins a slice at a
+  // time, which bounds the per-outer-tuple scratch of the probe and scan
+  // (16 bytes per tuple) and the intermediate results of multi-atom rules;
+  // the slices' outputs are appended like one pass's.
+  u64 outer_slice = u64(1) << 28;  // hl_options.outer_slice_log2
+
   // Evaluates one plan, appending head tuples to the head's candidates.
   template <typename K>
   void run_plan(const Plan& p) {
     Relation& O = rels[p.outer_rel];
+    const K* outer = p.outer_delta ? kp<K>(O.delta) : kp<K>(O.full);
+    const u64 n = p.outer_delta ? O.n_delta : O.n_full;
+    for (u64 o = 0; o < n; o += outer_slice)
+      run_plan_on<K>(p, outer + o, std::min(outer_slice, n - o));
+  }
+
+  template <typename K>
+  void run_plan_on(const Plan& p, const K* cur, u64 n) {
     Relation& H = rels[p.head];
-    const K* cur = p.outer_delta ? kp<K>(O.delta) : kp<K>(O.full);
-    u64 n = p.outer_delta ? O.n_delta : O.n_full;
     if (n == 0) return;
     u64* d_cursor = d_small;
     if (p.steps.empty()) {
@@ -1573,7 +1634,7 @@ struct hl_engine {
                                  join_items));
         const u64 tile_out = hl::join_tile_outputs(join_items);
         const u64 per = std::max<u64>(1, cap / tile_out);
-        reserve_grow(jchunk, per * tile_out * sizeof(K));
+        reserve(jchunk, per * tile_out * sizeof(K), per * tile_out * sizeof(K));
         const bool filt = js.fa >= 0 || js.ea >= 0 || js.dd;
         for (u64 t0 = 0; t0 < nt; t0 += per) {
           const u64 tiles = std::min(per, nt - t0);
@@ -1611,7 +1672,8 @@ struct hl_engine {
       K* out;
       u64 base = 0;
       if (last) {
-        reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + total) * sizeof(K));
+        reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + total) * sizeof(K),
+                     chunk_bytes());
         out = kp<K>(H.cand);
         base = H.n_cand;
       } else {
@@ -1694,7 +1756,8 @@ struct hl_engine {
     H.raw_cand += total;
     rule_out[p.rule] += total;
     st.join_outputs += total;
-    reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + total) * sizeof(K));
+    reserve_keep(H.cand, H.n_cand * sizeof(K), (H.n_cand + total) * sizeof(K),
+                     chunk_bytes());
     HIPCK(hl::join_nested<K>(cur, n, nj, nullptr, static_cast<u64*>(join_off.p), nullptr, nullptr,
                              nullptr, kp<K>(H.cand) + H.n_cand, stream));
     H.n_cand += total;
@@ -1750,7 +1813,7 @@ struct hl_engine {
       }
     } resume{this, caller};
     const int bits = kbits(R);
-    reserve_grow(alt, m * sizeof(K));
+    reserve_chunk(alt, m * sizeof(K));
     reserve(ws, hl::sort_workspace_bytes(m), hl::sort_workspace_bytes(m) * 2);
     K* sorted = nullptr;
     mark(HL_PHASE_SORT);
@@ -1781,10 +1844,10 @@ struct hl_engine {
     if (d == 0) return;
     mark(HL_PHASE_MERGE);
     if (p == 0) {
-      reserve(R.pend[0], d * sizeof(K), d * sizeof(K) * 2);
+      reserve(R.pend[0], d * sizeof(K), d * sizeof(K) * 3 / 2);
       HIPCK(hipMemcpyAsync(R.pend[0].p, sorted, d * sizeof(K), hipMemcpyDeviceToDevice, stream));
     } else {
-      reserve(R.pend[1], (p + d) * sizeof(K), (p + d) * sizeof(K) * 2);
+      reserve(R.pend[1], (p + d) * sizeof(K), (p + d) * sizeof(K) * 3 / 2);
       reserve(ws, hl::merge_workspace_bytes(p, d), hl::merge_workspace_bytes(p, d) * 2);
       HIPCK(hl::merge<K>(kp<K>(R.pend[0]), p, sorted, d, kp<K>(R.pend[1]), ws.p, stream, kt()));
       std::swap(R.pend[0], R.pend[1]);
@@ -1830,7 +1893,7 @@ struct hl_engine {
         HIPCK(hl::fill_zero(d_small + 2 * q, 2 * sizeof(u64), stream));
         continue;
       }
-      reserve_grow(alt, R.n_cand * sizeof(K));
+      reserve_chunk(alt, R.n_cand * sizeof(K));
       reserve(ws, hl::sort_workspace_bytes(R.n_cand), hl::sort_workspace_bytes(R.n_cand) * 2);
       K* sorted = nullptr;
       mark(HL_PHASE_SORT);
@@ -1841,15 +1904,25 @@ struct hl_engine {
       reserve(ws, hl::unique_diff_workspace_bytes(R.n_cand),
               hl::unique_diff_workspace_bytes(R.n_cand) * 2);
       mark(HL_PHASE_DIFF);
-      // delta is written over the sorted candidates, then takes their buffer
       hl::LearnedView<K> mv{};
       const bool use_model = diff_model<K>(R, R.n_cand, &mv);
-      // a tail run beside full is tested in the same pass
+      // a tail run beside full is tested in the same pass; the survivors
+      // stay in obuf until their count is known, then go to delta (which
+      // is sized by that count: handing delta the candidates' block would
+      // make both roles candidate-sized)
       HIPCK(hl::unique_diff<K>(kp<K>(sbuf), R.n_cand, kp<K>(R.full), R.n_full, kp<K>(obuf),
-                               kp<K>(sbuf), d_small + 2 * q, ws.p, stream, kt(),
+                               static_cast<K*>(nullptr), d_small + 2 * q, ws.p, stream, kt(),
                                use_model ? &mv : nullptr,
                                R.n_tail ? kp<K>(R.fz_tail[0]) : nullptr, R.n_tail, diff_items));
-      std::swap(R.delta, sbuf);
+      HIPCK(hipMemcpyAsync(h_small + 2 * q, d_small + 2 * q, sizeof(u64), hipMemcpyDeviceToHost,
+                           stream));
+      sync();
+      const u64 D = h_small[2 * q];
+      if (D > 0) {
+        reserve_grow(R.delta, D * sizeof(K));
+        HIPCK(hl::unique_diff_gather<K>(kp<K>(obuf), R.n_cand, ws.p, kp<K>(R.delta), stream,
+                                        diff_items));
+      }
     }
     HIPCK(hipMemcpyAsync(h_small, d_small, 2 * idbs.size() * sizeof(u64), hipMemcpyDeviceToHost,
                          stream));
@@ -2744,7 +2817,8 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   if (opt) o = *opt;
   if (!(o.ebm_k >= 1.0f) || !(o.hash_load_factor > 0.0f && o.hash_load_factor <= 1.0f))
     return HL_E_INVALID;
-  if (o.reserved0) return HL_E_INVALID;
+  if (o.outer_slice_log2 != 0 && (o.outer_slice_log2 < 8 || o.outer_slice_log2 > 31))
+    return HL_E_INVALID;
   if (o.arena && o.arena_bytes < 4096) return HL_E_INVALID;
   if (o.sort_chunk_log2 != 0 && (o.sort_chunk_log2 < 12 || o.sort_chunk_log2 > 31))
     return HL_E_INVALID;
@@ -2780,6 +2854,7 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   e->join_items = o.expand_tile ? int(o.expand_tile / 256) : 8;
   e->sort_items = o.sort_tile ? int(o.sort_tile / 256) : 32;
   e->tail_min_bytes = o.tail_min_bytes ? o.tail_min_bytes : hl_engine::kTailMinFullBytes;
+  e->outer_slice = u64(1) << (o.outer_slice_log2 ? o.outer_slice_log2 : 28);
   e->diff_items = o.diff_tile ? int(o.diff_tile / 256) : 16;
   int rc = guard(e, [&] {
     if (o.stream) {
@@ -2882,6 +2957,7 @@ int hl_batch_layout(hl_engine* e, const uint32_t* id_range, uint32_t n_inst) {
       if (R.n_raw) fail(HL_E_STATE, "batch layout after rows were loaded");
       if (R.arity > 2) fail(HL_E_UNSUPPORTED, "batches of relations of arity above 2");
     }
+    if (e->wide) fail(HL_E_UNSUPPORTED, "batches of wide programs");
     std::vector<u64> base(n_inst + 1, 0);
     for (u32 k = 0; k < n_inst; ++k) base[k + 1] = base[k] + id_range[k];
     if (base[n_inst] > (u64(1) << 32)) fail(HL_E_INVALID, "instance id ranges exceed 2^32");

@@ -558,15 +558,28 @@ __global__ __launch_bounds__(kFMNT) void fz_merge_kernel(const K* a, const K* b,
   const u64 tile = blockIdx.x;
   const u64 d0 = tile * kFMTile;
   if (d0 >= n) return;
-  __shared__ K s[kFMTile];
+  // written back padded by one slot per kFMItems keys (distinct banks)
+  __shared__ K s[kFMTile + kFMTile / kFMItems];
   const u64 d1 = (d0 + kFMTile) < n ? (d0 + kFMTile) : n;
   const u64 a0 = parts[tile], a1 = parts[tile + 1];
   const u64 b0 = d0 - a0, b1 = d1 - a1;
   const u32 la = u32(a1 - a0), lb = u32(b1 - b0);
-  for (u32 k = threadIdx.x; k < la; k += kFMNT) s[k] = a[a0 + k];
-  for (u32 k = threadIdx.x; k < lb; k += kFMNT) s[la + k] = b[b0 + k];
-  __syncthreads();
   const u32 total = la + lb;
+  {
+    // both slices side by side, every load issued before any is stored
+    K v[kFMItems];
+#pragma unroll
+    for (int q = 0; q < kFMItems; ++q) {
+      const u32 k = u32(q) * kFMNT + threadIdx.x;
+      v[q] = k < la ? a[a0 + k] : (k < total ? b[b0 + (k - la)] : K(0));
+    }
+#pragma unroll
+    for (int q = 0; q < kFMItems; ++q) {
+      const u32 k = u32(q) * kFMNT + threadIdx.x;
+      if (k < total) s[k] = v[q];
+    }
+  }
+  __syncthreads();
   u32 diag = threadIdx.x * kFMItems;
   if (diag > total) diag = total;
   u32 ai = u32(fz_merge_path(s, la, s + la, lb, diag));
@@ -586,10 +599,14 @@ __global__ __launch_bounds__(kFMNT) void fz_merge_kernel(const K* a, const K* b,
 #pragma unroll
   for (int k = 0; k < kFMItems; ++k) {
     const u32 o = threadIdx.x * kFMItems + k;
-    if (o < total) s[o] = v[k];
+    if (o < total) s[o + o / kFMItems] = v[k];
   }
   __syncthreads();
-  for (u32 k = threadIdx.x; k < total; k += kFMNT) out[d0 + k] = s[k];
+#pragma unroll
+  for (int q = 0; q < kFMItems; ++q) {
+    const u32 k = u32(q) * kFMNT + threadIdx.x;
+    if (k < total) out[d0 + k] = s[k + k / kFMItems];
+  }
 }
 
 // After the merges: the new delta is the next iteration's outer and the

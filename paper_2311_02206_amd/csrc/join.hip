@@ -280,11 +280,29 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   const u64 a0 = parts[tile], a1 = parts[tile + 1];
   const u64 b0 = d0 - a0, b1 = d1 - a1;
   const u32 la = u32(a1 - a0), lb = u32(b1 - b0);
-  for (u32 k = threadIdx.x; k < la; k += kNT) {
-    s_off[k] = u32(off[a0 + k] - b0);
-    s_start[k] = start[a0 + k];
-    const u64 i = a0 + k;
-    s_outer[k] = outer[i < n_split ? i : i - n_split];
+  {
+    // the tile's outer tuples (at most kTile), every load issued before any
+    // is stored
+    u64 o_off[kItems];
+    u32 o_start[kItems];
+    K o_key[kItems];
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const u32 k = u32(r) * kNT + threadIdx.x;
+      const u64 i = a0 + k;
+      o_off[r] = k < la ? off[i] : b0;
+      o_start[r] = k < la ? start[i] : 0u;
+      o_key[r] = k < la ? outer[i < n_split ? i : i - n_split] : K(0);
+    }
+#pragma unroll
+    for (int r = 0; r < kItems; ++r) {
+      const u32 k = u32(r) * kNT + threadIdx.x;
+      if (k < la) {
+        s_off[k] = u32(o_off[r] - b0);
+        s_start[k] = o_start[r];
+        s_outer[k] = o_key[r];
+      }
+    }
   }
   __syncthreads();
   // serial merge of this thread's slice of the tile's merged sequence

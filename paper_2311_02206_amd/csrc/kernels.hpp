@@ -88,11 +88,17 @@ u64 unique_diff_workspace_bytes(u64 n);
 // tail (ntail sorted unique keys, disjoint from full), keys it holds are
 // dropped too: the result is unique(sorted) \ (full U tail).
 // `items`: candidates per thread of a tile, 16 (4,096-candidate tiles) or 8.
+// With out == nullptr the survivors stay in tmp (compacted per tile) and
+// unique_diff_gather, called with the same n, ws and items before ws is
+// reused, writes them to their final place once the caller knows the count.
 template <typename K>
 hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
                        u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer = nullptr,
                        const LearnedView<K>* model = nullptr, const K* tail = nullptr,
                        u64 ntail = 0, int items = 16);
+template <typename K>
+hipError_t unique_diff_gather(const K* tmp, u64 n, const void* ws, K* out, hipStream_t s,
+                              int items = 16);
 
 // --------------------------------------------------------------- merge
 u64 merge_workspace_bytes(u64 na, u64 nb);
@@ -225,6 +231,9 @@ hipError_t wide_probe(const K* outer, u64 n, const WideSpec& ws, const Slot* tab
 template <typename K>
 hipError_t wide_probe_learned(const K* outer, u64 n, const WideSpec& ws, const LearnedView<K>& lv,
                               u32* start, u32* len, hipStream_t s, LaunchTimer* timer = nullptr);
+// A join with no shared column: (0, n_inner) for every outer tuple.
+hipError_t wide_probe_all(u64 n, u64 n_inner, u32* start, u32* len, hipStream_t s,
+                          LaunchTimer* timer = nullptr);
 // The expand of join_expand_tiles (8 outputs per thread) with WideSpec
 // outputs and tests.
 template <typename K>

@@ -111,6 +111,15 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
   const u64 hi = (part[2 * u64(tile) + 1] + 1) < nf ? (part[2 * u64(tile) + 1] + 1) : nf;
   const K before = base > 0 ? cand[base - 1] : K(0);
   const u64 m = hi - lo;
+  // the tile's candidates: every load issued before any is used (a loop
+  // that stores each into LDS as it arrives waits out one memory latency
+  // per key)
+  K cv[kUdItems];
+#pragma unroll
+  for (int q = 0; q < kUdItems; ++q) {
+    const u32 k = u32(q) * kUdNT + threadIdx.x;
+    cv[q] = k < cnt ? cand[base + k] : K(0);
+  }
   constexpr int kPer = int(kUdStage / kUdNT);
   K next[kPer];
   if (m <= kUdStreamMax) {
@@ -120,7 +129,11 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
       next[r] = i < hi ? full[i] : K(0);
     }
   }
-  for (u32 k = threadIdx.x; k < cnt; k += kUdNT) s_c[pad<kUdItems>(k)] = cand[base + k];
+#pragma unroll
+  for (int q = 0; q < kUdItems; ++q) {
+    const u32 k = u32(q) * kUdNT + threadIdx.x;
+    if (k < cnt) s_c[pad<kUdItems>(k)] = cv[q];
+  }
   __syncthreads();
   const u32 b = threadIdx.x * kUdItems;
   u32 keep_bits = 0, nkeep = 0, uniq = 0;
@@ -332,7 +345,18 @@ __global__ __launch_bounds__(kUdNT) void ud_gather_kernel(const K* tmp, const u3
   const u32 c = tile_counts[tile];
   const u64 src = u64(tile) * tile_keys;
   const u64 dst = tile_off[tile];
-  for (u32 k = threadIdx.x; k < c; k += kUdNT) out[dst + k] = tmp[src + k];
+  // at most 16 keys per thread (the largest tile), loaded before any store
+  K v[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const u32 k = u32(q) * kUdNT + threadIdx.x;
+    v[q] = k < c ? tmp[src + k] : K(0);
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const u32 k = u32(q) * kUdNT + threadIdx.x;
+    if (k < c) out[dst + k] = v[q];
+  }
 }
 
 __global__ void zero_u64x2_kernel(u64* p) {
@@ -373,17 +397,32 @@ __global__ void merge_partition_kernel(const K* a, u64 na, const K* b, u64 nb, u
 template <typename K>
 __global__ __launch_bounds__(kMgNT) void merge_kernel(const K* a, u64 na, const K* b, u64 nb,
                                                       const u64* parts, K* out) {
-  __shared__ K s[kMgTile];
+  // the merged tile goes back through LDS padded by one slot per
+  // kMgItems keys, so that each thread's run of kMgItems writes falls in
+  // distinct banks
+  __shared__ K s[kMgTile + kMgTile / kMgItems];
   const u32 tile = xcd_tile(blockIdx.x, gridDim.x);
   const u64 d0 = u64(tile) * kMgTile;
   const u64 d1 = (d0 + kMgTile) < (na + nb) ? (d0 + kMgTile) : (na + nb);
   const u64 a0 = parts[tile], a1 = parts[tile + 1];
   const u64 b0 = d0 - a0, b1 = d1 - a1;
   const u32 la = u32(a1 - a0), lb = u32(b1 - b0);
-  for (u32 k = threadIdx.x; k < la; k += kMgNT) s[k] = a[a0 + k];
-  for (u32 k = threadIdx.x; k < lb; k += kMgNT) s[la + k] = b[b0 + k];
-  __syncthreads();
   const u32 total = la + lb;
+  {
+    // both slices side by side, every load issued before any is stored
+    K v[kMgItems];
+#pragma unroll
+    for (int q = 0; q < kMgItems; ++q) {
+      const u32 k = u32(q) * kMgNT + threadIdx.x;
+      v[q] = k < la ? a[a0 + k] : (k < total ? b[b0 + (k - la)] : K(0));
+    }
+#pragma unroll
+    for (int q = 0; q < kMgItems; ++q) {
+      const u32 k = u32(q) * kMgNT + threadIdx.x;
+      if (k < total) s[k] = v[q];
+    }
+  }
+  __syncthreads();
   u32 diag = threadIdx.x * kMgItems;
   if (diag > total) diag = total;
   u32 ai = u32(merge_path(s, la, s + la, lb, diag));
@@ -408,10 +447,14 @@ __global__ __launch_bounds__(kMgNT) void merge_kernel(const K* a, u64 na, const 
 #pragma unroll
   for (int k = 0; k < kMgItems; ++k) {
     u32 o = threadIdx.x * kMgItems + k;
-    if (o < total) s[o] = r[k];
+    if (o < total) s[o + o / kMgItems] = r[k];
   }
   __syncthreads();
-  for (u32 k = threadIdx.x; k < total; k += kMgNT) out[d0 + k] = s[k];
+#pragma unroll
+  for (int q = 0; q < kMgItems; ++q) {
+    const u32 k = u32(q) * kMgNT + threadIdx.x;
+    if (k < total) out[d0 + k] = s[k + k / kMgItems];
+  }
 }
 
 u64 ud_tiles(u64 n, u64 tile) { return (n + tile - 1) / tile; }
@@ -483,8 +526,23 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   // the distinct count: a prefix sum whose total is all that is kept (into
   // part, which the select no longer needs)
   e = scan_u32_u64(tile_uniq, nt, part, d_counts + 1, p, s);
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || !out) return e;
   ud_gather_kernel<K><<<grid, kUdNT, 0, s>>>(tmp, tile_counts, tile_off, tile_keys, out);
+  return hipGetLastError();
+}
+
+template <typename K>
+hipError_t unique_diff_gather(const K* tmp, u64 n, const void* ws, K* out, hipStream_t s,
+                              int items) {
+  if (n == 0) return hipSuccess;
+  if (n >= (u64(1) << 32) || (items != 8 && items != 16)) return hipErrorInvalidValue;
+  const u64 tile_keys = u64(kUdNT) * u64(items);
+  const u64 nt = ud_tiles(n, tile_keys);
+  const char* p = static_cast<const char*>(ws);
+  const u32* tile_counts = reinterpret_cast<const u32*>(p);
+  p += 2 * align_up(nt * sizeof(u32), 256);
+  const u64* tile_off = reinterpret_cast<const u64*>(p);
+  ud_gather_kernel<K><<<dim3(u32(nt)), kUdNT, 0, s>>>(tmp, tile_counts, tile_off, tile_keys, out);
   return hipGetLastError();
 }
 
@@ -517,6 +575,10 @@ template hipError_t unique_diff<u32>(const u32*, u64, const u32*, u64, u32*, u32
 template hipError_t unique_diff<u64>(const u64*, u64, const u64*, u64, u64*, u64*, u64*, void*,
                                      hipStream_t, LaunchTimer*, const LearnedView<u64>*,
                                      const u64*, u64, int);
+template hipError_t unique_diff_gather<u32>(const u32*, u64, const void*, u32*, hipStream_t,
+                                            int);
+template hipError_t unique_diff_gather<u64>(const u64*, u64, const void*, u64*, hipStream_t,
+                                            int);
 template hipError_t merge<u32>(const u32*, u64, const u32*, u64, u32*, void*, hipStream_t,
                                LaunchTimer*);
 template hipError_t merge<u64>(const u64*, u64, const u64*, u64, u64*, void*, hipStream_t,

@@ -178,6 +178,16 @@ __global__ __launch_bounds__(kNT) void wide_probe_learned_kernel(const K* outer,
   }
 }
 
+// A join with no shared column (a cross product): every outer tuple takes
+// the whole inner array.
+__global__ __launch_bounds__(kNT) void wide_probe_all_kernel(u64 n, u32 n_inner, u32* start,
+                                                             u32* len) {
+  const u64 i = u64(blockIdx.x) * kNT + threadIdx.x;
+  if (i >= n) return;
+  start[i] = 0;
+  len[i] = n_inner;
+}
+
 // One-atom bodies: each input tuple becomes one head tuple (column sources
 // 0..3 of the input, 8 the constant 0), kept if it passes the tests.
 template <typename K>
@@ -303,6 +313,18 @@ hipError_t wide_probe(const K* outer, u64 n, const WideSpec& ws, const Slot* tab
   wide_probe_kernel<K><<<dim3(u32(blocks)), kNT, 0, s>>>(outer, n, ws, table, cap, inner, start,
                                                          len);
   if (timer) timer->end(K_JOIN_PROBE, s, n * (sizeof(K) + sizeof(Slot) + 2 * sizeof(u32)));
+  return hipGetLastError();
+}
+
+hipError_t wide_probe_all(u64 n, u64 n_inner, u32* start, u32* len, hipStream_t s,
+                          LaunchTimer* timer) {
+  if (n == 0) return hipSuccess;
+  if (n_inner >= (u64(1) << 32)) return hipErrorInvalidValue;
+  const u64 blocks = (n + kNT - 1) / kNT;
+  if (blocks >= (u64(1) << 31)) return hipErrorInvalidValue;
+  if (timer) timer->begin(K_JOIN_PROBE, s);
+  wide_probe_all_kernel<<<dim3(u32(blocks)), kNT, 0, s>>>(n, u32(n_inner), start, len);
+  if (timer) timer->end(K_JOIN_PROBE, s, n * 2 * sizeof(u32));
   return hipGetLastError();
 }
 

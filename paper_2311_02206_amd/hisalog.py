@@ -63,7 +63,7 @@ class Options(ctypes.Structure):
         ("hash_load_factor", ctypes.c_float), ("sort_chunk_log2", ctypes.c_uint32),
         ("fused_capacity", ctypes.c_uint32), ("expand_tile", ctypes.c_uint32),
         ("sort_tile", ctypes.c_uint32), ("diff_tile", ctypes.c_uint32),
-        ("reserved0", ctypes.c_uint32), ("tail_min_bytes", ctypes.c_uint64),
+        ("outer_slice_log2", ctypes.c_uint32), ("tail_min_bytes", ctypes.c_uint64),
     ]
 
 
@@ -191,7 +191,7 @@ class Engine:
                  join_dedup: bool = False, fused: bool = False, hip_graph: bool = False,
                  fused_capacity: int = 0, nested_joins: bool = False, expand_tile: int = 0,
                  sort_tile: int = 0, diff_tile: int = 0, levels: bool = True,
-                 tail_min_bytes: int = 0):
+                 tail_min_bytes: int = 0, outer_slice_log2: int = 0):
         L = lib()
         opt = Options()
         L.hl_options_init(ctypes.byref(opt))
@@ -213,6 +213,7 @@ class Engine:
         opt.sort_tile = sort_tile
         opt.diff_tile = diff_tile
         opt.tail_min_bytes = tail_min_bytes
+        opt.outer_slice_log2 = outer_slice_log2
         self._arena = arena  # keep the caller's tensor alive
         if arena is not None:
             opt.arena = _ptr(arena)
