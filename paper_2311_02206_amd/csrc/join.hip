@@ -262,13 +262,14 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   constexpr u32 kDedupSlots = 2 * u32(kTile);
   // Offsets of the tile's outer tuples relative to its first output b0: the
   // merge path puts every one of them in [b0, b1], so 32 bits hold them.
-  // s_pool holds them and the run starts; after the block scan below (once
-  // both are no longer read) it holds the surviving outputs instead.
+  // s_pool holds them (la words), the owner of each of the tile's outputs
+  // right after them (lb words; la + lb <= kTile) and the run starts; after
+  // the block scan below (once all are no longer read) it holds the
+  // surviving outputs instead.
   __shared__ u32 s_pool[2 * kTile];
   static_assert(sizeof(K) * kTile <= sizeof(u32) * 2 * kTile, "survivors fit the pool");
   u32* s_off = s_pool;
   u32* s_start = s_pool + kTile;
-  __shared__ u32 s_owner[kTile];
   __shared__ K s_outer[kTile];
   // tiles tile0 .. tile0 + gridDim.x - 1; unfiltered outputs are written
   // relative to the first output of tile0
@@ -280,6 +281,7 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   const u64 a0 = parts[tile], a1 = parts[tile + 1];
   const u64 b0 = d0 - a0, b1 = d1 - a1;
   const u32 la = u32(a1 - a0), lb = u32(b1 - b0);
+  u32* s_owner = s_pool + la;
   {
     // the tile's outer tuples (at most kTile), every load issued before any
     // is stored
