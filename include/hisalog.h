@@ -157,7 +157,8 @@ typedef struct hl_options {
                                 against ~2.5 at 0.5) */
   uint32_t sort_chunk_log2;  /* an iteration's new tuples are sorted in chunks
                                 of at most 2^sort_chunk_log2 keys (12..31;
-                                0: 31) */
+                                0: just under 2^32 keys for 4-byte keys,
+                                2^31 for 8-byte keys) */
   uint32_t fused_capacity;   /* new tuples (distinct candidates, new or
                                 already held) a fused iteration gathers per
                                 relation in LDS (HL_FLAG_FUSED): a power of

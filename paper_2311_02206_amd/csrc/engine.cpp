@@ -478,7 +478,7 @@ struct hl_engine {
   u32 flags = 0;
   float ebm_k = 8.0f;
   float load_factor = 0.5f;
-  int sort_chunk_log2 = 31;
+  int sort_chunk_log2 = 0;  // 0: the largest one sort takes (chunk_keys)
   u32 fused_capacity = 0;  // 0: the largest that fits
   int join_items = 8;      // join expand outputs per thread (4, 8, 16)
   int sort_items = 32;     // radix sort keys per thread of a tile (16, 32)
@@ -578,7 +578,14 @@ struct hl_engine {
   }
   void reserve_grow(Buf& b, u64 need) { reserve(b, need, need + need / 2); }
   // Largest array of keys one sort takes (a chunk), in bytes.
-  u64 chunk_bytes() const { return (u64(1) << sort_chunk_log2) * key_bytes; }
+  u64 chunk_bytes() const { return chunk_keys() * key_bytes; }
+  // Keys of one sort chunk: 2^sort_chunk_log2 when set, else just under
+  // the sort's 2^32 limit for 4-byte keys (a 17 GB chunk) and 2^31 for
+  // 8-byte keys (a chunk's three buffers of 17 GB each).
+  u64 chunk_keys() const {
+    if (sort_chunk_log2) return u64(1) << sort_chunk_log2;
+    return key_bytes == 4 ? (u64(1) << 32) - (u64(1) << 16) : u64(1) << 31;
+  }
   // Like reserve_grow for a buffer that holds at most one chunk of keys in
   // its steady use: its growth stops at the chunk's size.
   void reserve_chunk(Buf& b, u64 need) {
@@ -1434,7 +1441,7 @@ struct hl_engine {
         st.join_outputs += total;
       }
       const bool filtered = ws.nf > 0 || ws.ne > 0;
-      const u64 cap = u64(1) << sort_chunk_log2;
+      const u64 cap = chunk_keys();
       const u64 nt = hl::join_tiles(n, total, 8);
       reserve_grow(join_parts, hl::join_parts(n, total, 8) * sizeof(u64));
       u64* parts = static_cast<u64*>(join_parts.p);
@@ -1622,7 +1629,7 @@ struct hl_engine {
         H.raw_cand += total;
         st.join_outputs += total;
       }
-      const u64 cap = u64(1) << sort_chunk_log2;
+      const u64 cap = chunk_keys();
       if (last && total > cap) {
         // One join's outputs exceed one sort: expand a range of tiles at a
         // time (at most `cap` outputs) and absorb each range into the head
@@ -1750,7 +1757,7 @@ struct hl_engine {
     if (u32(h_small[2]) != 0)
       fail(HL_E_UNSUPPORTED, "nested join: an outer tuple with 2^32 or more outputs");
     const u64 total = h_small[1];
-    if (total > (u64(1) << sort_chunk_log2)) return false;
+    if (total > chunk_keys()) return false;
     if (total == 0) return true;
     // the nested form counts kept outputs only: they are its join outputs
     H.raw_cand += total;
@@ -1856,12 +1863,12 @@ struct hl_engine {
   }
 
   // Delta of a relation that has pending tuples or whose new tuples exceed
-  // one sort (2^sort_chunk_log2 keys): the candidates are absorbed chunk by
+  // one sort chunk (chunk_keys()): the candidates are absorbed chunk by
   // chunk and the pending set becomes delta.  Returns (|delta|, sum over
   // chunks of their distinct tuples).
   template <typename K>
   std::pair<u64, u64> chunked_delta(Relation& R) {
-    const u64 kChunk = u64(1) << sort_chunk_log2;
+    const u64 kChunk = chunk_keys();
     for (u64 c = 0; c < R.n_cand; c += kChunk)
       absorb<K>(R, kp<K>(R.cand) + c, std::min(kChunk, R.n_cand - c));
     std::swap(R.delta, R.pend[0]);
@@ -1888,7 +1895,7 @@ struct hl_engine {
         HIPCK(hl::fill_zero(d_small + 2 * q, 2 * sizeof(u64), stream));
         continue;
       }
-      if (R.n_pend > 0 || R.n_cand > (u64(1) << sort_chunk_log2)) {
+      if (R.n_pend > 0 || R.n_cand > chunk_keys()) {
         chunked.push_back({q, chunked_delta<K>(R)});
         HIPCK(hl::fill_zero(d_small + 2 * q, 2 * sizeof(u64), stream));
         continue;
@@ -2849,7 +2856,7 @@ int hl_create(const hl_options* opt, hl_engine** out) {
   e->flags = o.flags;
   e->ebm_k = o.ebm_k;
   e->load_factor = o.hash_load_factor;
-  e->sort_chunk_log2 = o.sort_chunk_log2 ? int(o.sort_chunk_log2) : 31;
+  e->sort_chunk_log2 = int(o.sort_chunk_log2);
   e->fused_capacity = o.fused_capacity;
   e->join_items = o.expand_tile ? int(o.expand_tile / 256) : 8;
   e->sort_items = o.sort_tile ? int(o.sort_tile / 256) : 32;
