@@ -27,23 +27,63 @@ __global__ __launch_bounds__(kNT) void scan_reduce_kernel(const Tin* in, u64 n, 
   if (threadIdx.x == 0) sums[blockIdx.x] = s;
 }
 
+// Eight consecutive values of in from i (zero past n): two or four 16-byte
+// loads when the eight lie inside the array and the address is aligned.
+template <typename Tin>
+__device__ __forceinline__ void load_items(const Tin* in, u64 i, u64 n, u64 (&v)[kItems]) {
+  const Tin* p = in + i;
+  if (i + kItems <= n && (reinterpret_cast<uintptr_t>(p) & 15) == 0) {
+    if constexpr (sizeof(Tin) == 4) {
+      const uint4 a = reinterpret_cast<const uint4*>(p)[0];
+      const uint4 b = reinterpret_cast<const uint4*>(p)[1];
+      v[0] = a.x, v[1] = a.y, v[2] = a.z, v[3] = a.w;
+      v[4] = b.x, v[5] = b.y, v[6] = b.z, v[7] = b.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < kItems / 2; ++k) {
+        const ulonglong2 a = reinterpret_cast<const ulonglong2*>(p)[k];
+        v[2 * k] = a.x;
+        v[2 * k + 1] = a.y;
+      }
+    }
+    return;
+  }
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) v[j] = (i + j < n) ? u64(p[j]) : 0;
+}
+
 // offsets == nullptr: one block scans `tiles` tiles in turn, from 0.
+// Each thread takes kItems consecutive values: a serial scan of its own,
+// one block scan of the thread totals, then its outputs written together.
 template <typename Tin>
 __global__ __launch_bounds__(kNT) void scan_down_kernel(const Tin* in, u64 n, const u64* offsets,
                                                         u64* out, u64* d_total, u32 tiles = 1) {
   __shared__ u64 lds[kNT / kWave];
   u64 carry = offsets ? offsets[blockIdx.x] : 0;
   for (u32 q = 0; q < tiles; ++q) {
-    const u64 base = (u64(blockIdx.x) + q) * kTile;
+    const u64 i0 = (u64(blockIdx.x) + q) * kTile + u64(threadIdx.x) * kItems;
+    u64 v[kItems];
+    load_items(in, i0, n, v);
+    u64 run = 0;
 #pragma unroll
     for (int j = 0; j < kItems; ++j) {
-      u64 i = base + u64(j) * kNT + threadIdx.x;
-      u64 v = i < n ? u64(in[i]) : 0;
-      u64 tot;
-      u64 ex = block_exclusive_scan<kNT>(v, lds, tot);
-      if (i < n) out[i] = carry + ex;
-      carry += tot;
+      const u64 x = v[j];
+      v[j] = run;
+      run += x;
     }
+    u64 tot;
+    const u64 ex = carry + block_exclusive_scan<kNT>(run, lds, tot);
+    u64* o = out + i0;
+    if (i0 + kItems <= n && (reinterpret_cast<uintptr_t>(o) & 15) == 0) {
+#pragma unroll
+      for (int k = 0; k < kItems / 2; ++k)
+        reinterpret_cast<ulonglong2*>(o)[k] = make_ulonglong2(ex + v[2 * k], ex + v[2 * k + 1]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < kItems; ++j)
+        if (i0 + j < n) o[j] = ex + v[j];
+    }
+    carry += tot;
   }
   if (d_total && blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) *d_total = carry;
 }
