@@ -55,39 +55,57 @@ __device__ __forceinline__ K pick(int src, K c0, K c1, K o) {
   return src == 0 ? c0 : (src == 1 ? c1 : (src == 2 ? o : K(0)));
 }
 
-// One lane per outer tuple.  Outer arrays are sorted on (or grouped by)
-// their first column, so neighbouring tuples often share the join key: only
-// the first lane of each run of equal keys within a wave probes, and the
-// run's other lanes take its result by a wave shuffle.
+// kProbeItems outer tuples per lane, in rounds of kNT consecutive tuples
+// per block (64 per wave): every round's outer loads are issued first, then
+// every round's probes, then the writes, so a wave keeps several
+// independent memory accesses in flight.  Outer arrays are sorted on (or
+// grouped by) their first column, so neighbouring tuples often share the
+// join key: only the first lane of each run of equal keys within a wave
+// probes, and the run's other lanes take its result by a wave shuffle.
+constexpr int kProbeItems = 4;
+
 template <typename K>
 __global__ __launch_bounds__(kNT) void probe_kernel(const K* outer, u64 n, int outer_col, int w,
                                                     const Slot* table, u64 cap, u32* start,
                                                     u32* len) {
-  const u64 i = u64(blockIdx.x) * kNT + threadIdx.x;
-  const bool valid = i < n;
   const K mask = (K(1) << w) - 1;
-  u32 jc = 0, prev = 0;
-  if (valid) {
-    const K k = outer[i];
-    jc = outer_col == 0 ? u32(k >> w) : u32(k & mask);
-    if (i > 0) {
-      const K kp = outer[i - 1];
-      prev = outer_col == 0 ? u32(kp >> w) : u32(kp & mask);
+  const u64 i0 = u64(blockIdx.x) * (kNT * kProbeItems) + threadIdx.x;
+  const int lane = lane_id();
+  u32 jc[kProbeItems];
+#pragma unroll
+  for (int r = 0; r < kProbeItems; ++r) {
+    const u64 i = i0 + u64(r) * kNT;
+    jc[r] = 0;
+    if (i < n) {
+      const K k = outer[i];
+      jc[r] = outer_col == 0 ? u32(k >> w) : u32(k & mask);
     }
   }
-  const int lane = lane_id();
-  const bool leader = valid && (lane == 0 || i == 0 || jc != prev);
-  const u64 lm = ballot(leader);
-  u32 st = 0, ln = 0;
-  if (leader && !hisa_find(table, cap, jc, st, ln)) ln = 0;
-  // the leader of this lane's run: highest leader lane at or below it
-  const u64 upto = lm & ((lane == 63) ? ~u64(0) : ((u64(2) << lane) - 1));
-  const int src = upto ? 63 - __clzll((long long)upto) : lane;
-  st = __shfl(st, src, kWave);
-  ln = __shfl(ln, src, kWave);
-  if (valid) {
-    start[i] = st;
-    len[i] = ln;
+  u32 st[kProbeItems], ln[kProbeItems];
+  u64 lm[kProbeItems];
+#pragma unroll
+  for (int r = 0; r < kProbeItems; ++r) {
+    const u64 i = i0 + u64(r) * kNT;
+    // a wave's first lane always probes; any other lane probes when its key
+    // differs from the lane below
+    const u32 below = __shfl_up(jc[r], 1, kWave);
+    const bool leader = i < n && (lane == 0 || jc[r] != below);
+    lm[r] = ballot(leader);
+    st[r] = ln[r] = 0;
+    if (leader && !hisa_find(table, cap, jc[r], st[r], ln[r])) ln[r] = 0;
+  }
+#pragma unroll
+  for (int r = 0; r < kProbeItems; ++r) {
+    const u64 i = i0 + u64(r) * kNT;
+    // the leader of this lane's run: highest leader lane at or below it
+    const u64 upto = lm[r] & ((lane == 63) ? ~u64(0) : ((u64(2) << lane) - 1));
+    const int src = upto ? 63 - __clzll((long long)upto) : lane;
+    const u32 s0 = __shfl(st[r], src, kWave);
+    const u32 l0 = __shfl(ln[r], src, kWave);
+    if (i < n) {
+      start[i] = s0;
+      len[i] = l0;
+    }
   }
 }
 
@@ -95,48 +113,53 @@ template <typename K>
 __global__ __launch_bounds__(kNT) void probe_learned_kernel(const K* outer, u64 n, int outer_col,
                                                             int w, LearnedView<K> lv, u32* start,
                                                             u32* len) {
-  const u64 i = u64(blockIdx.x) * kNT + threadIdx.x;
-  const bool valid = i < n;
   const K mask = (K(1) << w) - 1;
-  u32 jc = 0, prev = 0;
-  if (valid) {
-    const K k = outer[i];
-    jc = outer_col == 0 ? u32(k >> w) : u32(k & mask);
-    if (i > 0) {
-      const K kp = outer[i - 1];
-      prev = outer_col == 0 ? u32(kp >> w) : u32(kp & mask);
-    }
-  }
+  const u64 i0 = u64(blockIdx.x) * (kNT * kProbeItems) + threadIdx.x;
   const int lane = lane_id();
-  const bool leader = valid && (lane == 0 || i == 0 || jc != prev);
-  const u64 lm = ballot(leader);
-  u32 st = 0, ln = 0;
-  if (leader) {
-    st = lm_lower_bound(lv, K(jc) << w);
-    // the run's end: gallop forward from its start (runs are short, so
-    // this stays within a cache line or two of the start), then bisect
-    if (st < lv.n && K(lv.keys[st] >> w) == K(jc)) {
-      u64 good = st, step = 1;  // keys[good] is in the run
-      while (good + step < lv.n && K(lv.keys[good + step] >> w) == K(jc)) {
-        good += step;
-        step <<= 1;
-      }
-      u64 lo = good + 1, hi = (good + step < lv.n) ? good + step : lv.n;  // end in [lo, hi]
-      while (lo < hi) {
-        const u64 mid = (lo + hi) >> 1;
-        if (K(lv.keys[mid] >> w) == K(jc)) lo = mid + 1;
-        else hi = mid;
-      }
-      ln = u32(lo - st);
+  u32 jc[kProbeItems];
+#pragma unroll
+  for (int r = 0; r < kProbeItems; ++r) {
+    const u64 i = i0 + u64(r) * kNT;
+    jc[r] = 0;
+    if (i < n) {
+      const K k = outer[i];
+      jc[r] = outer_col == 0 ? u32(k >> w) : u32(k & mask);
     }
   }
-  const u64 upto = lm & ((lane == 63) ? ~u64(0) : ((u64(2) << lane) - 1));
-  const int src = upto ? 63 - __clzll((long long)upto) : lane;
-  st = __shfl(st, src, kWave);
-  ln = __shfl(ln, src, kWave);
-  if (valid) {
-    start[i] = ln ? st : 0;
-    len[i] = ln;
+#pragma unroll
+  for (int r = 0; r < kProbeItems; ++r) {
+    const u64 i = i0 + u64(r) * kNT;
+    const u32 below = __shfl_up(jc[r], 1, kWave);
+    const bool leader = i < n && (lane == 0 || jc[r] != below);
+    const u64 lm = ballot(leader);
+    u32 st = 0, ln = 0;
+    if (leader) {
+      st = lm_lower_bound(lv, K(jc[r]) << w);
+      // the run's end: gallop forward from its start (runs are short, so
+      // this stays within a cache line or two of the start), then bisect
+      if (st < lv.n && K(lv.keys[st] >> w) == K(jc[r])) {
+        u64 good = st, step = 1;  // keys[good] is in the run
+        while (good + step < lv.n && K(lv.keys[good + step] >> w) == K(jc[r])) {
+          good += step;
+          step <<= 1;
+        }
+        u64 lo = good + 1, hi = (good + step < lv.n) ? good + step : lv.n;  // end in [lo, hi]
+        while (lo < hi) {
+          const u64 mid = (lo + hi) >> 1;
+          if (K(lv.keys[mid] >> w) == K(jc[r])) lo = mid + 1;
+          else hi = mid;
+        }
+        ln = u32(lo - st);
+      }
+    }
+    const u64 upto = lm & ((lane == 63) ? ~u64(0) : ((u64(2) << lane) - 1));
+    const int src = upto ? 63 - __clzll((long long)upto) : lane;
+    st = __shfl(st, src, kWave);
+    ln = __shfl(ln, src, kWave);
+    if (i < n) {
+      start[i] = ln ? st : 0;
+      len[i] = ln;
+    }
   }
 }
 
@@ -270,7 +293,6 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   static_assert(sizeof(K) * kTile <= sizeof(u32) * 2 * kTile, "survivors fit the pool");
   u32* s_off = s_pool;
   u32* s_start = s_pool + kTile;
-  __shared__ K s_outer[kTile];
   // tiles tile0 .. tile0 + gridDim.x - 1; unfiltered outputs are written
   // relative to the first output of tile0
   const u64 tile = tile0 + blockIdx.x;
@@ -287,14 +309,12 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
     // is stored
     u64 o_off[kItems];
     u32 o_start[kItems];
-    K o_key[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const u32 k = u32(r) * kNT + threadIdx.x;
       const u64 i = a0 + k;
       o_off[r] = k < la ? off[i] : b0;
       o_start[r] = k < la ? start[i] : 0u;
-      o_key[r] = k < la ? outer[i < n_split ? i : i - n_split] : K(0);
     }
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
@@ -302,7 +322,6 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
       if (k < la) {
         s_off[k] = u32(o_off[r] - b0);
         s_start[k] = o_start[r];
-        s_outer[k] = o_key[r];
       }
     }
   }
@@ -355,7 +374,10 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
       const bool here = u64(i) >= a0;
       const u64 pos = here ? u64(s_start[u64(i) - a0]) + (k - s_off[u64(i) - a0])
                            : u64(start[i]) + (b0 + k - off[i]);
-      const K ok = here ? s_outer[u64(i) - a0] : outer[u64(i) < n_split ? i : i - n_split];
+      // the outer tuple from global memory (consecutive outputs share it, so
+      // it is a cache hit; keeping it out of LDS leaves room for more
+      // workgroups per CU), read beside the inner tuple
+      const K ok = outer[u64(i) < n_split ? i : i - n_split];
       const K* in = u64(i) < n_split ? inner : inner2;
       bool pass;
       v[r] = g(ok, in[pos], pass);
@@ -510,7 +532,7 @@ hipError_t join_probe(const K* outer, u64 n, const JoinSpec& js, const Slot* tab
   if (n == 0) return hipSuccess;
   if (cap == 0 || cap > (u64(1) << 32) || js.outer_col < 0 || js.outer_col > 1)
     return hipErrorInvalidValue;
-  const u64 blocks = (n + kNT - 1) / kNT;
+  const u64 blocks = (n + kNT * kProbeItems - 1) / (kNT * kProbeItems);
   if (blocks >= (u64(1) << 31)) return hipErrorInvalidValue;
   if (timer) timer->begin(K_JOIN_PROBE, s);
   probe_kernel<K><<<dim3(u32(blocks)), kNT, 0, s>>>(outer, n, js.outer_col, js.w, table, cap,
@@ -525,7 +547,7 @@ hipError_t join_probe_learned(const K* outer, u64 n, const JoinSpec& js,
                               LaunchTimer* timer) {
   if (n == 0) return hipSuccess;
   if (js.outer_col < 0 || js.outer_col > 1 || lv.n >= (u64(1) << 32)) return hipErrorInvalidValue;
-  const u64 blocks = (n + kNT - 1) / kNT;
+  const u64 blocks = (n + kNT * kProbeItems - 1) / (kNT * kProbeItems);
   if (blocks >= (u64(1) << 31)) return hipErrorInvalidValue;
   if (timer) timer->begin(K_JOIN_PROBE, s);
   probe_learned_kernel<K><<<dim3(u32(blocks)), kNT, 0, s>>>(outer, n, js.outer_col, js.w, lv,
