@@ -392,6 +392,10 @@ struct Relation {
   u64 n_raw = 0;
   Buf full, full_spare, delta, cand;
   u64 n_full = 0, n_delta = 0, n_cand = 0;
+  // share of the tiles of this relation's last set difference whose slice
+  // of full was searched in global memory rather than streamed: a model of
+  // full is fitted for the set difference only where such searches happen
+  double lockstep_share = 0;
   Index idx[2];
   // indexes of the tail run of a relation probed as a join inner (kept as
   // two levels): tidx[0] over the tail itself, tidx[1] over its
@@ -579,6 +583,11 @@ struct hl_engine {
   void reserve_grow(Buf& b, u64 need) { reserve(b, need, need + need / 2); }
   // Largest array of keys one sort takes (a chunk), in bytes.
   u64 chunk_bytes() const { return chunk_keys() * key_bytes; }
+  // Tiles of a set difference over m candidates.
+  u64 diff_tiles(u64 m) const {
+    const u64 t = 256 * u64(diff_items);
+    return std::max<u64>(1, (m + t - 1) / t);
+  }
   // Keys of one sort chunk: 2^sort_chunk_log2 when set, else just under
   // the sort's 2^32 limit for 4-byte keys (a 17 GB chunk) and 2^31 for
   // 8-byte keys (a chunk's three buffers of 17 GB each).
@@ -1775,17 +1784,21 @@ struct hl_engine {
   // Model of R's full relation for the set difference of n_cand sorted
   // candidates, if it has a current one.  A relation that no join probes
   // gets one fitted here when its candidates are spread thinly over a
-  // large full (at least 8 keys of full per candidate, so a tile's slice is
-  // searched, not streamed) and full is large enough to be kept stable by
-  // a tail run: the model then lasts until the tail is folded in, and each
-  // search starts from the model's window instead of the whole slice.
+  // large full (at least 8 keys of full per candidate), the relation's
+  // last difference searched a quarter or more of its tiles in global
+  // memory (candidates grouped by their first column keep slices short
+  // however large full is), and full is being kept stable by a tail run:
+  // the model then lasts until the tail is folded in, and each search
+  // starts from the model's window instead of the whole slice.  A full
+  // merged anew every iteration would need a fit per difference, which the
+  // searches do not repay.
   template <typename K>
   bool diff_model(Relation& R, u64 n_cand, hl::LearnedView<K>* mv) {
     if (!learned() || R.n_full == 0) return false;
     Index& ix = R.idx[0];
     bool use = ix.lm_ok && ix.lm_keys == R.full.p && ix.lm_n == R.n_full;
     if (!use && !ix.used && tail_ok(R) && R.n_full * sizeof(K) >= tail_min_bytes &&
-        R.n_full >= 8 * n_cand) {
+        R.n_full >= 8 * n_cand && R.lockstep_share >= 0.25 && R.n_tail > 0) {
       const int caller = marks.empty() ? -1 : marks.back().first;
       mark(HL_PHASE_INDEX);
       fit_model<K>(R, 0);
@@ -1833,11 +1846,14 @@ struct hl_engine {
     hl::LearnedView<K> mv{};
     const bool use_model = diff_model<K>(R, m, &mv);
     // the tail run beside full, if any, is tested in the same pass
+    HIPCK(hl::fill_zero(dc + 2, sizeof(u64), stream));
     HIPCK(hl::unique_diff<K>(sorted, m, kp<K>(R.full), R.n_full, other, sorted, dc, ws.p, stream,
                              kt(), use_model ? &mv : nullptr,
-                             R.n_tail ? kp<K>(R.fz_tail[0]) : nullptr, R.n_tail, diff_items));
-    HIPCK(hipMemcpyAsync(hc, dc, 2 * sizeof(u64), hipMemcpyDeviceToHost, stream));
+                             R.n_tail ? kp<K>(R.fz_tail[0]) : nullptr, R.n_tail, diff_items,
+                             dc + 2));
+    HIPCK(hipMemcpyAsync(hc, dc, 3 * sizeof(u64), hipMemcpyDeviceToHost, stream));
     sync();
+    R.lockstep_share = double(hc[2]) / double(diff_tiles(m));
     u64 d = hc[0];
     R.pend_uniq += hc[1];
     const u64 p = R.n_pend;
@@ -1917,13 +1933,19 @@ struct hl_engine {
       // stay in obuf until their count is known, then go to delta (which
       // is sized by that count: handing delta the candidates' block would
       // make both roles candidate-sized)
+      u64* d_lock = d_small + kChunkSlots + 2;
+      HIPCK(hl::fill_zero(d_lock, sizeof(u64), stream));
       HIPCK(hl::unique_diff<K>(kp<K>(sbuf), R.n_cand, kp<K>(R.full), R.n_full, kp<K>(obuf),
                                static_cast<K*>(nullptr), d_small + 2 * q, ws.p, stream, kt(),
                                use_model ? &mv : nullptr,
-                               R.n_tail ? kp<K>(R.fz_tail[0]) : nullptr, R.n_tail, diff_items));
+                               R.n_tail ? kp<K>(R.fz_tail[0]) : nullptr, R.n_tail, diff_items,
+                               d_lock));
       HIPCK(hipMemcpyAsync(h_small + 2 * q, d_small + 2 * q, sizeof(u64), hipMemcpyDeviceToHost,
                            stream));
+      HIPCK(hipMemcpyAsync(h_small + kChunkSlots + 2, d_lock, sizeof(u64), hipMemcpyDeviceToHost,
+                           stream));
       sync();
+      R.lockstep_share = double(h_small[kChunkSlots + 2]) / double(diff_tiles(R.n_cand));
       const u64 D = h_small[2 * q];
       if (D > 0) {
         reserve_grow(R.delta, D * sizeof(K));
@@ -2655,6 +2677,7 @@ struct hl_engine {
       R.new_counts.clear();
       R.n_delta = R.n_cand = 0;
       R.n_tail = 0;
+      R.lockstep_share = 0;
       R.dedup = true;
       R.raw_cand = 0;
       R.idx[0].lm_ok = R.idx[1].lm_ok = false;

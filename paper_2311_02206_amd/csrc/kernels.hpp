@@ -91,11 +91,13 @@ u64 unique_diff_workspace_bytes(u64 n);
 // With out == nullptr the survivors stay in tmp (compacted per tile) and
 // unique_diff_gather, called with the same n, ws and items before ws is
 // reused, writes them to their final place once the caller knows the count.
+// lockstep_tiles (device, optional): incremented once per tile whose slice
+// of full is too long to stream (its keys are searched in global memory).
 template <typename K>
 hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
                        u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer = nullptr,
                        const LearnedView<K>* model = nullptr, const K* tail = nullptr,
-                       u64 ntail = 0, int items = 16);
+                       u64 ntail = 0, int items = 16, u64* lockstep_tiles = nullptr);
 template <typename K>
 hipError_t unique_diff_gather(const K* tmp, u64 n, const void* ws, K* out, hipStream_t s,
                               int items = 16);

@@ -92,7 +92,8 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
                                                           u64 nf, K* tmp, u32* tile_counts,
                                                           u32* tile_uniq, LearnedView<K> lv,
                                                           const u64* part, const K* tail,
-                                                          u64 ntail, u64* alg_bytes) {
+                                                          u64 ntail, u64* alg_bytes,
+                                                          u64* lockstep_tiles) {
   constexpr u64 kUdTile = u64(kUdNT) * kUdItems;
   __shared__ u32 wsum[kUdNT / kWave];
   __shared__ u32 wsum2[kUdNT / kWave];
@@ -111,6 +112,8 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
   const u64 hi = (part[2 * u64(tile) + 1] + 1) < nf ? (part[2 * u64(tile) + 1] + 1) : nf;
   const K before = base > 0 ? cand[base - 1] : K(0);
   const u64 m = hi - lo;
+  if (m > kUdStreamMax && lockstep_tiles && threadIdx.x == 0)
+    atomicAdd(reinterpret_cast<unsigned long long*>(lockstep_tiles), 1ull);
   // the tile's candidates: every load issued before any is used (a loop
   // that stores each into LDS as it arrives waits out one memory latency
   // per key)
@@ -471,7 +474,8 @@ u64 unique_diff_workspace_bytes(u64 n) {
 template <typename K>
 hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K* out,
                        u64* d_counts, void* ws, hipStream_t s, LaunchTimer* timer,
-                       const LearnedView<K>* model, const K* tail, u64 ntail, int items) {
+                       const LearnedView<K>* model, const K* tail, u64 ntail, int items,
+                       u64* lockstep_tiles) {
   zero_u64x2_kernel<<<1, 1, 0, s>>>(d_counts);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || n == 0) return e;
@@ -506,16 +510,20 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
                                                              part, lv);
   if (model && items == 16)
     ud_select_kernel<K, true, 16><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
-                                                          tile_uniq, lv, part, tail, ntail, alg);
+                                                          tile_uniq, lv, part, tail, ntail, alg,
+                                                          lockstep_tiles);
   else if (model)
     ud_select_kernel<K, true, 8><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
-                                                         tile_uniq, lv, part, tail, ntail, alg);
+                                                         tile_uniq, lv, part, tail, ntail, alg,
+                                                          lockstep_tiles);
   else if (items == 16)
     ud_select_kernel<K, false, 16><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
-                                                           tile_uniq, lv, part, tail, ntail, alg);
+                                                           tile_uniq, lv, part, tail, ntail, alg,
+                                                          lockstep_tiles);
   else
     ud_select_kernel<K, false, 8><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
-                                                          tile_uniq, lv, part, tail, ntail, alg);
+                                                          tile_uniq, lv, part, tail, ntail, alg,
+                                                          lockstep_tiles);
   // the tiles count their own bytes (above); without a device counter only
   // the candidate reads are known here
   if (timer) timer->end(K_UNIQUE_DIFF, s, alg ? 0 : n * sizeof(K), alg);
@@ -571,10 +579,10 @@ hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipSt
 
 template hipError_t unique_diff<u32>(const u32*, u64, const u32*, u64, u32*, u32*, u64*, void*,
                                      hipStream_t, LaunchTimer*, const LearnedView<u32>*,
-                                     const u32*, u64, int);
+                                     const u32*, u64, int, u64*);
 template hipError_t unique_diff<u64>(const u64*, u64, const u64*, u64, u64*, u64*, u64*, void*,
                                      hipStream_t, LaunchTimer*, const LearnedView<u64>*,
-                                     const u64*, u64, int);
+                                     const u64*, u64, int, u64*);
 template hipError_t unique_diff_gather<u32>(const u32*, u64, const void*, u32*, hipStream_t,
                                             int);
 template hipError_t unique_diff_gather<u64>(const u64*, u64, const void*, u64*, hipStream_t,
