@@ -236,7 +236,7 @@ int hl_create(const hl_options* opt, hl_engine** out);
 void hl_destroy(hl_engine* e);
 
 /* Declares relation `name` (identifier, at most 63 bytes) of `arity` columns
- * (1 or 2; others HL_E_UNSUPPORTED), extensional (is_edb != 0: loaded with
+ * (1 to 4; others HL_E_UNSUPPORTED), extensional (is_edb != 0: loaded with
  * hl_load*) or intensional (derived by rules).  Before hl_program.
  * Duplicate names: HL_E_INVALID. */
 int hl_declare(hl_engine* e, const char* name, uint32_t arity, int32_t is_edb);
