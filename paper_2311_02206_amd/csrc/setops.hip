@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kUdNT) void ud_partition_kernel(const K* cand, u64 
 // membership tests the cheaper of reading the slice of full it spans and
 // one 64-byte line per distinct key searched (the same for the tail).
 template <typename K, bool kModel, int kUdItems>
-__global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, const K* full,
+__global__ __launch_bounds__(kUdNT) __attribute__((amdgpu_waves_per_eu(sizeof(K) == 4 && !kModel ? 6 : 1))) void ud_select_kernel(const K* cand, u64 n, const K* full,
                                                           u64 nf, K* tmp, u32* tile_counts,
                                                           u32* tile_uniq, LearnedView<K> lv,
                                                           const u64* part, const K* tail,
@@ -96,7 +96,6 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
                                                           u64* lockstep_tiles) {
   constexpr u64 kUdTile = u64(kUdNT) * kUdItems;
   __shared__ u32 wsum[kUdNT / kWave];
-  __shared__ u32 wsum2[kUdNT / kWave];
   __shared__ K s_c[kUdTile + kUdTile / kUdItems];
   __shared__ K staged[kUdStage];
   const u32 tile = blockIdx.x;
@@ -137,6 +136,12 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
     const u32 k = u32(q) * kUdNT + threadIdx.x;
     if (k < cnt) s_c[pad<kUdItems>(k)] = cv[q];
   }
+  // the slice's first chunk goes to LDS under the same barrier as the
+  // candidates (most slices are one chunk: no barrier of their own)
+  if (m <= kUdStreamMax) {
+#pragma unroll
+    for (int r = 0; r < kPer; ++r) staged[r * kUdNT + threadIdx.x] = next[r];
+  }
   __syncthreads();
   const u32 b = threadIdx.x * kUdItems;
   u32 keep_bits = 0, nkeep = 0, uniq = 0;
@@ -158,14 +163,15 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
     uniq = u32(__popc(first_bits));
     u32 pending = first_bits;  // distinct keys not yet resolved
     // each thread holds its share of the next chunk in registers, loaded
-    // while the current chunk is searched (the first one was requested
-    // above)
+    // while the current chunk is searched (the first one is already in LDS)
     for (u64 c0 = lo; c0 < hi; c0 += kUdStage) {  // block-uniform trip count
       const u32 cm = u32((hi - c0) < kUdStage ? (hi - c0) : kUdStage);
-      __syncthreads();  // the previous chunk is no longer read
+      if (c0 != lo) {
+        __syncthreads();  // the previous chunk is no longer read
 #pragma unroll
-      for (int r = 0; r < kPer; ++r) staged[r * kUdNT + threadIdx.x] = next[r];
-      __syncthreads();
+        for (int r = 0; r < kPer; ++r) staged[r * kUdNT + threadIdx.x] = next[r];
+        __syncthreads();
+      }
       const u64 c1 = c0 + kUdStage;
       if (c1 < hi) {
 #pragma unroll
@@ -311,8 +317,15 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
       }
     }
   }
-  u32 total;
-  u32 pos = block_exclusive_scan<kUdNT>(nkeep, wsum, total);
+  // One block scan serves two counts: kept keys (their exclusive prefix
+  // places the survivors) and distinct keys, each at most one tile (below
+  // 2^16), in the two halves of a word.
+  static_assert(kUdTile < (u64(1) << 16), "tile counts share one word");
+  u32 packed_total;
+  const u32 packed = block_exclusive_scan<kUdNT>(nkeep | (uniq << 16), wsum, packed_total);
+  u32 pos = packed & 0xffffu;
+  const u32 total = packed_total & 0xffffu;
+  uniq = packed_total >> 16;
   // survivors go back into s_c at their compacted positions (all reads of
   // s_c happened before the scan's barriers), then out coalesced
   K mine[kUdItems];
@@ -324,7 +337,6 @@ __global__ __launch_bounds__(kUdNT) void ud_select_kernel(const K* cand, u64 n, 
     if (keep_bits & (1u << q)) s_c[pad<kUdItems>(pos++)] = mine[q];
   __syncthreads();
   for (u32 k = threadIdx.x; k < total; k += kUdNT) tmp[base + k] = s_c[pad<kUdItems>(k)];
-  uniq = block_sum<kUdNT>(uniq, wsum2);
   u32 searched = 0;
   if (alg_bytes) searched = block_sum<kUdNT>(tail_searched, wsum);
   if (threadIdx.x == 0) {
