@@ -32,11 +32,11 @@ constexpr int kNT = 256;
 constexpr int kItems = 8;
 constexpr u64 kTile = u64(kNT) * kItems;
 
-__device__ __forceinline__ bool hisa_find(const Slot* table, u64 cap, u32 key, u32& start,
-                                          u32& len) {
-  u64 slot = slot_of(key, cap);
+// Linear probing from slot `slot`, whose entry `sl` has been read already.
+__device__ __forceinline__ bool hisa_resolve(const Slot* table, u64 cap, u32 key, u64 slot,
+                                             Slot sl, u32& start, u32& len) {
   for (u64 probe = 0; probe < cap; ++probe) {
-    const Slot sl = table[slot];
+    if (probe > 0) sl = table[slot];
     if (sl.w0 == 0) return false;
     if (u32(sl.w0) == key) {
       len = u32(sl.w0 >> 32);
@@ -46,6 +46,12 @@ __device__ __forceinline__ bool hisa_find(const Slot* table, u64 cap, u32 key, u
     slot = (slot + 1 == cap) ? 0 : slot + 1;
   }
   return false;
+}
+
+__device__ __forceinline__ bool hisa_find(const Slot* table, u64 cap, u32 key, u32& start,
+                                          u32& len) {
+  const u64 slot = slot_of(key, cap);
+  return hisa_resolve(table, cap, key, slot, table[slot], start, len);
 }
 
 // Value number src of (c0, c1, inner's other column); 3 is the constant 0
@@ -71,28 +77,38 @@ __global__ __launch_bounds__(kNT) void probe_kernel(const K* outer, u64 n, int o
   const K mask = (K(1) << w) - 1;
   const u64 i0 = u64(blockIdx.x) * (kNT * kProbeItems) + threadIdx.x;
   const int lane = lane_id();
+  // every load of a phase is issued before any of its values is used (work
+  // on a value inside its load's branch would wait for that load first)
+  K kv[kProbeItems];
+#pragma unroll
+  for (int r = 0; r < kProbeItems; ++r) {
+    const u64 i = i0 + u64(r) * kNT;
+    kv[r] = i < n ? outer[i] : K(0);
+  }
   u32 jc[kProbeItems];
 #pragma unroll
-  for (int r = 0; r < kProbeItems; ++r) {
-    const u64 i = i0 + u64(r) * kNT;
-    jc[r] = 0;
-    if (i < n) {
-      const K k = outer[i];
-      jc[r] = outer_col == 0 ? u32(k >> w) : u32(k & mask);
-    }
-  }
-  u32 st[kProbeItems], ln[kProbeItems];
-  u64 lm[kProbeItems];
+  for (int r = 0; r < kProbeItems; ++r) jc[r] = outer_col == 0 ? u32(kv[r] >> w) : u32(kv[r] & mask);
+  // a wave's first lane always probes; any other lane probes when its key
+  // differs from the lane below.  The leaders' home slots are read together,
+  // then collisions are followed one round at a time.
+  u64 lm[kProbeItems], home[kProbeItems];
+  bool lead[kProbeItems];
 #pragma unroll
   for (int r = 0; r < kProbeItems; ++r) {
     const u64 i = i0 + u64(r) * kNT;
-    // a wave's first lane always probes; any other lane probes when its key
-    // differs from the lane below
     const u32 below = __shfl_up(jc[r], 1, kWave);
-    const bool leader = i < n && (lane == 0 || jc[r] != below);
-    lm[r] = ballot(leader);
+    lead[r] = i < n && (lane == 0 || jc[r] != below);
+    lm[r] = ballot(lead[r]);
+    home[r] = slot_of(jc[r], cap);
+  }
+  Slot sl[kProbeItems];
+#pragma unroll
+  for (int r = 0; r < kProbeItems; ++r) sl[r] = (lead[r] && cap > 0) ? table[home[r]] : Slot{0, 0};
+  u32 st[kProbeItems], ln[kProbeItems];
+#pragma unroll
+  for (int r = 0; r < kProbeItems; ++r) {
     st[r] = ln[r] = 0;
-    if (leader && !hisa_find(table, cap, jc[r], st[r], ln[r])) ln[r] = 0;
+    if (lead[r] && !hisa_resolve(table, cap, jc[r], home[r], sl[r], st[r], ln[r])) ln[r] = 0;
   }
 #pragma unroll
   for (int r = 0; r < kProbeItems; ++r) {
@@ -116,16 +132,15 @@ __global__ __launch_bounds__(kNT) void probe_learned_kernel(const K* outer, u64 
   const K mask = (K(1) << w) - 1;
   const u64 i0 = u64(blockIdx.x) * (kNT * kProbeItems) + threadIdx.x;
   const int lane = lane_id();
-  u32 jc[kProbeItems];
+  K kv[kProbeItems];
 #pragma unroll
   for (int r = 0; r < kProbeItems; ++r) {
     const u64 i = i0 + u64(r) * kNT;
-    jc[r] = 0;
-    if (i < n) {
-      const K k = outer[i];
-      jc[r] = outer_col == 0 ? u32(k >> w) : u32(k & mask);
-    }
+    kv[r] = i < n ? outer[i] : K(0);
   }
+  u32 jc[kProbeItems];
+#pragma unroll
+  for (int r = 0; r < kProbeItems; ++r) jc[r] = outer_col == 0 ? u32(kv[r] >> w) : u32(kv[r] & mask);
 #pragma unroll
   for (int r = 0; r < kProbeItems; ++r) {
     const u64 i = i0 + u64(r) * kNT;
@@ -286,13 +301,16 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   // Offsets of the tile's outer tuples relative to its first output b0: the
   // merge path puts every one of them in [b0, b1], so 32 bits hold them.
   // s_pool holds them (la words), the owner of each of the tile's outputs
-  // right after them (lb words; la + lb <= kTile) and the run starts; after
-  // the block scan below (once all are no longer read) it holds the
-  // surviving outputs instead.
-  __shared__ u32 s_pool[2 * kTile];
+  // right after them (lb words; la + lb <= kTile) and, from kTile on, each
+  // run's position base (la + 1 words: entry 0 for the run carried in from
+  // before the tile, entry j for outer tuple a0 + j - 1); after the block
+  // scan below (once all are no longer read) it holds the surviving outputs
+  // instead.  Output k of the tile owned by outer tuple i reads the inner
+  // tuple at base + k (mod 2^32; inner positions are 32-bit).
+  __shared__ u32 s_pool[2 * kTile + 1];
   static_assert(sizeof(K) * kTile <= sizeof(u32) * 2 * kTile, "survivors fit the pool");
   u32* s_off = s_pool;
-  u32* s_start = s_pool + kTile;
+  u32* s_pbase = s_pool + kTile;
   // tiles tile0 .. tile0 + gridDim.x - 1; unfiltered outputs are written
   // relative to the first output of tile0
   const u64 tile = tile0 + blockIdx.x;
@@ -305,25 +323,33 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
   const u32 la = u32(a1 - a0), lb = u32(b1 - b0);
   u32* s_owner = s_pool + la;
   {
-    // the tile's outer tuples (at most kTile), every load issued before any
-    // is stored
-    u64 o_off[kItems];
-    u32 o_start[kItems];
+    // the tile's outer tuples (at most kTile) and the run carried in, every
+    // load issued before any is stored.  Only the low words of the 64-bit
+    // offsets are read: the tile's relative offsets fit 32 bits, and a
+    // 64-bit load whose high half is dead lets the compiler reuse that half
+    // while the load is in flight, which costs a wait per load.
+    const u32* off_lo = reinterpret_cast<const u32*>(off);
+    u32 o_off[kItems], o_start[kItems];
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const u32 k = u32(r) * kNT + threadIdx.x;
       const u64 i = a0 + k;
-      o_off[r] = k < la ? off[i] : b0;
+      o_off[r] = k < la ? off_lo[2 * i] : u32(b0);
       o_start[r] = k < la ? start[i] : 0u;
     }
+    const bool carry = threadIdx.x == 0 && a0 > 0;
+    const u64 c_off = carry ? off[a0 - 1] : b0;
+    const u32 c_start = carry ? start[a0 - 1] : 0u;
 #pragma unroll
     for (int r = 0; r < kItems; ++r) {
       const u32 k = u32(r) * kNT + threadIdx.x;
       if (k < la) {
-        s_off[k] = u32(o_off[r] - b0);
-        s_start[k] = o_start[r];
+        const u32 rel = o_off[r] - u32(b0);
+        s_off[k] = rel;
+        s_pbase[k + 1] = o_start[r] - rel;
       }
     }
+    if (threadIdx.x == 0) s_pbase[0] = c_start + u32(b0 - c_off);
   }
   __syncthreads();
   // serial merge of this thread's slice of the tile's merged sequence
@@ -343,7 +369,7 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
       if (ai < la && (bi >= lb || s_off[ai] <= bi)) {
         ++ai;
       } else {
-        s_owner[bi] = u32(a0 + ai - 1);  // global index of the owning outer tuple
+        s_owner[bi] = ai;  // run ai: outer tuple a0 + ai - 1
         ++bi;
       }
     }
@@ -360,8 +386,33 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
     for (u32 k = threadIdx.x; k < kDedupSlots; k += kNT) dset[k] = ~K(0);
   if (g.dedup()) __syncthreads();
   // each thread's kItems outputs (strided, so reads of each inner run and
-  // the unfiltered writes are coalesced), computed with every load issued
-  // before any is used
+  // the unfiltered writes are coalesced): first every owner and position
+  // from LDS, then every load, then the outputs (the gather's branches on
+  // the join's columns would otherwise keep each output's loads from
+  // overlapping the next one's)
+  u32 own[kItems], ipos[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const u32 k = u32(r) * kNT + threadIdx.x;
+    const u32 j = k < lb ? s_owner[k] : 0u;
+    own[r] = u32(a0) + j - 1;  // wraps only for the unused j = 0 of tile 0
+    ipos[r] = s_pbase[j] + k;
+  }
+  // the outer tuple from global memory (consecutive outputs share it, so it
+  // is a cache hit; keeping it out of LDS leaves room for more workgroups
+  // per CU), read beside the inner tuple
+  K okv[kItems], ikv[kItems];
+#pragma unroll
+  for (int r = 0; r < kItems; ++r) {
+    const u32 k = u32(r) * kNT + threadIdx.x;
+    okv[r] = 0;
+    ikv[r] = 0;
+    if (k < lb) {
+      const u64 i = own[r];
+      okv[r] = outer[i < n_split ? i : i - n_split];
+      ikv[r] = (i < n_split ? inner : inner2)[ipos[r]];
+    }
+  }
   K v[kItems];
   u32 keep = 0;
 #pragma unroll
@@ -369,18 +420,8 @@ __global__ __launch_bounds__(kNT) void expand_kernel(const K* outer, u64 n_outer
     const u32 k = u32(r) * kNT + threadIdx.x;
     v[r] = 0;
     if (k < lb) {
-      const u32 i = s_owner[k];
-      // the owner is in this tile's slice, or the run carried in from before
-      const bool here = u64(i) >= a0;
-      const u64 pos = here ? u64(s_start[u64(i) - a0]) + (k - s_off[u64(i) - a0])
-                           : u64(start[i]) + (b0 + k - off[i]);
-      // the outer tuple from global memory (consecutive outputs share it, so
-      // it is a cache hit; keeping it out of LDS leaves room for more
-      // workgroups per CU), read beside the inner tuple
-      const K ok = outer[u64(i) < n_split ? i : i - n_split];
-      const K* in = u64(i) < n_split ? inner : inner2;
       bool pass;
-      v[r] = g(ok, in[pos], pass);
+      v[r] = g(okv[r], ikv[r], pass);
       if (pass) keep |= 1u << r;
     }
   }
