@@ -1949,8 +1949,8 @@ struct hl_engine {
       const u64 D = h_small[2 * q];
       if (D > 0) {
         reserve_grow(R.delta, D * sizeof(K));
-        HIPCK(hl::unique_diff_gather<K>(kp<K>(obuf), R.n_cand, ws.p, kp<K>(R.delta), stream,
-                                        diff_items));
+        HIPCK(hl::unique_diff_gather<K>(kp<K>(obuf), R.n_cand, R.n_full, ws.p, kp<K>(R.delta),
+                                        stream, diff_items));
       }
     }
     HIPCK(hipMemcpyAsync(h_small, d_small, 2 * idbs.size() * sizeof(u64), hipMemcpyDeviceToHost,

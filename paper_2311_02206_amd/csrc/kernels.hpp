@@ -89,8 +89,11 @@ u64 unique_diff_workspace_bytes(u64 n);
 // dropped too: the result is unique(sorted) \ (full U tail).
 // `items`: candidates per thread of a tile, 16 (4,096-candidate tiles) or 8.
 // With out == nullptr the survivors stay in tmp (compacted per tile) and
-// unique_diff_gather, called with the same n, ws and items before ws is
+// unique_diff_gather, called with the same n, nf, ws and items before ws is
 // reused, writes them to their final place once the caller knows the count.
+// When full has no more keys than there are candidates (nf <= n) the tiles
+// follow the merge path of the two arrays instead (items and the model do
+// not apply).
 // lockstep_tiles (device, optional): incremented once per tile whose slice
 // of full is too long to stream (its keys are searched in global memory).
 template <typename K>
@@ -99,8 +102,8 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
                        const LearnedView<K>* model = nullptr, const K* tail = nullptr,
                        u64 ntail = 0, int items = 16, u64* lockstep_tiles = nullptr);
 template <typename K>
-hipError_t unique_diff_gather(const K* tmp, u64 n, const void* ws, K* out, hipStream_t s,
-                              int items = 16);
+hipError_t unique_diff_gather(const K* tmp, u64 n, u64 nf, const void* ws, K* out,
+                              hipStream_t s, int items = 16);
 
 // --------------------------------------------------------------- merge
 u64 merge_workspace_bytes(u64 na, u64 nb);

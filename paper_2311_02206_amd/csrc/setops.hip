@@ -355,10 +355,12 @@ __global__ __launch_bounds__(kUdNT) __attribute__((amdgpu_waves_per_eu(sizeof(K)
 template <typename K>
 __global__ __launch_bounds__(kUdNT) void ud_gather_kernel(const K* tmp, const u32* tile_counts,
                                                           const u64* tile_off, u64 tile_keys,
-                                                          K* out) {
+                                                          const u64* tile_src, K* out) {
   const u32 tile = blockIdx.x;
   const u32 c = tile_counts[tile];
-  const u64 src = u64(tile) * tile_keys;
+  // a tile's survivors start at its first candidate's index (tile_src), or
+  // at the tile's own start when tiles hold a fixed number of candidates
+  const u64 src = tile_src ? tile_src[tile] : u64(tile) * tile_keys;
   const u64 dst = tile_off[tile];
   // at most 16 keys per thread (the largest tile), loaded before any store
   K v[16];
@@ -401,10 +403,10 @@ __device__ __forceinline__ u64 merge_path(const K* a, u64 na, const K* b, u64 nb
 
 template <typename K>
 __global__ void merge_partition_kernel(const K* a, u64 na, const K* b, u64 nb, u64* parts,
-                                       u64 nparts) {
+                                       u64 nparts, u64 tile_len) {
   u64 t = u64(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= nparts) return;
-  u64 diag = t * kMgTile;
+  u64 diag = t * tile_len;
   if (diag > na + nb) diag = na + nb;
   parts[t] = merge_path(a, na, b, nb, diag);
 }
@@ -472,8 +474,179 @@ __global__ __launch_bounds__(kMgNT) void merge_kernel(const K* a, u64 na, const 
   }
 }
 
+// Set difference by merge path, used when the candidates are at least as
+// many as the keys of full (so nearly every key of full lies between two
+// candidates and is read anyway).  The merged order of the candidates and
+// full (ties: the candidate first) is cut into tiles of kUmTile positions;
+// a tile loads both of its slices in one round and each thread walks
+// kUmItems consecutive merged positions.  A candidate is in full exactly
+// when the first key of full not yet passed equals it (the merge never
+// passes a key of full that is not below the candidate).  Survivors are
+// written compacted (in order) from the tile's first candidate in tmp;
+// kept and distinct counts go to tile_counts and tile_uniq as in the
+// select above, and a tail run is searched in the same way.
+constexpr int kUmItems = 16;
+constexpr u64 kUmTile = u64(kUdNT) * kUmItems;
+
+template <typename K>
+__global__ __launch_bounds__(kUdNT) void ud_merge_kernel(const K* cand, u64 n, const K* full,
+                                                         u64 nf, const u64* parts, K* tmp,
+                                                         u32* tile_counts, u32* tile_uniq,
+                                                         const K* tail, u64 ntail,
+                                                         u64* alg_bytes) {
+  __shared__ u32 wsum[kUdNT / kWave];
+  __shared__ K s[kUmTile + kUmTile / kUmItems];
+  const u32 tile = blockIdx.x;
+  const u64 d0 = u64(tile) * kUmTile;
+  const u64 d1 = (d0 + kUmTile) < (n + nf) ? (d0 + kUmTile) : (n + nf);
+  const u64 a0 = parts[tile], a1 = parts[tile + 1];
+  const u64 b0 = d0 - a0, b1 = d1 - a1;
+  const u32 la = u32(a1 - a0), lb = u32(b1 - b0);
+  const u32 total = la + lb;
+  // the candidate before the tile (for the first-of-run test) and the key
+  // of full after it (the next unpassed key once the tile's slice is spent)
+  const bool has_before = a0 > 0, has_after = b1 < nf;
+  const K before = has_before ? cand[a0 - 1] : K(0);
+  const K after = has_after ? full[b1] : K(0);
+  {
+    K v[kUmItems];
+#pragma unroll
+    for (int q = 0; q < kUmItems; ++q) {
+      const u32 k = u32(q) * kUdNT + threadIdx.x;
+      v[q] = k < la ? cand[a0 + k] : (k < total ? full[b0 + (k - la)] : K(0));
+    }
+#pragma unroll
+    for (int q = 0; q < kUmItems; ++q) {
+      const u32 k = u32(q) * kUdNT + threadIdx.x;
+      if (k < total) s[k] = v[q];
+    }
+  }
+  __syncthreads();
+  u32 diag = threadIdx.x * kUmItems;
+  if (diag > total) diag = total;
+  u32 ai = u32(merge_path(s, la, s + la, lb, diag));
+  u32 bi = diag - ai;
+  bool has_prev = ai > 0 || has_before;
+  K prev = ai > 0 ? s[ai - 1] : before;
+  K val[kUmItems];
+  u32 keep_bits = 0, nkeep = 0, uniq = 0;
+#pragma unroll
+  for (int k = 0; k < kUmItems; ++k) {
+    val[k] = 0;
+    if (diag + k < total) {  // then ai < la or bi < lb
+      const bool take_a = (bi >= lb) || (ai < la && !(s[la + bi] < s[ai]));
+      if (take_a) {
+        const K c = s[ai];
+        if (!has_prev || c != prev) {
+          ++uniq;
+          const bool in_full = bi < lb ? s[la + bi] == c : (has_after && after == c);
+          if (!in_full) {
+            keep_bits |= 1u << k;
+            ++nkeep;
+            val[k] = c;
+          }
+        }
+        prev = c;
+        has_prev = true;
+        ++ai;
+      } else {
+        ++bi;
+      }
+    }
+  }
+  // the tail: every survivor searched there, kUdLock at a time in lockstep
+  const u32 tail_searched = ntail > 0 ? nkeep : 0u;
+  if (ntail > 0) {
+#pragma unroll
+    for (int g = 0; g < kUmItems; g += kUdLock) {
+      if (!((keep_bits >> g) & ((1u << kUdLock) - 1))) continue;
+      const K* at[kUdLock];
+#pragma unroll
+      for (int j = 0; j < kUdLock; ++j) at[j] = tail;
+      u64 len = ntail;
+      while (len > 1) {
+        const u64 half = len >> 1;
+#pragma unroll
+        for (int j = 0; j < kUdLock; ++j)
+          if ((keep_bits >> (g + j)) & 1u) at[j] = (at[j][half] < val[g + j]) ? at[j] + half : at[j];
+        len -= half;
+      }
+#pragma unroll
+      for (int j = 0; j < kUdLock; ++j) {
+        if ((keep_bits >> (g + j)) & 1u) {
+          const u64 p = u64(at[j] - tail) + ((*at[j] < val[g + j]) ? 1 : 0);
+          if (p < ntail && tail[p] == val[g + j]) {
+            keep_bits &= ~(1u << (g + j));
+            --nkeep;
+          }
+        }
+      }
+    }
+  }
+  static_assert(kUmTile < (u64(1) << 16), "tile counts share one word");
+  u32 packed_total;
+  const u32 packed = block_exclusive_scan<kUdNT>(nkeep | (uniq << 16), wsum, packed_total);
+  u32 pos = packed & 0xffffu;
+  const u32 kept = packed_total & 0xffffu;
+  uniq = packed_total >> 16;
+  // every read of s happened before the scan's barriers
+#pragma unroll
+  for (int k = 0; k < kUmItems; ++k)
+    if (keep_bits & (1u << k)) s[pad<kUmItems>(pos++)] = val[k];
+  __syncthreads();
+  for (u32 k = threadIdx.x; k < kept; k += kUdNT) tmp[a0 + k] = s[pad<kUmItems>(k)];
+  u32 searched = 0;
+  if (alg_bytes) searched = block_sum<kUdNT>(tail_searched, wsum);
+  if (threadIdx.x == 0) {
+    tile_counts[tile] = kept;
+    tile_uniq[tile] = uniq;
+    if (alg_bytes) {
+      const u64 full_b = u64(lb) * sizeof(K) < u64(uniq) * 64 ? u64(lb) * sizeof(K) : u64(uniq) * 64;
+      const u64 tail_b =
+          ntail * sizeof(K) < u64(searched) * 64 ? ntail * sizeof(K) : u64(searched) * 64;
+      atomicAdd(reinterpret_cast<unsigned long long*>(alg_bytes),
+                static_cast<unsigned long long>(u64(la + kept) * sizeof(K) + full_b + tail_b));
+    }
+  }
+}
+
 u64 ud_tiles(u64 n, u64 tile) { return (n + tile - 1) / tile; }
 u64 mg_tiles(u64 n) { return (n + kMgTile - 1) / kMgTile; }
+
+// The workspace of one set difference: per-tile kept and distinct counts,
+// the kept counts' offsets, and the partition (two bounds per tile for the
+// select, one diagonal split per tile boundary for the merge path; the
+// distinct counts' prefix sum goes after the first nt + 1 entries once the
+// tiles have run).  The merge path is taken when full has no more keys
+// than there are candidates: its tiles are then at most as many as the
+// select's smallest tiles, which the workspace is sized for.
+struct UdLayout {
+  bool by_merge;
+  u64 tile_keys, nt;
+  u32* tile_counts;
+  u32* tile_uniq;
+  u64* tile_off;
+  u64* part;
+  char* rest;
+};
+
+UdLayout ud_layout(u64 n, u64 nf, int items, void* ws) {
+  UdLayout L;
+  L.by_merge = nf > 0 && nf <= n;
+  L.tile_keys = L.by_merge ? kUmTile : u64(kUdNT) * u64(items);
+  L.nt = L.by_merge ? ud_tiles(n + nf, kUmTile) : ud_tiles(n, L.tile_keys);
+  char* p = static_cast<char*>(ws);
+  L.tile_counts = reinterpret_cast<u32*>(p);
+  p += align_up(L.nt * sizeof(u32), 256);
+  L.tile_uniq = reinterpret_cast<u32*>(p);
+  p += align_up(L.nt * sizeof(u32), 256);
+  L.tile_off = reinterpret_cast<u64*>(p);
+  p += align_up((L.nt + 1) * sizeof(u64), 256);
+  L.part = reinterpret_cast<u64*>(p);
+  p += align_up((2 * L.nt + 1) * sizeof(u64), 256);
+  L.rest = p;
+  return L;
+}
 
 }  // namespace
 
@@ -493,17 +666,13 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   if (e != hipSuccess || n == 0) return e;
   if (n >= (u64(1) << 32)) return hipErrorInvalidValue;
   if (items != 8 && items != 16) return hipErrorInvalidValue;
-  const u64 tile_keys = u64(kUdNT) * u64(items);
-  const u64 nt = ud_tiles(n, tile_keys);
-  char* p = static_cast<char*>(ws);
-  u32* tile_counts = reinterpret_cast<u32*>(p);
-  p += align_up(nt * sizeof(u32), 256);
-  u32* tile_uniq = reinterpret_cast<u32*>(p);
-  p += align_up(nt * sizeof(u32), 256);
-  u64* tile_off = reinterpret_cast<u64*>(p);
-  p += align_up((nt + 1) * sizeof(u64), 256);
-  u64* part = reinterpret_cast<u64*>(p);  // 2 nt bounds, later nt + 1 offsets
-  p += align_up((2 * nt + 1) * sizeof(u64), 256);
+  const UdLayout L = ud_layout(n, nf, items, ws);
+  const u64 tile_keys = L.tile_keys, nt = L.nt;
+  u32* tile_counts = L.tile_counts;
+  u32* tile_uniq = L.tile_uniq;
+  u64* tile_off = L.tile_off;
+  u64* part = L.part;
+  char* p = L.rest;
   if (model && (model->keys != full || model->n != nf)) return hipErrorInvalidValue;
   // Candidates at least one per 8 keys of full leave tiles' slices short
   // enough to stream, where the model is not used; the kernel without it
@@ -514,28 +683,35 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   const LearnedView<K> lv = model ? *model : LearnedView<K>{};
   const dim3 grid = dim3(u32(nt));
   if (timer) timer->begin(K_UNIQUE_DIFF, s);
-  if (model)
-    ud_partition_kernel<K, true><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, tile_keys,
-                                                            part, lv);
-  else
-    ud_partition_kernel<K, false><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt, tile_keys,
-                                                             part, lv);
-  if (model && items == 16)
-    ud_select_kernel<K, true, 16><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
-                                                          tile_uniq, lv, part, tail, ntail, alg,
-                                                          lockstep_tiles);
-  else if (model)
-    ud_select_kernel<K, true, 8><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
-                                                         tile_uniq, lv, part, tail, ntail, alg,
-                                                          lockstep_tiles);
-  else if (items == 16)
-    ud_select_kernel<K, false, 16><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
+  if (L.by_merge) {
+    merge_partition_kernel<K><<<dim3(u32((nt + 1 + 255) / 256)), 256, 0, s>>>(
+        sorted, n, full, nf, part, nt + 1, kUmTile);
+    ud_merge_kernel<K><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, part, tmp, tile_counts,
+                                              tile_uniq, tail, ntail, alg);
+  } else {
+    if (model)
+      ud_partition_kernel<K, true><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt,
+                                                              tile_keys, part, lv);
+    else
+      ud_partition_kernel<K, false><<<dim3(pb), kUdNT, 0, s>>>(sorted, n, full, nf, nt,
+                                                               tile_keys, part, lv);
+    if (model && items == 16)
+      ud_select_kernel<K, true, 16><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
+                                                            tile_counts, tile_uniq, lv, part, tail,
+                                                            ntail, alg, lockstep_tiles);
+    else if (model)
+      ud_select_kernel<K, true, 8><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
                                                            tile_uniq, lv, part, tail, ntail, alg,
-                                                          lockstep_tiles);
-  else
-    ud_select_kernel<K, false, 8><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp, tile_counts,
-                                                          tile_uniq, lv, part, tail, ntail, alg,
-                                                          lockstep_tiles);
+                                                           lockstep_tiles);
+    else if (items == 16)
+      ud_select_kernel<K, false, 16><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
+                                                             tile_counts, tile_uniq, lv, part,
+                                                             tail, ntail, alg, lockstep_tiles);
+    else
+      ud_select_kernel<K, false, 8><<<grid, kUdNT, 0, s>>>(sorted, n, full, nf, tmp,
+                                                            tile_counts, tile_uniq, lv, part, tail,
+                                                            ntail, alg, lockstep_tiles);
+  }
   // the tiles count their own bytes (above); without a device counter only
   // the candidate reads are known here
   if (timer) timer->end(K_UNIQUE_DIFF, s, alg ? 0 : n * sizeof(K), alg);
@@ -543,26 +719,24 @@ hipError_t unique_diff(const K* sorted, u64 n, const K* full, u64 nf, K* tmp, K*
   if (e != hipSuccess) return e;
   e = scan_u32_u64(tile_counts, nt, tile_off, d_counts, p, s);
   if (e != hipSuccess) return e;
-  // the distinct count: a prefix sum whose total is all that is kept (into
-  // part, which the select no longer needs)
-  e = scan_u32_u64(tile_uniq, nt, part, d_counts + 1, p, s);
+  // the distinct count: a prefix sum whose total is all that is kept (after
+  // the merge path's splits, which the gather still reads)
+  e = scan_u32_u64(tile_uniq, nt, part + nt + 1, d_counts + 1, p, s);
   if (e != hipSuccess || !out) return e;
-  ud_gather_kernel<K><<<grid, kUdNT, 0, s>>>(tmp, tile_counts, tile_off, tile_keys, out);
+  ud_gather_kernel<K><<<grid, kUdNT, 0, s>>>(tmp, tile_counts, tile_off, tile_keys,
+                                             L.by_merge ? part : nullptr, out);
   return hipGetLastError();
 }
 
 template <typename K>
-hipError_t unique_diff_gather(const K* tmp, u64 n, const void* ws, K* out, hipStream_t s,
+hipError_t unique_diff_gather(const K* tmp, u64 n, u64 nf, const void* ws, K* out, hipStream_t s,
                               int items) {
   if (n == 0) return hipSuccess;
   if (n >= (u64(1) << 32) || (items != 8 && items != 16)) return hipErrorInvalidValue;
-  const u64 tile_keys = u64(kUdNT) * u64(items);
-  const u64 nt = ud_tiles(n, tile_keys);
-  const char* p = static_cast<const char*>(ws);
-  const u32* tile_counts = reinterpret_cast<const u32*>(p);
-  p += 2 * align_up(nt * sizeof(u32), 256);
-  const u64* tile_off = reinterpret_cast<const u64*>(p);
-  ud_gather_kernel<K><<<dim3(u32(nt)), kUdNT, 0, s>>>(tmp, tile_counts, tile_off, tile_keys, out);
+  const UdLayout L = ud_layout(n, nf, items, const_cast<void*>(ws));
+  ud_gather_kernel<K><<<dim3(u32(L.nt)), kUdNT, 0, s>>>(tmp, L.tile_counts, L.tile_off,
+                                                        L.tile_keys, L.by_merge ? L.part : nullptr,
+                                                        out);
   return hipGetLastError();
 }
 
@@ -580,7 +754,7 @@ hipError_t merge(const K* a, u64 na, const K* b, u64 nb, K* out, void* ws, hipSt
   u64* parts = static_cast<u64*>(ws);
   const u64 nparts = nt + 1;
   merge_partition_kernel<K><<<dim3(u32((nparts + 255) / 256)), 256, 0, s>>>(a, na, b, nb, parts,
-                                                                           nparts);
+                                                                           nparts, kMgTile);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (timer) timer->begin(K_MERGE, s);
@@ -595,10 +769,10 @@ template hipError_t unique_diff<u32>(const u32*, u64, const u32*, u64, u32*, u32
 template hipError_t unique_diff<u64>(const u64*, u64, const u64*, u64, u64*, u64*, u64*, void*,
                                      hipStream_t, LaunchTimer*, const LearnedView<u64>*,
                                      const u64*, u64, int, u64*);
-template hipError_t unique_diff_gather<u32>(const u32*, u64, const void*, u32*, hipStream_t,
-                                            int);
-template hipError_t unique_diff_gather<u64>(const u64*, u64, const void*, u64*, hipStream_t,
-                                            int);
+template hipError_t unique_diff_gather<u32>(const u32*, u64, u64, const void*, u32*,
+                                            hipStream_t, int);
+template hipError_t unique_diff_gather<u64>(const u64*, u64, u64, const void*, u64*,
+                                            hipStream_t, int);
 template hipError_t merge<u32>(const u32*, u64, const u32*, u64, u32*, void*, hipStream_t,
                                LaunchTimer*);
 template hipError_t merge<u64>(const u64*, u64, const u64*, u64, u64*, void*, hipStream_t,

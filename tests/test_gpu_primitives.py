@@ -86,7 +86,12 @@ def test_sort_special(eng, kb):
                                         (20_000, 30_000, 60_000), (100_000, 5_000, 1 << 30),
                                         (50_000, 2_000_000, 4_000_000), (300_000, 1000, 2000),
                                         (100_000, 1_500_000, 3_000_000),
-                                        (9_000, 600_000, 10_000_000)])
+                                        (9_000, 600_000, 10_000_000),
+                                        # full no larger than the candidates (merge-path
+                                        # tiles): overlapping, few long runs, nearly all
+                                        # candidates present, full around the candidates
+                                        (1_000_000, 900_000, 1_500_000), (2_000_000, 100, 50),
+                                        (500_000, 400_000, 400_000), (70_001, 70_000, 1 << 40)])
 def test_unique_diff(eng, kb, n, nf, span):
     import torch
     say(f"unique_diff kb={kb} n={n} nf={nf} span={span}")
