@@ -474,9 +474,9 @@ __global__ __launch_bounds__(kMgNT) void merge_kernel(const K* a, u64 na, const 
   }
 }
 
-// Set difference by merge path, used when the candidates are at least as
-// many as the keys of full (so nearly every key of full lies between two
-// candidates and is read anyway).  The merged order of the candidates and
+// Set difference by merge path, used when full has at most kUmFullPerCand
+// keys per candidate (so most keys of full lie between two candidates and
+// are read anyway).  The merged order of the candidates and
 // full (ties: the candidate first) is cut into tiles of kUmTile positions;
 // a tile loads both of its slices in one round and each thread walks
 // kUmItems consecutive merged positions.  A candidate is in full exactly
@@ -487,9 +487,10 @@ __global__ __launch_bounds__(kMgNT) void merge_kernel(const K* a, u64 na, const 
 // select above, and a tail run is searched in the same way.
 constexpr int kUmItems = 16;
 constexpr u64 kUmTile = u64(kUdNT) * kUmItems;
+constexpr u64 kUmFullPerCand = 1;  // the merge path is taken for nf <= n
 
 template <typename K>
-__global__ __launch_bounds__(kUdNT) void ud_merge_kernel(const K* cand, u64 n, const K* full,
+__global__ __launch_bounds__(kUdNT) __attribute__((amdgpu_waves_per_eu(sizeof(K) == 4 ? 8 : 1))) void ud_merge_kernel(const K* cand, u64 n, const K* full,
                                                          u64 nf, const u64* parts, K* tmp,
                                                          u32* tile_counts, u32* tile_uniq,
                                                          const K* tail, u64 ntail,
@@ -530,29 +531,28 @@ __global__ __launch_bounds__(kUdNT) void ud_merge_kernel(const K* cand, u64 n, c
   K prev = ai > 0 ? s[ai - 1] : before;
   K val[kUmItems];
   u32 keep_bits = 0, nkeep = 0, uniq = 0;
+  // Branch-free steps: both heads are read (at a valid index when a side
+  // is spent) and selects decide; a branch per step would diverge within
+  // a wave and run both sides.
 #pragma unroll
   for (int k = 0; k < kUmItems; ++k) {
-    val[k] = 0;
-    if (diag + k < total) {  // then ai < la or bi < lb
-      const bool take_a = (bi >= lb) || (ai < la && !(s[la + bi] < s[ai]));
-      if (take_a) {
-        const K c = s[ai];
-        if (!has_prev || c != prev) {
-          ++uniq;
-          const bool in_full = bi < lb ? s[la + bi] == c : (has_after && after == c);
-          if (!in_full) {
-            keep_bits |= 1u << k;
-            ++nkeep;
-            val[k] = c;
-          }
-        }
-        prev = c;
-        has_prev = true;
-        ++ai;
-      } else {
-        ++bi;
-      }
-    }
+    const bool live = diag + k < total;  // then ai < la or bi < lb
+    const bool a_left = ai < la, b_left = bi < lb;
+    const K x = s[a_left ? ai : 0u];
+    const K y = s[b_left ? la + bi : 0u];
+    const bool take_a = live && (!b_left || (a_left && !(y < x)));
+    const bool first = take_a && (!has_prev || x != prev);
+    // the first key of full not yet passed: y, or the one after the tile
+    const bool in_full = b_left ? (y == x) : (has_after && after == x);
+    const bool keep = first && !in_full;
+    val[k] = x;
+    uniq += first ? 1u : 0u;
+    nkeep += keep ? 1u : 0u;
+    keep_bits |= keep ? (1u << k) : 0u;
+    prev = take_a ? x : prev;
+    has_prev = has_prev || take_a;
+    ai += take_a ? 1u : 0u;
+    bi += (live && !take_a) ? 1u : 0u;
   }
   // the tail: every survivor searched there, kUdLock at a time in lockstep
   const u32 tail_searched = ntail > 0 ? nkeep : 0u;
@@ -618,8 +618,9 @@ u64 mg_tiles(u64 n) { return (n + kMgTile - 1) / kMgTile; }
 // select, one diagonal split per tile boundary for the merge path; the
 // distinct counts' prefix sum goes after the first nt + 1 entries once the
 // tiles have run).  The merge path is taken when full has no more keys
-// than there are candidates: its tiles are then at most as many as the
-// select's smallest tiles, which the workspace is sized for.
+// than kUmFullPerCand times the candidates (beyond that most of full lies
+// outside the candidates' tiles, which the select does not read); the
+// workspace is sized for the larger tile count of the two paths.
 struct UdLayout {
   bool by_merge;
   u64 tile_keys, nt;
@@ -632,7 +633,7 @@ struct UdLayout {
 
 UdLayout ud_layout(u64 n, u64 nf, int items, void* ws) {
   UdLayout L;
-  L.by_merge = nf > 0 && nf <= n;
+  L.by_merge = nf > 0 && nf <= kUmFullPerCand * n;
   L.tile_keys = L.by_merge ? kUmTile : u64(kUdNT) * u64(items);
   L.nt = L.by_merge ? ud_tiles(n + nf, kUmTile) : ud_tiles(n, L.tile_keys);
   char* p = static_cast<char*>(ws);
@@ -651,7 +652,10 @@ UdLayout ud_layout(u64 n, u64 nf, int items, void* ws) {
 }  // namespace
 
 u64 unique_diff_workspace_bytes(u64 n) {
-  u64 nt = ud_tiles(n, kUdMinTile);  // the smallest tile: the most tiles
+  // the select's smallest tile, or the merge path over at most
+  // (1 + kUmFullPerCand) n keys: whichever makes more tiles
+  const u64 sel = ud_tiles(n, kUdMinTile), mrg = ud_tiles((1 + kUmFullPerCand) * n, kUmTile);
+  const u64 nt = sel > mrg ? sel : mrg;
   return 2 * align_up(nt * sizeof(u32), 256) + align_up((nt + 1) * sizeof(u64), 256) +
          align_up((2 * nt + 1) * sizeof(u64), 256) + scan_workspace_bytes(nt);
 }
