@@ -421,7 +421,10 @@ int hl_sort_keys_noalloc(hl_engine* e, void* d_keys, uint64_t n, uint32_t key_by
 /* d_out = unique(d_sorted) minus d_full (Section 5.1, "Populating delta";
  * Section 4.2, "Deduplication").  d_sorted: n ascending keys (repeats
  * allowed); d_full: n_full ascending distinct keys; d_out: room for n keys.
- * *n_out = |d_out|, *n_unique = distinct keys of d_sorted.  n < 2^32. */
+ * *n_out = |d_out|, *n_unique = distinct keys of d_sorted.  n < 2^32.
+ * When n_full <= n the two arrays are walked together in merge-path tiles;
+ * otherwise each tile of candidates searches the slice of d_full it spans
+ * (the result is the same). */
 int hl_unique_diff(hl_engine* e, const void* d_sorted, uint64_t n, const void* d_full,
                    uint64_t n_full, void* d_out, uint64_t* n_out, uint64_t* n_unique,
                    uint32_t key_bytes);
