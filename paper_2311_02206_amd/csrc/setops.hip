@@ -88,12 +88,12 @@ __global__ __launch_bounds__(kUdNT) void ud_partition_kernel(const K* cand, u64 
 // membership tests the cheaper of reading the slice of full it spans and
 // one 64-byte line per distinct key searched (the same for the tail).
 template <typename K, bool kModel, int kUdItems>
-__global__ __launch_bounds__(kUdNT) __attribute__((amdgpu_waves_per_eu(sizeof(K) == 4 && !kModel ? 6 : 1))) void ud_select_kernel(const K* cand, u64 n, const K* full,
-                                                          u64 nf, K* tmp, u32* tile_counts,
-                                                          u32* tile_uniq, LearnedView<K> lv,
-                                                          const u64* part, const K* tail,
-                                                          u64 ntail, u64* alg_bytes,
-                                                          u64* lockstep_tiles) {
+__global__ __launch_bounds__(kUdNT)
+__attribute__((amdgpu_waves_per_eu(sizeof(K) == 4 && !kModel ? 6 : 1)))
+void ud_select_kernel(const K* cand, u64 n, const K* full, u64 nf, K* tmp, u32* tile_counts,
+                      u32* tile_uniq, LearnedView<K> lv, const u64* part, const K* tail,
+                      u64 ntail, u64* alg_bytes,
+                      u64* lockstep_tiles) {
   constexpr u64 kUdTile = u64(kUdNT) * kUdItems;
   __shared__ u32 wsum[kUdNT / kWave];
   __shared__ K s_c[kUdTile + kUdTile / kUdItems];
@@ -475,8 +475,8 @@ __global__ __launch_bounds__(kMgNT) void merge_kernel(const K* a, u64 na, const 
 }
 
 // Set difference by merge path, used when full has at most kUmFullPerCand
-// keys per candidate (so most keys of full lie between two candidates and
-// are read anyway).  The merged order of the candidates and
+// keys per candidate (then nearly every key of full lies between two
+// candidates and would be read by the select too).  The merged order of the candidates and
 // full (ties: the candidate first) is cut into tiles of kUmTile positions;
 // a tile loads both of its slices in one round and each thread walks
 // kUmItems consecutive merged positions.  A candidate is in full exactly
@@ -490,11 +490,10 @@ constexpr u64 kUmTile = u64(kUdNT) * kUmItems;
 constexpr u64 kUmFullPerCand = 1;  // the merge path is taken for nf <= n
 
 template <typename K>
-__global__ __launch_bounds__(kUdNT) __attribute__((amdgpu_waves_per_eu(sizeof(K) == 4 ? 8 : 1))) void ud_merge_kernel(const K* cand, u64 n, const K* full,
-                                                         u64 nf, const u64* parts, K* tmp,
-                                                         u32* tile_counts, u32* tile_uniq,
-                                                         const K* tail, u64 ntail,
-                                                         u64* alg_bytes) {
+__global__ __launch_bounds__(kUdNT) __attribute__((amdgpu_waves_per_eu(sizeof(K) == 4 ? 8 : 1)))
+void ud_merge_kernel(const K* cand, u64 n, const K* full, u64 nf, const u64* parts, K* tmp,
+                     u32* tile_counts, u32* tile_uniq, const K* tail, u64 ntail,
+                     u64* alg_bytes) {
   __shared__ u32 wsum[kUdNT / kWave];
   __shared__ K s[kUmTile + kUmTile / kUmItems];
   const u32 tile = blockIdx.x;
@@ -618,9 +617,10 @@ u64 mg_tiles(u64 n) { return (n + kMgTile - 1) / kMgTile; }
 // select, one diagonal split per tile boundary for the merge path; the
 // distinct counts' prefix sum goes after the first nt + 1 entries once the
 // tiles have run).  The merge path is taken when full has no more keys
-// than kUmFullPerCand times the candidates (beyond that most of full lies
-// outside the candidates' tiles, which the select does not read); the
-// workspace is sized for the larger tile count of the two paths.
+// than kUmFullPerCand times the candidates (with 2 or 4 keys of full per
+// candidate the merge path measured slower than the select on the
+// same-generation fixpoint); the workspace is sized for the larger tile
+// count of the two paths.
 struct UdLayout {
   bool by_merge;
   u64 tile_keys, nt;
