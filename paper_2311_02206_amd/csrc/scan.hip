@@ -13,20 +13,6 @@ constexpr int kItems = 8;
 constexpr u64 kTile = kNT * kItems;
 constexpr u64 kSingleTiles = 4;  // inputs up to this many tiles scan in one block
 
-template <typename Tin>
-__global__ __launch_bounds__(kNT) void scan_reduce_kernel(const Tin* in, u64 n, u64* sums) {
-  __shared__ u64 lds[kNT / kWave];
-  const u64 base = u64(blockIdx.x) * kTile;
-  u64 s = 0;
-#pragma unroll
-  for (int j = 0; j < kItems; ++j) {
-    u64 i = base + u64(j) * kNT + threadIdx.x;
-    if (i < n) s += u64(in[i]);
-  }
-  s = block_sum<kNT>(s, lds);
-  if (threadIdx.x == 0) sums[blockIdx.x] = s;
-}
-
 // Eight consecutive values of in from i (zero past n): two or four 16-byte
 // loads when the eight lie inside the array and the address is aligned.
 template <typename Tin>
@@ -50,6 +36,21 @@ __device__ __forceinline__ void load_items(const Tin* in, u64 i, u64 n, u64 (&v)
   }
 #pragma unroll
   for (int j = 0; j < kItems; ++j) v[j] = (i + j < n) ? u64(p[j]) : 0;
+}
+
+// Sum of each tile: every thread reads its eight consecutive values with
+// load_items (all loads issued before any is added; a conditional add per
+// load waited for each load in turn).
+template <typename Tin>
+__global__ __launch_bounds__(kNT) void scan_reduce_kernel(const Tin* in, u64 n, u64* sums) {
+  __shared__ u64 lds[kNT / kWave];
+  u64 v[kItems];
+  load_items(in, u64(blockIdx.x) * kTile + u64(threadIdx.x) * kItems, n, v);
+  u64 s = 0;
+#pragma unroll
+  for (int j = 0; j < kItems; ++j) s += v[j];
+  s = block_sum<kNT>(s, lds);
+  if (threadIdx.x == 0) sums[blockIdx.x] = s;
 }
 
 // offsets == nullptr: one block scans `tiles` tiles in turn, from 0.
